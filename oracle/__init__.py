@@ -1,0 +1,265 @@
+"""FP64 CPU oracle of the hybrid WENO5-AO gas-kinetic scheme -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package. It loads ``oracle/liboracle.so`` (built from ``hgks_oracle.c`` by
+``oracle/build.py``) and shares no code with the HIP library in ``paper_2304_05572_amd``.
+
+Every function follows a passage of Mu et al., arXiv 2304.05572; see ``hgks_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_NOSLIP = 0, 1, 2, 3
+RECON_HYBRID, RECON_WENOAO, RECON_LINEAR = 0, 1, 2
+EULER, NS = 0, 1
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+        ("eqn", C.c_int32), ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
+        ("cfl", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("fixed_dt", C.c_double),
+        ("bc", C.c_int32 * 4), ("recon", C.c_int32),
+        ("gamma_hi", C.c_double), ("gamma_lo", C.c_double), ("weno_eps", C.c_double),
+        ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32),
+    ]
+
+
+@dataclasses.dataclass
+class Problem:
+    """Problem statement (paper Sec. 2 and Sec. 3); defaults are the paper's usual parameters."""
+    dim: int = 2
+    nx: int = 64
+    ny: int = 64
+    x0: float = 0.0
+    x1: float = 1.0
+    y0: float = 0.0
+    y1: float = 1.0
+    eqn: int = EULER
+    gamma: float = 1.4
+    mu: float = 0.0
+    Pr: float = 1.0
+    cfl: float = 0.5
+    c1: float = 0.01
+    c2: float = 1.0
+    fixed_dt: float = 0.0
+    bc: tuple = (BC_OUTFLOW,) * 4
+    recon: int = RECON_HYBRID
+    gamma_hi: float = 0.85
+    gamma_lo: float = 0.85
+    weno_eps: float = 1e-8
+    zeta1_mode: int = 0
+    tangential_flag_mode: int = 0
+
+    @property
+    def nc(self) -> int:
+        return self.dim + 2
+
+    @property
+    def shape(self):
+        return (self.nc, self.nx) if self.dim == 1 else (self.nc, self.ny, self.nx)
+
+    def c_struct(self) -> _Problem:
+        s = _Problem()
+        for f in dataclasses.fields(self):
+            v = getattr(self, f.name)
+            if f.name == "bc":
+                arr = (C.c_int32 * 4)(*[int(b) for b in (list(v) + [0] * 4)[:4]])
+                s.bc = arr
+            else:
+                setattr(s, f.name, v)
+        return s
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(LIB_PATH)
+        d, i32, vp = C.c_double, C.c_int32, C.c_void_p
+        P = C.POINTER(_Problem)
+        dp = C.POINTER(C.c_double)
+        sig = {
+            "oracle_flags": (i32, [P, vp, vp, vp]),
+            "oracle_cfl_dt": (d, [P, vp]),
+            "oracle_step": (i32, [P, vp, dp, d, dp, i32]),
+            "oracle_stage_fluxes": (i32, [P, vp, d, vp, vp, vp, vp, i32]),
+            "oracle_stencil_eval": (None, [i32, vp, d, dp, dp]),
+            "oracle_beta": (d, [i32, vp]),
+            "oracle_ao_eval": (None, [vp, d, d, d, d, dp, dp]),
+            "oracle_indicator": (i32, [vp, d, i32, dp, dp, C.POINTER(i32)]),
+            "oracle_char_matrices": (None, [i32, i32, vp, d, vp, vp]),
+            "oracle_maxwell_moments": (None, [d, d, d, d, d, i32, vp, vp, vp]),
+            "oracle_slope_solve": (None, [i32, vp, d, vp, vp]),
+            "oracle_time_coeffs": (None, [d, d, vp]),
+            "oracle_gp_flux": (None, [P, vp, vp, vp, vp, vp, vp, d, vp, vp, dp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle returned status {code}")
+        self.code = code
+
+
+# ---------------------------------------------------------------- whole scheme
+def flags(prob: Problem, W):
+    """Widened troubled-cell flags (Sec. 2.3.1 Steps 1-4) of every interior cell: (fx, fy)."""
+    W = _f64(W)
+    ps = prob.c_struct()
+    cells = prob.nx * (prob.ny if prob.dim == 2 else 1)
+    fx = np.zeros(cells, np.uint8)
+    fy = np.zeros(cells, np.uint8)
+    rc = lib().oracle_flags(C.byref(ps), _ptr(W), _ptr(fx), _ptr(fy))
+    if rc:
+        raise OracleError(rc)
+    shp = (prob.nx,) if prob.dim == 1 else (prob.ny, prob.nx)
+    return fx.reshape(shp), (fy.reshape(shp) if prob.dim == 2 else None)
+
+
+def cfl_dt(prob: Problem, W) -> float:
+    """CFL time step (Sec. 3) before clipping to the end time."""
+    W = _f64(W)
+    ps = prob.c_struct()
+    return lib().oracle_cfl_dt(C.byref(ps), _ptr(W))
+
+
+def step(prob: Problem, W, t: float, t_end: float = float("inf"), nthreads: int = 1):
+    """One S2O4 step (Sec. 2.2). Returns (W_new, t_new, dt_taken)."""
+    W = _f64(W).copy()
+    ps = prob.c_struct()
+    tt = C.c_double(t)
+    dtk = C.c_double(0.0)
+    rc = lib().oracle_step(C.byref(ps), _ptr(W), C.byref(tt), float(t_end), C.byref(dtk), int(nthreads))
+    if rc:
+        raise OracleError(rc)
+    return W, tt.value, dtk.value
+
+
+def run(prob: Problem, W, t_end: float, max_steps: int = 10**9, t0: float = 0.0, nthreads: int = 1):
+    """Advance to t_end (or max_steps). Returns (W, t, steps, dts)."""
+    W = _f64(W).copy()
+    t = t0
+    dts = []
+    while t < t_end and len(dts) < max_steps:
+        W, t, dt = step(prob, W, t, t_end, nthreads)
+        dts.append(dt)
+    return W, t, len(dts), dts
+
+
+def stage_fluxes(prob: Problem, W, dt: float, nthreads: int = 1):
+    """F and dF/dt at every interface for time step dt (paper eqs. for F and its time derivative)."""
+    W = _f64(W)
+    ps = prob.c_struct()
+    nc, nx, ny = prob.nc, prob.nx, (prob.ny if prob.dim == 2 else 1)
+    Fx = np.zeros((nc, ny, nx + 1))
+    Gx = np.zeros_like(Fx)
+    Fy = np.zeros((nc, ny + 1, nx)) if prob.dim == 2 else np.zeros(1)
+    Gy = np.zeros_like(Fy)
+    rc = lib().oracle_stage_fluxes(C.byref(ps), _ptr(W), float(dt), _ptr(Fx), _ptr(Gx), _ptr(Fy),
+                                   _ptr(Gy), int(nthreads))
+    if rc:
+        raise OracleError(rc)
+    if prob.dim == 1:
+        return Fx[:, 0, :], Gx[:, 0, :], None, None
+    return Fx, Gx, Fy, Gy
+
+
+# ---------------------------------------------------------------- unit level
+def stencil_eval(k: int, q, xi: float):
+    q = _f64(q)
+    v, d = C.c_double(), C.c_double()
+    lib().oracle_stencil_eval(int(k), _ptr(q), float(xi), C.byref(v), C.byref(d))
+    return v.value, d.value
+
+
+def beta(k: int, q) -> float:
+    q = _f64(q)
+    return lib().oracle_beta(int(k), _ptr(q))
+
+
+def ao_eval(q, xi: float, gamma_hi=0.85, gamma_lo=0.85, eps=1e-8):
+    q = _f64(q)
+    v, d = C.c_double(), C.c_double()
+    lib().oracle_ao_eval(_ptr(q), float(xi), gamma_hi, gamma_lo, eps, C.byref(v), C.byref(d))
+    return v.value, d.value
+
+
+def indicator(q, h: float, zeta1_mode: int = 0):
+    """Troubled-cell test of one component: (troubled, xbar, xhat, deciding step)."""
+    q = _f64(q)
+    xb, xh = C.c_double(), C.c_double()
+    st = C.c_int32()
+    t = lib().oracle_indicator(_ptr(q), float(h), int(zeta1_mode), C.byref(xb), C.byref(xh), C.byref(st))
+    return int(t), xb.value, xh.value, st.value
+
+
+def char_matrices(dim: int, direction: int, W, gamma=1.4):
+    W = _f64(W)
+    n = dim + 2
+    R = np.zeros((n, n))
+    L = np.zeros((n, n))
+    lib().oracle_char_matrices(int(dim), int(direction), _ptr(W), float(gamma), _ptr(R), _ptr(L))
+    return R, L
+
+
+def maxwell_moments(U, V, lam, K, half=0):
+    Mu = np.zeros(9)
+    Mv = np.zeros(9)
+    Mx = np.zeros(4)
+    lib().oracle_maxwell_moments(1.0, float(U), float(V), float(lam), float(K), int(half), _ptr(Mu),
+                                 _ptr(Mv), _ptr(Mx))
+    return Mu, Mv, Mx
+
+
+def slope_solve(dim: int, W, b, gamma=1.4):
+    W = _f64(W)
+    b = _f64(b)
+    a = np.zeros(dim + 2)
+    lib().oracle_slope_solve(int(dim), _ptr(W), float(gamma), _ptr(b), _ptr(a))
+    return a
+
+
+def time_coeffs(delta: float, tau: float):
+    Cc = np.zeros(5)
+    lib().oracle_time_coeffs(float(delta), float(tau), _ptr(Cc))
+    return Cc
+
+
+def gp_flux(prob: Problem, Wl, Wxl, Wyl, Wr, Wxr, Wyr, dt: float):
+    """Time-integrated flux at one Gauss point for delta = dt and dt/2, and the collision time."""
+    arrs = [_f64(a) for a in (Wl, Wxl, Wyl, Wr, Wxr, Wyr)]
+    n = prob.nc
+    Fd = np.zeros(n)
+    Fh = np.zeros(n)
+    tau = C.c_double()
+    ps = prob.c_struct()
+    lib().oracle_gp_flux(C.byref(ps), *[_ptr(a) for a in arrs], float(dt), _ptr(Fd), _ptr(Fh), C.byref(tau))
+    return Fd, Fh, tau.value

@@ -1,0 +1,1153 @@
+/*
+ * hgks_oracle.c -- TEST INFRASTRUCTURE ONLY (see hgks_oracle.h).
+ *
+ * A plain, slow FP64 CPU implementation of what the HIP library computes, written
+ * from the paper (Mu et al., arXiv 2304.05572) step by step in its order and notation:
+ *   Sec. 2.1  BGK model, Maxwellian g, moments <.>, Eq. (equ6)/(equ10) interface solution,
+ *             time-integrated flux Eq. (equ12)
+ *   Sec. 2.2  two-stage fourth-order (S2O4) time marching
+ *   Sec. 2.3  hybrid WENO5-AO reconstruction: troubled-cell indicator Steps 1-4, linear upwind
+ *             Step 5, WENO-AO(5,3) in characteristic variables, equilibrium state Eq. (equ46)-(equ47),
+ *             2D dimension-by-dimension reconstruction at two Gauss points
+ *   Sec. 3    collision time, CFL time step, boundary conditions of the tests
+ * It deliberately uses generic machinery (reconstruction polynomials fitted from cell averages,
+ * moments integrated term by term from explicitly expanded integrands, 4x4 linear solves) rather
+ * than the pre-expanded coefficient formulas of the HIP kernels, so that the two share nothing
+ * but the definitions. Where the paper is silent or garbled the readings are the ones listed in
+ * the design notes (troubled-cell threshold in normalised units, perpendicular cell flag for the
+ * tangential step, u<0 in the second half-space integral, g_l paired with H(u), ...).
+ *
+ * The troubled-cell discriminant is evaluated with one fixed expression tree and no floating
+ * point contraction (build with -ffp-contract=off), because that decision must come out the same,
+ * bit for bit, on the GPU.
+ */
+#include "hgks_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NG 4    /* ghost layers: the widened flag of the first ghost cell needs 4 cells */
+#define MAXC 4  /* conserved variables in 2D */
+
+/* ======================================================================== */
+/* 1. Reconstruction polynomials in the normalised coordinate xi=(x-x_i)/dx  */
+/* ======================================================================== */
+
+static double ipow(double x, int m) {
+  double r = 1.0;
+  for (int i = 0; i < m; ++i) r *= x;
+  return r;
+}
+
+/* Average of xi^m over cell j, i.e. over [j-1/2, j+1/2]. */
+static double cell_avg_monomial(int j, int m) {
+  return (ipow(j + 0.5, m + 1) - ipow(j - 0.5, m + 1)) / (double)(m + 1);
+}
+
+/* Solve A x = b (n <= 6) by Gaussian elimination with partial pivoting. */
+static void lin_solve(int n, const double* Ain, const double* bin, double* x) {
+  double A[6][7];
+  for (int r = 0; r < n; ++r) {
+    for (int c = 0; c < n; ++c) A[r][c] = Ain[r * n + c];
+    A[r][n] = bin[r];
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (piv != col)
+      for (int c = 0; c <= n; ++c) {
+        double t = A[col][c];
+        A[col][c] = A[piv][c];
+        A[piv][c] = t;
+      }
+    for (int r = col + 1; r < n; ++r) {
+      double f = A[r][col] / A[col][col];
+      for (int c = col; c <= n; ++c) A[r][c] -= f * A[col][c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = A[r][n];
+    for (int c = r + 1; c < n; ++c) s -= A[r][c] * x[c];
+    x[r] = s / A[r][r];
+  }
+}
+
+static void mat_inverse(int n, const double* A, double* Ainv) {
+  double e[6], col[6];
+  for (int c = 0; c < n; ++c) {
+    for (int r = 0; r < n; ++r) e[r] = (r == c) ? 1.0 : 0.0;
+    lin_solve(n, A, e, col);
+    for (int r = 0; r < n; ++r) Ainv[r * n + c] = col[r];
+  }
+}
+
+/* Stencils (Sec. 2.3.1): S0={i-2,i-1,i}, S1={i-1,i,i+1}, S2={i,i+1,i+2} (quadratics p_k^{r3})
+ * and S3={i-2..i+2} (quartic p_3^{r5}). Each polynomial is fixed by matching the cell averages. */
+static const int g_off[4][5] = {{-2, -1, 0, 0, 0}, {-1, 0, 1, 0, 0}, {0, 1, 2, 0, 0}, {-2, -1, 0, 1, 2}};
+static const int g_npts[4] = {3, 3, 3, 5};
+static const int g_first[4] = {0, 1, 2, 0}; /* position in the 5-cell window of the first cell */
+static double g_fit[4][25];                 /* polynomial coefficients = g_fit * cell averages */
+static int g_ready = 0;
+
+static void oracle_init(void) {
+  if (g_ready) return;
+  for (int k = 0; k < 4; ++k) {
+    int n = g_npts[k];
+    double A[25];
+    for (int r = 0; r < n; ++r)
+      for (int m = 0; m < n; ++m) A[r * n + m] = cell_avg_monomial(g_off[k][r], m);
+    mat_inverse(n, A, g_fit[k]);
+  }
+  g_ready = 1;
+}
+
+/* Coefficients c[0..deg] of stencil polynomial k from the five-cell window q[0..4]. */
+static void stencil_coeffs(int k, const double* q, double* c) {
+  int n = g_npts[k];
+  for (int m = 0; m < n; ++m) {
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s += g_fit[k][m * n + r] * q[g_first[k] + r];
+    c[m] = s;
+  }
+}
+
+static void poly_eval(const double* c, int deg, double xi, double* val, double* der) {
+  double v = 0.0, d = 0.0;
+  for (int m = deg; m >= 0; --m) v = v * xi + c[m];
+  for (int m = deg; m >= 1; --m) d = d * xi + m * c[m];
+  *val = v;
+  *der = d;
+}
+
+/* Smoothness indicator: sum over q of  dx^(2q-1) * integral over the cell of (d^q p/dx^q)^2, which in
+ * the normalised coordinate is sum_q integral_{-1/2}^{1/2} (d^q p/dxi^q)^2 dxi. */
+static double beta_of(const double* c, int deg) {
+  double b = 0.0;
+  for (int q = 1; q <= deg; ++q) {
+    double d[5] = {0}, sq[9] = {0};
+    int dd = deg - q;
+    for (int m = 0; m <= dd; ++m) {
+      double f = 1.0;
+      for (int s = m + 1; s <= m + q; ++s) f *= s;
+      d[m] = c[m + q] * f;
+    }
+    for (int a = 0; a <= dd; ++a)
+      for (int e = 0; e <= dd; ++e) sq[a + e] += d[a] * d[e];
+    for (int m = 0; m <= 2 * dd; ++m) b += sq[m] * (ipow(0.5, m + 1) - ipow(-0.5, m + 1)) / (m + 1);
+  }
+  return b;
+}
+
+/* WENO-AO(5,3) of the five cell averages q at xi: value and xi-derivative. The same normalised
+ * weights serve the value and the derivative (the derivative is that of the same polynomial). */
+static void ao_eval(const double* q, double xi, double ghi, double glo, double eps, double* val,
+                    double* der) {
+  double c[5], pv[4], pd[4], beta[4], gam[4], w[4], sw = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    int deg = g_npts[k] - 1;
+    stencil_coeffs(k, q, c);
+    poly_eval(c, deg, xi, &pv[k], &pd[k]);
+    beta[k] = beta_of(c, deg);
+  }
+  gam[3] = ghi;
+  gam[0] = (1.0 - ghi) * (1.0 - glo) / 2.0;
+  gam[2] = gam[0];
+  gam[1] = (1.0 - ghi) * glo;
+  double delta = (fabs(beta[3] - beta[0]) + fabs(beta[3] - beta[1]) + fabs(beta[3] - beta[2])) / 3.0;
+  for (int k = 0; k < 4; ++k) {
+    w[k] = gam[k] * (1.0 + delta / (beta[k] + eps));
+    sw += w[k];
+  }
+  double v = pv[3], d = pd[3];
+  for (int k = 0; k < 3; ++k) {
+    v -= gam[k] * pv[k];
+    d -= gam[k] * pd[k];
+  }
+  v *= (w[3] / sw) / gam[3];
+  d *= (w[3] / sw) / gam[3];
+  for (int k = 0; k < 3; ++k) {
+    v += (w[k] / sw) * pv[k];
+    d += (w[k] / sw) * pd[k];
+  }
+  *val = v;
+  *der = d;
+}
+
+/* ======================================================================== */
+/* 2. Troubled-cell indicator (Sec. 2.3.1, Steps 1-4)                        */
+/* ======================================================================== */
+
+/* Returns 1 if the cell is troubled for this component. q: cells i-2..i+2; h: cell size.
+ * D1 = 10*a1*dx and D2 = 34*a2*dx^2 are the least-squares quadratic's coefficients in
+ * normalised units; Step 1 compares |2 a2| with zeta1 = (5/17) h in normalised units. */
+static int troubled_component(const double* q, double h, int zeta1_mode, double* xbar_out,
+                              double* xhat_out, int* step_out) {
+  double Qm2 = q[0], Qm1 = q[1], Q0 = q[2], Qp1 = q[3], Qp2 = q[4];
+  double D1 = (Qp1 - Qm1) + 2.0 * (Qp2 - Qm2);
+  double D2 = (4.0 * (Qm2 + Qp2) + (Qm1 + Qp1)) - 10.0 * Q0;
+  double thr = (zeta1_mode == 0) ? 5.0 * h : 5.0 * h * h * h;
+  *xbar_out = NAN;
+  *xhat_out = NAN;
+  if (fabs(D2) <= thr) { *step_out = 1; return 0; }
+  double xbar = -(17.0 * D1) / (10.0 * D2); /* extreme point of the least-squares quadratic */
+  *xbar_out = xbar;
+  if (fabs(xbar) > 2.5) { *step_out = 2; return 0; }
+  double a1h = 0.5 * (Qp1 - Qm1);           /* conservative quadratic on {i-1,i,i+1} */
+  double a2h = 0.5 * ((Qm1 + Qp1) - 2.0 * Q0);
+  double den = 2.0 * a2h + (a2h == 0.0 ? 1e-30 : 0.0);
+  double xhat = -a1h / den;
+  *xhat_out = xhat;
+  *step_out = 3;
+  if (fabs(xbar - xhat) <= 0.25) return 0;
+  return 1;
+}
+
+/* ======================================================================== */
+/* 3. Characteristic matrices                                               */
+/* ======================================================================== */
+
+/* Right eigenvectors of the Euler flux Jacobian in direction dir (1: first velocity component,
+ * 2: second), columns ordered by eigenvalue u_n - c, u_n (entropy), [u_n (shear)], u_n + c. */
+static void char_R(int dim, int dir, const double* W, double gamma, double* R) {
+  int nc = dim + 2;
+  double rho = W[0];
+  double u[2] = {W[1] / rho, dim == 2 ? W[2] / rho : 0.0};
+  double E = W[nc - 1];
+  double q2 = u[0] * u[0] + u[1] * u[1];
+  double p = (gamma - 1.0) * (E - 0.5 * rho * q2);
+  double c = sqrt(gamma * p / rho);
+  double H = (E + p) / rho;
+  double un = u[dir - 1];
+  memset(R, 0, sizeof(double) * nc * nc);
+  int last = nc - 1;
+  /* column 0: u_n - c */
+  R[0 * nc + 0] = 1.0;
+  for (int d = 0; d < dim; ++d) R[(1 + d) * nc + 0] = u[d] - (d == dir - 1 ? c : 0.0);
+  R[last * nc + 0] = H - un * c;
+  /* column 1: entropy wave */
+  R[0 * nc + 1] = 1.0;
+  for (int d = 0; d < dim; ++d) R[(1 + d) * nc + 1] = u[d];
+  R[last * nc + 1] = 0.5 * q2;
+  if (dim == 2) {
+    /* column 2: shear wave */
+    int t = (dir == 1) ? 2 : 1; /* row of the tangential momentum */
+    R[t * nc + 2] = 1.0;
+    R[last * nc + 2] = u[t - 1];
+  }
+  /* last column: u_n + c */
+  R[0 * nc + last] = 1.0;
+  for (int d = 0; d < dim; ++d) R[(1 + d) * nc + last] = u[d] + (d == dir - 1 ? c : 0.0);
+  R[last * nc + last] = H + un * c;
+}
+
+/* ======================================================================== */
+/* 4. One-sided hybrid reconstruction of a vector of conserved variables     */
+/* ======================================================================== */
+
+typedef struct {
+  int dim, nc;
+  double gamma, K, mu, Pr, c1, c2;
+  int ns;
+  double ghi, glo, eps;
+  int recon, zeta1_mode;
+} params;
+
+/* q5[r][c]: the side's five cells (offsets -2..2), xi: evaluation point. Unflagged: component-wise
+ * linear quartic (Step 5). Flagged: WENO-AO on U = R^{-1} Q, then back-projection with R. */
+static void recon_side(const params* pp, const double q5[5][MAXC], double xi, int flag,
+                       const double* R, const double* L, double* val, double* der) {
+  int nc = pp->nc;
+  double q[5], c[5];
+  if (!flag) {
+    for (int cc = 0; cc < nc; ++cc) {
+      for (int r = 0; r < 5; ++r) q[r] = q5[r][cc];
+      stencil_coeffs(3, q, c);
+      poly_eval(c, 4, xi, &val[cc], &der[cc]);
+    }
+    return;
+  }
+  double cv[MAXC], cd[MAXC];
+  for (int k = 0; k < nc; ++k) {
+    for (int r = 0; r < 5; ++r) {
+      double s = 0.0;
+      for (int cc = 0; cc < nc; ++cc) s += L[k * nc + cc] * q5[r][cc];
+      q[r] = s;
+    }
+    ao_eval(q, xi, pp->ghi, pp->glo, pp->eps, &cv[k], &cd[k]);
+  }
+  for (int cc = 0; cc < nc; ++cc) {
+    double sv = 0.0, sd = 0.0;
+    for (int k = 0; k < nc; ++k) {
+      sv += R[cc * nc + k] * cv[k];
+      sd += R[cc * nc + k] * cd[k];
+    }
+    val[cc] = sv;
+    der[cc] = sd;
+  }
+}
+
+/* ======================================================================== */
+/* 5. Kinetic part: Maxwellian moments and the gas-kinetic flux (Sec. 2.1)   */
+/* ======================================================================== */
+
+#define NMOM 12
+typedef struct {
+  double rho, U, V, lam;
+  double Mu[NMOM]; /* <u^n> over all u */
+  double Mh[NMOM]; /* <u^n> over u>0 (side +1) or u<0 (side -1) */
+  double Mv[NMOM]; /* <v^n> */
+  double Mx[4];    /* <(xi^2)^n> over the K internal degrees of freedom */
+} maxw;
+
+/* Moments of the normalised Maxwellian (rho = 1) of a Gaussian in u with mean U and variance
+ * 1/(2 lam): integration by parts gives <u^(n+2)> = U <u^(n+1)> + (n+1)/(2 lam) <u^n>, the same
+ * recurrence on a half line because the boundary term at u = 0 vanishes for n >= 0. */
+static void maxw_moments(double U, double V, double lam, double K, int side, maxw* g) {
+  g->Mu[0] = 1.0;
+  g->Mu[1] = U;
+  g->Mv[0] = 1.0;
+  g->Mv[1] = V;
+  for (int n = 0; n + 2 < NMOM; ++n) {
+    g->Mu[n + 2] = U * g->Mu[n + 1] + (n + 1) / (2.0 * lam) * g->Mu[n];
+    g->Mv[n + 2] = V * g->Mv[n + 1] + (n + 1) / (2.0 * lam) * g->Mv[n];
+  }
+  if (side != 0) {
+    double s = (double)side;
+    g->Mh[0] = 0.5 * erfc(-s * sqrt(lam) * U);
+    g->Mh[1] = U * g->Mh[0] + s * exp(-lam * U * U) / (2.0 * sqrt(M_PI * lam));
+    for (int n = 0; n + 2 < NMOM; ++n)
+      g->Mh[n + 2] = U * g->Mh[n + 1] + (n + 1) / (2.0 * lam) * g->Mh[n];
+  } else {
+    for (int n = 0; n < NMOM; ++n) g->Mh[n] = NAN;
+  }
+  /* xi^2 = sum of K squared Gaussians of variance 1/(2 lam): chi-square moments */
+  g->Mx[0] = 1.0;
+  g->Mx[1] = K / (2.0 * lam);
+  g->Mx[2] = K * (K + 2.0) / (4.0 * lam * lam);
+  g->Mx[3] = K * (K + 2.0) * (K + 4.0) / (8.0 * lam * lam * lam);
+}
+
+static void maxw_from_W(const params* pp, const double* W, int side, maxw* g) {
+  int nc = pp->nc;
+  double rho = W[0];
+  double U = W[1] / rho;
+  double V = pp->dim == 2 ? W[2] / rho : 0.0;
+  double p = (pp->gamma - 1.0) * (W[nc - 1] - 0.5 * rho * (U * U + V * V));
+  g->rho = rho;
+  g->U = U;
+  g->V = V;
+  g->lam = rho / (2.0 * p);
+  maxw_moments(U, V, g->lam, pp->K, side, g);
+}
+
+/* Polynomials in (u, v, xi^2) as explicit term lists: coef * u^i * v^j * (xi^2)^k. */
+typedef struct {
+  double c;
+  int i, j, k;
+} term;
+#define MAXT 64
+typedef struct {
+  int n;
+  term t[MAXT];
+} poly;
+
+static void p_set(poly* p, int n, const term* t) {
+  p->n = n;
+  for (int s = 0; s < n; ++s) p->t[s] = t[s];
+}
+static void p_push(poly* p, double c, int i, int j, int k) {
+  p->t[p->n].c = c;
+  p->t[p->n].i = i;
+  p->t[p->n].j = j;
+  p->t[p->n].k = k;
+  p->n++;
+}
+
+/* psi_alpha: (1, u, v, (u^2+v^2+xi^2)/2) in 2D, (1, u, (u^2+xi^2)/2) in 1D. */
+static void psi_poly(const params* pp, int alpha, poly* p) {
+  p->n = 0;
+  if (alpha == 0) p_push(p, 1.0, 0, 0, 0);
+  else if (alpha == 1) p_push(p, 1.0, 1, 0, 0);
+  else if (alpha == 2 && pp->dim == 2) p_push(p, 1.0, 0, 1, 0);
+  else {
+    p_push(p, 0.5, 2, 0, 0);
+    if (pp->dim == 2) p_push(p, 0.5, 0, 2, 0);
+    p_push(p, 0.5, 0, 0, 1);
+  }
+}
+
+/* The microscopic slope a = a_1 + a_2 u (+ a_3 v) + a_last (u^2 (+v^2) + xi^2)/2, i.e. a . psi. */
+static void a_poly(const params* pp, const double* a, poly* p) {
+  poly ps;
+  p->n = 0;
+  for (int al = 0; al < pp->nc; ++al) {
+    psi_poly(pp, al, &ps);
+    for (int s = 0; s < ps.n; ++s) p_push(p, a[al] * ps.t[s].c, ps.t[s].i, ps.t[s].j, ps.t[s].k);
+  }
+}
+
+static double mom(const maxw* g, int half, int i, int j, int k) {
+  return (half ? g->Mh[i] : g->Mu[i]) * g->Mv[j] * g->Mx[k];
+}
+
+/* out[alpha] = < A * B * psi_alpha > for the normalised Maxwellian g (half: over the half line). */
+static void momvec(const params* pp, const poly* A, const poly* B, const maxw* g, int half,
+                   double* out) {
+  poly ps;
+  for (int al = 0; al < pp->nc; ++al) {
+    psi_poly(pp, al, &ps);
+    double s = 0.0;
+    for (int a = 0; a < A->n; ++a)
+      for (int b = 0; b < B->n; ++b)
+        for (int r = 0; r < ps.n; ++r)
+          s += A->t[a].c * B->t[b].c * ps.t[r].c *
+               mom(g, half, A->t[a].i + B->t[b].i + ps.t[r].i, A->t[a].j + B->t[b].j + ps.t[r].j,
+                   A->t[a].k + B->t[b].k + ps.t[r].k);
+    out[al] = s;
+  }
+}
+
+/* scalar < A * B * C > */
+static double mom3(const poly* A, const poly* B, const poly* C, const maxw* g, int half) {
+  double s = 0.0;
+  for (int a = 0; a < A->n; ++a)
+    for (int b = 0; b < B->n; ++b)
+      for (int r = 0; r < C->n; ++r)
+        s += A->t[a].c * B->t[b].c * C->t[r].c *
+             mom(g, half, A->t[a].i + B->t[b].i + C->t[r].i, A->t[a].j + B->t[b].j + C->t[r].j,
+                 A->t[a].k + B->t[b].k + C->t[r].k);
+  return s;
+}
+
+static const term T_ONE = {1.0, 0, 0, 0};
+static const term T_U = {1.0, 1, 0, 0};
+static const term T_V = {1.0, 0, 1, 0};
+static const term T_UU = {1.0, 2, 0, 0};
+static const term T_UV = {1.0, 1, 1, 0};
+
+/* Solve <a psi> = b for the coefficients of a (the relation between a microscopic slope and the
+ * macroscopic one, Sec. 2.1), with the 'mass matrix' <psi_alpha psi_beta> of g. */
+static void solve_slope(const params* pp, const maxw* g, const double* b, double* a) {
+  int nc = pp->nc;
+  double M[16], colv[MAXC];
+  poly one, ps;
+  p_set(&one, 1, &T_ONE);
+  for (int be = 0; be < nc; ++be) {
+    psi_poly(pp, be, &ps);
+    momvec(pp, &ps, &one, g, 0, colv);
+    for (int al = 0; al < nc; ++al) M[al * nc + be] = colv[al];
+  }
+  lin_solve(nc, M, b, a);
+}
+
+/* Time integrals over [0, delta] of the coefficient functions of Eq. (equ10):
+ *   C1: 1 - e^{-t/tau}                 (g0)
+ *   C2: (t + tau) e^{-t/tau} - tau     (g0 (a1 u + a2 v))
+ *   C3: t - tau + tau e^{-t/tau}       (g0 A)
+ *   C4: e^{-t/tau}                     (g_k, and -tau g_k A^k)
+ *   C5: (t + tau) e^{-t/tau}           (-g_k (a1^k u + a2^k v))
+ * tau = 0 is the limit; for delta/tau < 1 the Taylor series of the same integrals is summed
+ * because the closed forms cancel there. */
+static void time_coeffs(double d, double tau, double* C) {
+  if (tau == 0.0) {
+    C[0] = d;
+    C[1] = 0.0;
+    C[2] = 0.5 * d * d;
+    C[3] = 0.0;
+    C[4] = 0.0;
+    return;
+  }
+  double x = d / tau;
+  if (x < 1.0) {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, term_k = 1.0;
+    for (int k = 1; k <= 40; ++k) {
+      term_k *= x / k; /* x^k / k! */
+      double sg = (k % 2 == 0) ? 1.0 : -1.0; /* (-1)^k */
+      if (k >= 2) s1 += sg * term_k;
+      if (k >= 3) {
+        s2 += sg * (k - 2) * term_k;
+        s3 -= sg * term_k;
+      }
+      s4 -= sg * term_k;
+    }
+    C[0] = tau * s1;
+    C[1] = tau * tau * s2;
+    C[2] = tau * tau * s3;
+    C[3] = tau * s4;
+    C[4] = tau * tau * (x + s2);
+    return;
+  }
+  double E = exp(-x);
+  C[0] = d - tau * (1.0 - E);
+  C[1] = 2.0 * tau * tau - tau * d - tau * (d + 2.0 * tau) * E;
+  C[2] = 0.5 * d * d - tau * d + tau * tau * (1.0 - E);
+  C[3] = tau * (1.0 - E);
+  C[4] = 2.0 * tau * tau - tau * (2.0 * tau + d) * E;
+}
+
+/* Gas-kinetic flux at one Gauss point: time-integrated fluxes F(W, dt) and F(W, dt/2) of
+ * Eq. (equ12) with the interface distribution of Eq. (equ10). Inputs are the reconstructed
+ * non-equilibrium states W^{l,r} and their normal (x) and tangential (y) derivatives. */
+static void gp_flux(const params* pp, const double* Wl, const double* Wxl, const double* Wyl,
+                    const double* Wr, const double* Wxr, const double* Wyr, double dt, double* Fd,
+                    double* Fh, double* tau_out) {
+  int nc = pp->nc, dim = pp->dim;
+  maxw gs[2];
+  const double* Ws[2] = {Wl, Wr};
+  const double* Wxs[2] = {Wxl, Wxr};
+  const double* Wys[2] = {Wyl, Wyr};
+  double ax[2][MAXC], ay[2][MAXC], A[2][MAXC];
+  poly one, pu, pv, puu, puv, pax, pay, pA;
+  p_set(&one, 1, &T_ONE);
+  p_set(&pu, 1, &T_U);
+  p_set(&pv, 1, &T_V);
+  p_set(&puu, 1, &T_UU);
+  p_set(&puv, 1, &T_UV);
+
+  double Wc[MAXC] = {0}, Wxc[MAXC] = {0}, Wyc[MAXC] = {0};
+  double M4a[MAXC] = {0}, M4b[MAXC] = {0}, M5[MAXC] = {0};
+  double tmp[MAXC], tmp2[MAXC], b[MAXC];
+  for (int s = 0; s < 2; ++s) {
+    int side = (s == 0) ? +1 : -1; /* g_l over u>0, g_r over u<0 */
+    maxw_from_W(pp, Ws[s], side, &gs[s]);
+    const maxw* g = &gs[s];
+    for (int al = 0; al < nc; ++al) b[al] = Wxs[s][al] / g->rho;
+    solve_slope(pp, g, b, ax[s]);
+    for (int al = 0; al < nc; ++al) b[al] = (dim == 2 ? Wys[s][al] : 0.0) / g->rho;
+    solve_slope(pp, g, b, ay[s]);
+    /* compatibility of the initial distribution: <a1 u + a2 v + A> = 0 */
+    a_poly(pp, ax[s], &pax);
+    a_poly(pp, ay[s], &pay);
+    momvec(pp, &pax, &pu, g, 0, tmp);
+    momvec(pp, &pay, &pv, g, 0, tmp2);
+    for (int al = 0; al < nc; ++al) b[al] = -(tmp[al] + tmp2[al]);
+    solve_slope(pp, g, b, A[s]);
+    a_poly(pp, A[s], &pA);
+    /* equilibrium state and its slopes, Eq. (equ46)-(equ47) */
+    momvec(pp, &one, &one, g, 1, tmp);
+    for (int al = 0; al < nc; ++al) Wc[al] += g->rho * tmp[al];
+    momvec(pp, &pax, &one, g, 1, tmp);
+    for (int al = 0; al < nc; ++al) Wxc[al] += g->rho * tmp[al];
+    momvec(pp, &pay, &one, g, 1, tmp);
+    for (int al = 0; al < nc; ++al) Wyc[al] += g->rho * tmp[al];
+    /* free-transport terms of Eq. (equ10) */
+    momvec(pp, &one, &pu, g, 1, tmp);
+    for (int al = 0; al < nc; ++al) M4a[al] += g->rho * tmp[al];
+    momvec(pp, &pA, &pu, g, 1, tmp);
+    for (int al = 0; al < nc; ++al) M4b[al] += g->rho * tmp[al];
+    momvec(pp, &pax, &puu, g, 1, tmp);
+    momvec(pp, &pay, &puv, g, 1, tmp2);
+    for (int al = 0; al < nc; ++al) M5[al] += g->rho * (tmp[al] + tmp2[al]);
+  }
+  /* equilibrium g0 at the interface */
+  maxw g0;
+  maxw_from_W(pp, Wc, 0, &g0);
+  double a0[MAXC], b0[MAXC], A0[MAXC];
+  for (int al = 0; al < nc; ++al) b[al] = Wxc[al] / g0.rho;
+  solve_slope(pp, &g0, b, a0);
+  for (int al = 0; al < nc; ++al) b[al] = Wyc[al] / g0.rho;
+  solve_slope(pp, &g0, b, b0);
+  poly pa0, pb0, pA0;
+  a_poly(pp, a0, &pa0);
+  a_poly(pp, b0, &pb0);
+  momvec(pp, &pa0, &pu, &g0, 0, tmp);
+  momvec(pp, &pb0, &pv, &g0, 0, tmp2);
+  for (int al = 0; al < nc; ++al) b[al] = -(tmp[al] + tmp2[al]);
+  solve_slope(pp, &g0, b, A0);
+  a_poly(pp, A0, &pA0);
+  double M1[MAXC], M2[MAXC], M3[MAXC];
+  momvec(pp, &one, &pu, &g0, 0, M1);
+  momvec(pp, &pa0, &puu, &g0, 0, tmp);
+  momvec(pp, &pb0, &puv, &g0, 0, tmp2);
+  for (int al = 0; al < nc; ++al) {
+    M1[al] *= g0.rho;
+    M2[al] = g0.rho * (tmp[al] + tmp2[al]);
+  }
+  momvec(pp, &pA0, &pu, &g0, 0, M3);
+  for (int al = 0; al < nc; ++al) M3[al] *= g0.rho;
+
+  /* collision time (Sec. 3): pressures of the reconstructed states at this point */
+  double pl = gs[0].rho / (2.0 * gs[0].lam), pr = gs[1].rho / (2.0 * gs[1].lam);
+  double p0 = g0.rho / (2.0 * g0.lam);
+  double jump = fabs((pl - pr) / (pl + pr));
+  double tau = pp->ns ? pp->mu / p0 + pp->c2 * jump * dt : pp->c1 * dt + pp->c2 * jump * dt;
+  if (tau_out) *tau_out = tau;
+
+  /* heat-flux moments for the Prandtl-number correction (Navier-Stokes, Pr != 1) */
+  int prfix = pp->ns && pp->Pr != 1.0;
+  double Q1 = 0, Q2 = 0, Q3 = 0, Q4a = 0, Q4b = 0, Q5 = 0;
+  if (prfix) {
+    /* Q = (u-U0) ((u-U0)^2 + (v-V0)^2 + xi^2) / 2, expanded */
+    double U0 = g0.U, V0 = g0.V;
+    poly Q;
+    Q.n = 0;
+    /* (u-U0)^3 / 2 */
+    p_push(&Q, 0.5, 3, 0, 0);
+    p_push(&Q, -1.5 * U0, 2, 0, 0);
+    p_push(&Q, 1.5 * U0 * U0, 1, 0, 0);
+    p_push(&Q, -0.5 * U0 * U0 * U0, 0, 0, 0);
+    if (dim == 2) { /* (u-U0)(v-V0)^2 / 2 */
+      p_push(&Q, 0.5, 1, 2, 0);
+      p_push(&Q, -V0, 1, 1, 0);
+      p_push(&Q, 0.5 * V0 * V0, 1, 0, 0);
+      p_push(&Q, -0.5 * U0, 0, 2, 0);
+      p_push(&Q, U0 * V0, 0, 1, 0);
+      p_push(&Q, -0.5 * U0 * V0 * V0, 0, 0, 0);
+    }
+    p_push(&Q, 0.5, 1, 0, 1); /* (u-U0) xi^2 / 2 */
+    p_push(&Q, -0.5 * U0, 0, 0, 1);
+    Q1 = g0.rho * mom3(&Q, &one, &one, &g0, 0);
+    Q2 = g0.rho * (mom3(&Q, &pa0, &pu, &g0, 0) + mom3(&Q, &pb0, &pv, &g0, 0));
+    Q3 = g0.rho * mom3(&Q, &pA0, &one, &g0, 0);
+    for (int s = 0; s < 2; ++s) {
+      const maxw* g = &gs[s];
+      a_poly(pp, ax[s], &pax);
+      a_poly(pp, ay[s], &pay);
+      a_poly(pp, A[s], &pA);
+      Q4a += g->rho * mom3(&Q, &one, &one, g, 1);
+      Q4b += g->rho * mom3(&Q, &pA, &one, g, 1);
+      Q5 += g->rho * (mom3(&Q, &pax, &pu, g, 1) + mom3(&Q, &pay, &pv, g, 1));
+    }
+  }
+
+  double deltas[2] = {dt, 0.5 * dt};
+  double* outs[2] = {Fd, Fh};
+  for (int m = 0; m < 2; ++m) {
+    double C[5];
+    time_coeffs(deltas[m], tau, C);
+    for (int al = 0; al < nc; ++al)
+      outs[m][al] = C[0] * M1[al] + C[1] * M2[al] + C[2] * M3[al] + C[3] * (M4a[al] - tau * M4b[al]) -
+                    C[4] * M5[al];
+    if (prfix) {
+      double q = C[0] * Q1 + C[1] * Q2 + C[2] * Q3 + C[3] * (Q4a - tau * Q4b) - C[4] * Q5;
+      outs[m][nc - 1] += (1.0 / pp->Pr - 1.0) * q;
+    }
+  }
+}
+
+/* ======================================================================== */
+/* 6. Grid, ghost cells, flags, directional sweeps, S2O4                     */
+/* ======================================================================== */
+
+static void make_params(const oracle_problem* p, params* pp) {
+  pp->dim = p->dim;
+  pp->nc = p->dim + 2;
+  pp->gamma = p->gamma;
+  /* internal degrees of freedom: K + 2 = 2/(gamma-1) in 2D, K + 1 = 2/(gamma-1) in 1D */
+  pp->K = (p->dim == 2) ? (4.0 - 2.0 * p->gamma) / (p->gamma - 1.0) : (3.0 - p->gamma) / (p->gamma - 1.0);
+  pp->mu = p->mu;
+  pp->Pr = p->Pr;
+  pp->c1 = p->c1;
+  pp->c2 = p->c2;
+  pp->ns = (p->eqn == 1);
+  pp->ghi = p->gamma_hi;
+  pp->glo = p->gamma_lo;
+  pp->eps = p->weno_eps;
+  pp->recon = p->recon;
+  pp->zeta1_mode = p->zeta1_mode;
+}
+
+static int check_problem(const oracle_problem* p) {
+  if (p->dim != 1 && p->dim != 2) return ORACLE_EINVAL;
+  if (p->nx < 5 || (p->dim == 2 && p->ny < 5) || (p->dim == 1 && p->ny != 1)) return ORACLE_EINVAL;
+  if (!(p->gamma > 1.0) || !(p->x1 > p->x0) || (p->dim == 2 && !(p->y1 > p->y0))) return ORACLE_EINVAL;
+  if (p->eqn == 1 && !(p->Pr > 0.0 && p->mu >= 0.0)) return ORACLE_EINVAL;
+  int nb = p->dim == 2 ? 4 : 2;
+  for (int s = 0; s < nb; ++s)
+    if (p->bc[s] < 0 || p->bc[s] > 3) return ORACLE_EINVAL;
+  for (int s = 0; s < nb; s += 2)
+    if ((p->bc[s] == 0) != (p->bc[s + 1] == 0)) return ORACLE_EINVAL;
+  return ORACLE_OK;
+}
+
+/* Index of the interior cell that ghost index i (in 0..n-1 or outside) takes its data from,
+ * and which velocity components change sign (bit 0: normal, bit 1: tangential). */
+static int bc_map(int i, int n, int bc_lo, int bc_hi, int* flip) {
+  *flip = 0;
+  if (i >= 0 && i < n) return i;
+  int bc = (i < 0) ? bc_lo : bc_hi;
+  switch (bc) {
+    case 0: return ((i % n) + n) % n;          /* periodic */
+    case 1: return (i < 0) ? 0 : n - 1;        /* zero-gradient outflow */
+    case 2: *flip = 1; return (i < 0) ? -1 - i : 2 * n - 1 - i;  /* slip wall / symmetry */
+    default: *flip = 3; return (i < 0) ? -1 - i : 2 * n - 1 - i; /* no-slip adiabatic wall */
+  }
+}
+
+/* A directional view: normal index n (fast), tangential index t, padded by NG on every side that
+ * exists (no tangential padding in 1D). Components are rotated so that slot 1 is the normal
+ * momentum and slot 2 the tangential one. */
+typedef struct {
+  int nc, dim, nn, nt, pn, pt, tp;
+  double hn, ht;
+  double* P;
+} frame;
+
+static double* fr_at(const frame* f, int c, int jt, int in) {
+  return f->P + ((size_t)c * f->pt + (size_t)(jt + f->tp)) * f->pn + (size_t)(in + NG);
+}
+
+/* Build the padded frame for direction dir (0: x, 1: y) from the unpadded state. */
+static void build_frame(const oracle_problem* p, const double* W, int dir, frame* f) {
+  int nc = p->dim + 2, nx = p->nx, ny = p->ny;
+  f->nc = nc;
+  f->dim = p->dim;
+  double dx = (p->x1 - p->x0) / nx, dy = (p->dim == 2) ? (p->y1 - p->y0) / ny : 1.0;
+  if (dir == 0) { f->nn = nx; f->nt = ny; f->hn = dx; f->ht = dy; }
+  else { f->nn = ny; f->nt = nx; f->hn = dy; f->ht = dx; }
+  f->tp = (p->dim == 2) ? NG : 0;
+  f->pn = f->nn + 2 * NG;
+  f->pt = f->nt + 2 * f->tp;
+  f->P = (double*)malloc(sizeof(double) * nc * f->pn * f->pt);
+  for (int jt = -f->tp; jt < f->nt + f->tp; ++jt)
+    for (int in = -NG; in < f->nn + NG; ++in) {
+      int i = (dir == 0) ? in : jt, j = (dir == 0) ? jt : in;
+      int fxf, fyf = 0;
+      int ii = bc_map(i, nx, p->bc[0], p->bc[1], &fxf);
+      int jj = (p->dim == 2) ? bc_map(j, ny, p->bc[2], p->bc[3], &fyf) : 0;
+      double v[MAXC];
+      for (int c = 0; c < nc; ++c) v[c] = W[((size_t)c * ny + jj) * nx + ii];
+      /* x-walls flip the x velocity (and for no-slip also y); y-walls the reverse */
+      int negu = ((fxf & 1) != 0) ^ ((fyf & 2) != 0);
+      int negv = ((fxf & 2) != 0) ^ ((fyf & 1) != 0);
+      if (negu) v[1] = -v[1];
+      if (p->dim == 2 && negv) v[2] = -v[2];
+      if (dir == 1) { double t = v[1]; v[1] = v[2]; v[2] = t; }
+      for (int c = 0; c < nc; ++c) *fr_at(f, c, jt, in) = v[c];
+    }
+}
+
+/* Widened flags of every padded cell where the 7-cell stencil fits, along the normal (Fn) and
+ * along the tangential direction (Ft, 2D). Cells whose flag is undefined hold 255. */
+static void frame_flags(const frame* f, const params* pp, uint8_t* Fn, uint8_t* Ft) {
+  int pn = f->pn, pt = f->pt, nc = f->nc;
+  uint8_t* Tn = (uint8_t*)malloc((size_t)pn * pt);
+  uint8_t* Tt = (uint8_t*)malloc((size_t)pn * pt);
+  memset(Tn, 255, (size_t)pn * pt);
+  memset(Tt, 255, (size_t)pn * pt);
+  double q[5], xb, xh;
+  int st;
+  for (int a = 0; a < pt; ++a)
+    for (int b = 2; b < pn - 2; ++b) {
+      int T = 0;
+      for (int c = 0; c < nc; ++c) {
+        for (int r = 0; r < 5; ++r) q[r] = f->P[((size_t)c * pt + a) * pn + b - 2 + r];
+        T |= troubled_component(q, f->hn, pp->zeta1_mode, &xb, &xh, &st);
+      }
+      Tn[(size_t)a * pn + b] = (uint8_t)T;
+    }
+  if (f->dim == 2)
+    for (int a = 2; a < pt - 2; ++a)
+      for (int b = 0; b < pn; ++b) {
+        int T = 0;
+        for (int c = 0; c < nc; ++c) {
+          for (int r = 0; r < 5; ++r) q[r] = f->P[((size_t)c * pt + a - 2 + r) * pn + b];
+          T |= troubled_component(q, f->ht, pp->zeta1_mode, &xb, &xh, &st);
+        }
+        Tt[(size_t)a * pn + b] = (uint8_t)T;
+      }
+  memset(Fn, 255, (size_t)pn * pt);
+  if (Ft) memset(Ft, 255, (size_t)pn * pt);
+  for (int a = 0; a < pt; ++a)
+    for (int b = 3; b < pn - 3; ++b) {
+      size_t o = (size_t)a * pn + b;
+      uint8_t v = (uint8_t)(Tn[o - 1] | Tn[o] | Tn[o + 1]);
+      if (pp->recon == 1) v = 1;
+      if (pp->recon == 2) v = 0;
+      Fn[o] = v;
+    }
+  if (Ft && f->dim == 2)
+    for (int a = 3; a < pt - 3; ++a)
+      for (int b = 0; b < pn; ++b) {
+        size_t o = (size_t)a * pn + b;
+        uint8_t v = (uint8_t)(Tt[o - pn] | Tt[o] | Tt[o + pn]);
+        if (pp->recon == 1) v = 1;
+        if (pp->recon == 2) v = 0;
+        Ft[o] = v;
+      }
+  free(Tn);
+  free(Tt);
+}
+
+/* Time-integrated fluxes F(dt), F(dt/2) at every interface of the frame (normal-direction
+ * interfaces k = 0..nn of rows 0..nt-1), averaged over the Gauss points of each segment.
+ * Output layout: [nc][nt][nn+1], components in the frame's (rotated) order. */
+static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd, double* Fh,
+                         int nthreads) {
+  int nc = f->nc, nn = f->nn, nt = f->nt, pn = f->pn, pt = f->pt, tp = f->tp;
+  uint8_t* Fn = (uint8_t*)malloc((size_t)pn * pt);
+  uint8_t* Ft = (uint8_t*)malloc((size_t)pn * pt);
+  frame_flags(f, pp, Fn, f->dim == 2 ? Ft : NULL);
+  int nrows = (f->dim == 2) ? nt + 4 : 1; /* rows -2..nt+1 carry line values in 2D */
+  int r0 = (f->dim == 2) ? -2 : 0;
+  size_t lsz = (size_t)nrows * (nn + 1);
+  /* line values: [kind][c][row][k], kind 0: W^l, 1: W_x^l, 2: W^r, 3: W_x^r */
+  double* LV = (double*)malloc(sizeof(double) * 4 * nc * lsz);
+#define LVAT(kind, c, row, k) LV[(((size_t)(kind) * nc + (c)) * nrows + ((row) - r0)) * (nn + 1) + (k)]
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+  for (int row = r0; row < r0 + nrows; ++row) {
+    for (int k = 0; k <= nn; ++k) {
+      double q5[5][MAXC], R[16], L[16], avg[MAXC], val[MAXC], der[MAXC];
+      int fl = Fn[(size_t)(row + tp) * pn + (k - 1 + NG)];
+      int fr = Fn[(size_t)(row + tp) * pn + (k + NG)];
+      if (fl || fr) {
+        for (int c = 0; c < nc; ++c) avg[c] = 0.5 * (*fr_at(f, c, row, k - 1) + *fr_at(f, c, row, k));
+        char_R(f->dim, 1, avg, pp->gamma, R);
+        mat_inverse(nc, R, L);
+      }
+      for (int s = 0; s < 2; ++s) {
+        int cell = k - 1 + s;
+        for (int r = 0; r < 5; ++r)
+          for (int c = 0; c < nc; ++c) q5[r][c] = *fr_at(f, c, row, cell - 2 + r);
+        recon_side(pp, q5, s == 0 ? 0.5 : -0.5, s == 0 ? fl : fr, R, L, val, der);
+        for (int c = 0; c < nc; ++c) {
+          LVAT(2 * s, c, row, k) = val[c];
+          LVAT(2 * s + 1, c, row, k) = der[c] / f->hn;
+        }
+      }
+    }
+  }
+  const double eta = 1.0 / (2.0 * sqrt(3.0)); /* two-point Gauss-Legendre on [-1/2, 1/2] */
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+  for (int j = 0; j < nt; ++j) {
+    for (int k = 0; k <= nn; ++k) {
+      double sumd[MAXC] = {0}, sumh[MAXC] = {0};
+      double Ws[2][MAXC], Wxs[2][MAXC], Wys[2][MAXC], Fdg[MAXC], Fhg[MAXC];
+      if (f->dim == 1) {
+        for (int s = 0; s < 2; ++s)
+          for (int c = 0; c < nc; ++c) {
+            Ws[s][c] = LVAT(2 * s, c, 0, k);
+            Wxs[s][c] = LVAT(2 * s + 1, c, 0, k);
+            Wys[s][c] = 0.0;
+          }
+        gp_flux(pp, Ws[0], Wxs[0], Wys[0], Ws[1], Wxs[1], Wys[1], dt, sumd, sumh, NULL);
+      } else {
+        int ftf[2], anyf;
+        double R[16], L[16], avg[MAXC];
+        for (int s = 0; s < 2; ++s) ftf[s] = Ft[(size_t)(j + tp) * pn + (k - 1 + s + NG)];
+        anyf = ftf[0] || ftf[1];
+        if (anyf) {
+          for (int c = 0; c < nc; ++c) avg[c] = 0.5 * (LVAT(0, c, j, k) + LVAT(2, c, j, k));
+          char_R(f->dim, 2, avg, pp->gamma, R);
+          mat_inverse(nc, R, L);
+        }
+        for (int m = 0; m < 2; ++m) {
+          double xi = (m == 0) ? -eta : eta;
+          for (int s = 0; s < 2; ++s) {
+            double q5[5][MAXC], val[MAXC], der[MAXC];
+            for (int r = 0; r < 5; ++r)
+              for (int c = 0; c < nc; ++c) q5[r][c] = LVAT(2 * s, c, j - 2 + r, k);
+            recon_side(pp, q5, xi, ftf[s], R, L, val, der);
+            for (int c = 0; c < nc; ++c) {
+              Ws[s][c] = val[c];
+              Wys[s][c] = der[c] / f->ht;
+            }
+            for (int r = 0; r < 5; ++r)
+              for (int c = 0; c < nc; ++c) q5[r][c] = LVAT(2 * s + 1, c, j - 2 + r, k);
+            recon_side(pp, q5, xi, ftf[s], R, L, val, der);
+            for (int c = 0; c < nc; ++c) Wxs[s][c] = val[c];
+          }
+          gp_flux(pp, Ws[0], Wxs[0], Wys[0], Ws[1], Wxs[1], Wys[1], dt, Fdg, Fhg, NULL);
+          for (int c = 0; c < nc; ++c) {
+            sumd[c] += 0.5 * Fdg[c];
+            sumh[c] += 0.5 * Fhg[c];
+          }
+        }
+      }
+      for (int c = 0; c < nc; ++c) {
+        Fd[((size_t)c * nt + j) * (nn + 1) + k] = sumd[c];
+        Fh[((size_t)c * nt + j) * (nn + 1) + k] = sumh[c];
+      }
+    }
+  }
+#undef LVAT
+  free(LV);
+  free(Fn);
+  free(Ft);
+}
+
+/* Time-integrated fluxes of both directions in the grid's own component order:
+ * x: [nc][ny][nx+1], y: [nc][ny+1][nx]. */
+static void all_fluxes(const oracle_problem* p, const params* pp, const double* W, double dt,
+                       double* Fxd, double* Fxh, double* Fyd, double* Fyh, int nthreads) {
+  frame f;
+  build_frame(p, W, 0, &f);
+  frame_fluxes(&f, pp, dt, Fxd, Fxh, nthreads);
+  free(f.P);
+  if (p->dim == 2) {
+    int nx = p->nx, ny = p->ny, nc = pp->nc;
+    size_t n = (size_t)nc * nx * (ny + 1);
+    double* td = (double*)malloc(sizeof(double) * n);
+    double* th = (double*)malloc(sizeof(double) * n);
+    build_frame(p, W, 1, &f);
+    frame_fluxes(&f, pp, dt, td, th, nthreads); /* [nc'][nx][ny+1] */
+    free(f.P);
+    for (int c = 0; c < nc; ++c) {
+      int cs = (c == 1) ? 2 : (c == 2) ? 1 : c; /* rotate momentum back */
+      for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          Fyd[((size_t)c * (ny + 1) + j) * nx + i] = td[((size_t)cs * nx + i) * (ny + 1) + j];
+          Fyh[((size_t)c * (ny + 1) + j) * nx + i] = th[((size_t)cs * nx + i) * (ny + 1) + j];
+        }
+    }
+    free(td);
+    free(th);
+  }
+}
+
+static int nonphysical(const oracle_problem* p, const double* W) {
+  int nc = p->dim + 2;
+  size_t ncell = (size_t)p->nx * p->ny;
+  for (size_t s = 0; s < ncell; ++s) {
+    double rho = W[s], mx = W[ncell + s], my = (p->dim == 2) ? W[2 * ncell + s] : 0.0;
+    double E = W[(size_t)(nc - 1) * ncell + s];
+    double pr = (p->gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / rho);
+    if (!(rho > 0.0) || !(pr > 0.0) || !isfinite(E)) return 1;
+  }
+  return 0;
+}
+
+double oracle_cfl_dt(const oracle_problem* p, const double* W) {
+  /* dt = CFL * min over cells of min(h/(|U| + c), h^2/(4 nu)), nu = mu/rho, h = min(dx, dy) */
+  int nc = p->dim + 2;
+  size_t ncell = (size_t)p->nx * p->ny;
+  double dx = (p->x1 - p->x0) / p->nx;
+  double h = dx;
+  if (p->dim == 2) {
+    double dy = (p->y1 - p->y0) / p->ny;
+    if (dy < h) h = dy;
+  }
+  double qmin = INFINITY;
+  for (size_t s = 0; s < ncell; ++s) {
+    double rho = W[s];
+    double U = W[ncell + s] / rho;
+    double V = (p->dim == 2) ? W[2 * ncell + s] / rho : 0.0;
+    double pr = (p->gamma - 1.0) * (W[(size_t)(nc - 1) * ncell + s] - 0.5 * rho * (U * U + V * V));
+    double c = sqrt(p->gamma * pr / rho);
+    double sp = sqrt(U * U + V * V) + c;
+    double q = h / sp;
+    if (p->eqn == 1) {
+      double qv = (h * h) / (4.0 * (p->mu / rho));
+      q = fmin(q, qv);
+    }
+    qmin = fmin(qmin, q);
+  }
+  return p->cfl * qmin;
+}
+
+int oracle_stage_fluxes(const oracle_problem* p, const double* W, double dt, double* Fx, double* Gx,
+                        double* Fy, double* Gy, int nthreads) {
+  oracle_init();
+  int rc = check_problem(p);
+  if (rc) return rc;
+  params pp;
+  make_params(p, &pp);
+  int nc = pp.nc, nx = p->nx, ny = p->ny;
+  size_t nxf = (size_t)nc * ny * (nx + 1), nyf = (size_t)nc * (ny + 1) * nx;
+  double* Fxd = (double*)malloc(sizeof(double) * nxf);
+  double* Fxh = (double*)malloc(sizeof(double) * nxf);
+  double* Fyd = p->dim == 2 ? (double*)malloc(sizeof(double) * nyf) : NULL;
+  double* Fyh = p->dim == 2 ? (double*)malloc(sizeof(double) * nyf) : NULL;
+  all_fluxes(p, &pp, W, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
+  /* F = (4 F(dt/2) - F(dt))/dt, dF/dt = 4 (F(dt) - 2 F(dt/2))/dt^2 */
+  for (size_t s = 0; s < nxf; ++s) {
+    Fx[s] = (4.0 * Fxh[s] - Fxd[s]) / dt;
+    Gx[s] = 4.0 * (Fxd[s] - 2.0 * Fxh[s]) / (dt * dt);
+  }
+  if (p->dim == 2)
+    for (size_t s = 0; s < nyf; ++s) {
+      Fy[s] = (4.0 * Fyh[s] - Fyd[s]) / dt;
+      Gy[s] = 4.0 * (Fyd[s] - 2.0 * Fyh[s]) / (dt * dt);
+    }
+  free(Fxd);
+  free(Fxh);
+  free(Fyd);
+  free(Fyh);
+  return ORACLE_OK;
+}
+
+int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken,
+                int nthreads) {
+  oracle_init();
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (nthreads < 1) nthreads = 1;
+  params pp;
+  make_params(p, &pp);
+  if (dt_taken) *dt_taken = 0.0;
+  if (*t >= t_end) return ORACLE_OK;
+  double dt = (p->fixed_dt > 0.0) ? p->fixed_dt : oracle_cfl_dt(p, W);
+  if (!(dt > 0.0) || !isfinite(dt)) return ORACLE_EDT;
+  double tnew;
+  if (*t + dt >= t_end) {
+    dt = t_end - *t;
+    tnew = t_end;
+  } else {
+    tnew = *t + dt;
+  }
+  int nc = pp.nc, nx = p->nx, ny = p->ny, dim = p->dim;
+  double dx = (p->x1 - p->x0) / nx, dy = dim == 2 ? (p->y1 - p->y0) / ny : 1.0;
+  size_t ncell = (size_t)nx * ny;
+  size_t nxf = (size_t)nc * ny * (nx + 1), nyf = dim == 2 ? (size_t)nc * (ny + 1) * nx : 1;
+  double* Fxd = (double*)malloc(sizeof(double) * nxf);
+  double* Fxh = (double*)malloc(sizeof(double) * nxf);
+  double* Fyd = (double*)malloc(sizeof(double) * nyf);
+  double* Fyh = (double*)malloc(sizeof(double) * nyf);
+  double* Fx = (double*)malloc(sizeof(double) * nxf); /* F^n + dt/6 dF^n/dt, then the final flux */
+  double* Fy = (double*)malloc(sizeof(double) * nyf);
+  double* Gxn = (double*)malloc(sizeof(double) * nxf);
+  double* Gyn = (double*)malloc(sizeof(double) * nyf);
+  double* Ws = (double*)malloc(sizeof(double) * nc * ncell);
+
+  /* stage 1 at t_n */
+  all_fluxes(p, &pp, W, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
+  for (size_t s = 0; s < nxf; ++s) {
+    Fx[s] = (4.0 * Fxh[s] - Fxd[s]) / dt;
+    Gxn[s] = 4.0 * (Fxd[s] - 2.0 * Fxh[s]) / (dt * dt);
+  }
+  if (dim == 2)
+    for (size_t s = 0; s < nyf; ++s) {
+      Fy[s] = (4.0 * Fyh[s] - Fyd[s]) / dt;
+      Gyn[s] = 4.0 * (Fyd[s] - 2.0 * Fyh[s]) / (dt * dt);
+    }
+  /* W* = W^n - [F(dt/2)_{i+1/2} - F(dt/2)_{i-1/2}]/dx - [G(dt/2)_{j+1/2} - G(dt/2)_{j-1/2}]/dy */
+  for (int c = 0; c < nc; ++c)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double a = (Fxh[((size_t)c * ny + j) * (nx + 1) + i + 1] - Fxh[((size_t)c * ny + j) * (nx + 1) + i]) / dx;
+        double b = 0.0;
+        if (dim == 2) b = (Fyh[((size_t)c * (ny + 1) + j + 1) * nx + i] - Fyh[((size_t)c * (ny + 1) + j) * nx + i]) / dy;
+        size_t o = (size_t)c * ncell + (size_t)j * nx + i;
+        Ws[o] = W[o] - (a + b);
+      }
+  if (nonphysical(p, Ws)) rc = ORACLE_ENONPHYS;
+  if (!rc) {
+    /* stage 2 at t* = t_n + dt/2: only the time derivative of the flux is needed */
+    all_fluxes(p, &pp, Ws, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
+    for (size_t s = 0; s < nxf; ++s) {
+      double Gs = 4.0 * (Fxd[s] - 2.0 * Fxh[s]) / (dt * dt);
+      Fx[s] = Fx[s] + dt / 6.0 * (Gxn[s] + 2.0 * Gs);
+    }
+    if (dim == 2)
+      for (size_t s = 0; s < nyf; ++s) {
+        double Gs = 4.0 * (Fyd[s] - 2.0 * Fyh[s]) / (dt * dt);
+        Fy[s] = Fy[s] + dt / 6.0 * (Gyn[s] + 2.0 * Gs);
+      }
+    for (int c = 0; c < nc; ++c)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          double a = (Fx[((size_t)c * ny + j) * (nx + 1) + i + 1] - Fx[((size_t)c * ny + j) * (nx + 1) + i]) / dx;
+          double b = 0.0;
+          if (dim == 2) b = (Fy[((size_t)c * (ny + 1) + j + 1) * nx + i] - Fy[((size_t)c * (ny + 1) + j) * nx + i]) / dy;
+          size_t o = (size_t)c * ncell + (size_t)j * nx + i;
+          Ws[o] = W[o] - dt * (a + b);
+        }
+    if (nonphysical(p, Ws)) rc = ORACLE_ENONPHYS;
+    if (!rc) {
+      memcpy(W, Ws, sizeof(double) * nc * ncell);
+      *t = tnew;
+      if (dt_taken) *dt_taken = dt;
+    }
+  }
+  free(Fxd); free(Fxh); free(Fyd); free(Fyh);
+  free(Fx); free(Fy); free(Gxn); free(Gyn); free(Ws);
+  return rc;
+}
+
+int oracle_flags(const oracle_problem* p, const double* W, uint8_t* fx, uint8_t* fy) {
+  oracle_init();
+  int rc = check_problem(p);
+  if (rc) return rc;
+  params pp;
+  make_params(p, &pp);
+  for (int dir = 0; dir < p->dim; ++dir) {
+    frame f;
+    build_frame(p, W, dir, &f);
+    uint8_t* Fn = (uint8_t*)malloc((size_t)f.pn * f.pt);
+    frame_flags(&f, &pp, Fn, NULL);
+    uint8_t* out = (dir == 0) ? fx : fy;
+    for (int jt = 0; jt < f.nt; ++jt)
+      for (int in = 0; in < f.nn; ++in) {
+        uint8_t v = Fn[(size_t)(jt + f.tp) * f.pn + in + NG];
+        if (dir == 0) out[(size_t)jt * p->nx + in] = v;
+        else out[(size_t)in * p->nx + jt] = v;
+      }
+    free(Fn);
+    free(f.P);
+  }
+  return ORACLE_OK;
+}
+
+/* ======================================================================== */
+/* 7. Unit-level entry points                                               */
+/* ======================================================================== */
+
+void oracle_stencil_eval(int k, const double* q, double xi, double* val, double* der) {
+  oracle_init();
+  double c[5];
+  stencil_coeffs(k, q, c);
+  poly_eval(c, g_npts[k] - 1, xi, val, der);
+}
+
+double oracle_beta(int k, const double* q) {
+  oracle_init();
+  double c[5];
+  stencil_coeffs(k, q, c);
+  return beta_of(c, g_npts[k] - 1);
+}
+
+void oracle_ao_eval(const double* q, double xi, double ghi, double glo, double eps, double* val,
+                    double* der) {
+  oracle_init();
+  ao_eval(q, xi, ghi, glo, eps, val, der);
+}
+
+int oracle_indicator(const double* q, double h, int zeta1_mode, double* xbar, double* xhat, int* step) {
+  return troubled_component(q, h, zeta1_mode, xbar, xhat, step);
+}
+
+void oracle_char_matrices(int dim, int dir, const double* W, double gamma, double* R, double* L) {
+  oracle_init();
+  char_R(dim, dir, W, gamma, R);
+  mat_inverse(dim + 2, R, L);
+}
+
+void oracle_maxwell_moments(double rho, double U, double V, double lam, double K, int half,
+                            double* Mu, double* Mv, double* Mxi) {
+  maxw g;
+  (void)rho;
+  maxw_moments(U, V, lam, K, half, &g);
+  for (int n = 0; n < 9; ++n) {
+    Mu[n] = half ? g.Mh[n] : g.Mu[n];
+    Mv[n] = g.Mv[n];
+  }
+  for (int n = 0; n < 4; ++n) Mxi[n] = g.Mx[n];
+}
+
+void oracle_slope_solve(int dim, const double* W, double gamma, const double* b, double* a) {
+  oracle_problem p;
+  memset(&p, 0, sizeof p);
+  p.dim = dim;
+  p.gamma = gamma;
+  params pp;
+  make_params(&p, &pp);
+  maxw g;
+  maxw_from_W(&pp, W, 0, &g);
+  solve_slope(&pp, &g, b, a);
+}
+
+void oracle_time_coeffs(double delta, double tau, double* C) { time_coeffs(delta, tau, C); }
+
+void oracle_gp_flux(const oracle_problem* p, const double* Wl, const double* Wxl, const double* Wyl,
+                    const double* Wr, const double* Wxr, const double* Wyr, double dt, double* Fdt,
+                    double* Fdt2, double* tau_out) {
+  oracle_init();
+  params pp;
+  make_params(p, &pp);
+  gp_flux(&pp, Wl, Wxl, Wyl, Wr, Wxr, Wyr, dt, Fdt, Fdt2, tau_out);
+}

@@ -1,0 +1,73 @@
+/*
+ * hgks_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 CPU oracle of the two-stage fourth-order gas-kinetic scheme
+ * with hybrid WENO5-AO reconstruction (Mu, Zhuo, Zhang, Liu, Zhong, arXiv
+ * 2304.05572). Only the test suite, the smoke check and the benchmark's CPU
+ * baseline may load this library. It shares no code, header or table with the
+ * HIP library under paper_2304_05572_amd/ and the HIP library never calls it.
+ *
+ * Arrays of conserved variables are structure-of-arrays, x fastest:
+ *   2D: W[c][j][i], c in {rho, rho*U, rho*V, rho*E}, size 4*ny*nx
+ *   1D: W[c][i],    c in {rho, rho*U, rho*E},        size 3*nx
+ */
+#ifndef HGKS_ORACLE_H
+#define HGKS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Problem statement (Sec. 2 and Sec. 3 of the paper). Field meanings follow the
+ * HIP library's hgks_problem, but this is a separate declaration. */
+typedef struct {
+  int32_t dim, nx, ny;          /* dim 1 or 2; ny = 1 when dim == 1 */
+  double x0, x1, y0, y1;        /* uniform Cartesian cells */
+  int32_t eqn;                  /* 0 Euler (f = g), 1 Navier-Stokes (first-order Chapman-Enskog) */
+  double gamma, mu, Pr;         /* ratio of specific heats, dynamic viscosity, Prandtl number */
+  double cfl, c1, c2;           /* CFL number and collision-time constants (Sec. 3) */
+  double fixed_dt;              /* > 0: use this time step instead of the CFL one */
+  int32_t bc[4];                /* x-low, x-high, y-low, y-high: 0 periodic, 1 outflow, 2 reflect, 3 no-slip adiabatic */
+  int32_t recon;                /* 0 hybrid, 1 always WENO5-AO, 2 always linear */
+  double gamma_hi, gamma_lo, weno_eps;  /* WENO-AO linear-weight parameters and epsilon */
+  int32_t zeta1_mode;           /* 0: Step-1 threshold 5*h on the normalised quadratic, 1: 5*h^3 */
+  int32_t tangential_flag_mode; /* only 0 (perpendicular cell flag) is implemented */
+} oracle_problem;
+
+enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_ENONPHYS = -4, ORACLE_EDT = -5 };
+
+/* --- whole-scheme entry points ------------------------------------------ */
+/* Widened troubled-cell flags of every interior cell: fx (x direction), fy (y direction, 2D only). */
+int oracle_flags(const oracle_problem* p, const double* W, uint8_t* fx, uint8_t* fy);
+/* CFL time step of state W (before clipping to t_end). */
+double oracle_cfl_dt(const oracle_problem* p, const double* W);
+/* One S2O4 step in place. The step is the CFL one (or fixed_dt), clipped so that t never passes
+ * t_end; *t is advanced. Returns ORACLE_ENONPHYS if a non-physical state appears. */
+int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken, int nthreads);
+/* Stage fluxes of state W for time step dt: Fn, dtFn at every interface.
+ * Fx, Gx: [nc][ny][nx+1]; Fy, Gy: [nc][ny+1][nx] (2D only). */
+int oracle_stage_fluxes(const oracle_problem* p, const double* W, double dt,
+                        double* Fx, double* Gx, double* Fy, double* Gy, int nthreads);
+
+/* --- unit-level entry points (for tests) --------------------------------- */
+/* Sub-stencil polynomial k (0,1,2: quadratics on cells {-2..0},{-1..1},{0..2}; 3: quartic on
+ * {-2..2}) of the five cell averages q, evaluated at normalised coordinate xi. */
+void oracle_stencil_eval(int k, const double* q, double xi, double* val, double* der);
+double oracle_beta(int k, const double* q);
+void oracle_ao_eval(const double* q, double xi, double gamma_hi, double gamma_lo, double eps,
+                    double* val, double* der);
+int oracle_indicator(const double* q, double h, int zeta1_mode, double* xbar, double* xhat, int* step);
+void oracle_char_matrices(int dim, int dir, const double* W, double gamma, double* R, double* L);
+void oracle_maxwell_moments(double rho, double U, double V, double lam, double K, int half,
+                            double* Mu, double* Mv, double* Mxi);
+void oracle_slope_solve(int dim, const double* W, double gamma, const double* b, double* a);
+void oracle_time_coeffs(double delta, double tau, double* C);
+void oracle_gp_flux(const oracle_problem* p, const double* Wl, const double* Wxl, const double* Wyl,
+                    const double* Wr, const double* Wxr, const double* Wyr, double dt,
+                    double* Fdt, double* Fdt2, double* tau_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
