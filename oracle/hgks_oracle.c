@@ -827,14 +827,19 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
           }
         gp_flux(pp, Ws[0], Wxs[0], Wys[0], Ws[1], Wxs[1], Wys[1], dt, sumd, sumh, NULL);
       } else {
-        int ftf[2], anyf;
-        double R[16], L[16], avg[MAXC];
-        for (int s = 0; s < 2; ++s) ftf[s] = Ft[(size_t)(j + tp) * pn + (k - 1 + s + NG)];
-        anyf = ftf[0] || ftf[1];
-        if (anyf) {
-          for (int c = 0; c < nc; ++c) avg[c] = 0.5 * (LVAT(0, c, j, k) + LVAT(2, c, j, k));
-          char_R(f->dim, 2, avg, pp->gamma, R);
-          mat_inverse(nc, R, L);
+        /* Tangential characteristic variables: each side is decomposed about its own line-averaged state
+         * of the centre segment, the state of the cell being reconstructed (reading of "averaged
+         * conservative variables" for a Gauss point inside the segment). */
+        int ftf[2];
+        double R[2][16], L[2][16];
+        for (int s = 0; s < 2; ++s) {
+          ftf[s] = Ft[(size_t)(j + tp) * pn + (k - 1 + s + NG)];
+          if (ftf[s]) {
+            double own[MAXC];
+            for (int c = 0; c < nc; ++c) own[c] = LVAT(2 * s, c, j, k);
+            char_R(f->dim, 2, own, pp->gamma, R[s]);
+            mat_inverse(nc, R[s], L[s]);
+          }
         }
         for (int m = 0; m < 2; ++m) {
           double xi = (m == 0) ? -eta : eta;
@@ -842,14 +847,14 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
             double q5[5][MAXC], val[MAXC], der[MAXC];
             for (int r = 0; r < 5; ++r)
               for (int c = 0; c < nc; ++c) q5[r][c] = LVAT(2 * s, c, j - 2 + r, k);
-            recon_side(pp, q5, xi, ftf[s], R, L, val, der);
+            recon_side(pp, q5, xi, ftf[s], R[s], L[s], val, der);
             for (int c = 0; c < nc; ++c) {
               Ws[s][c] = val[c];
               Wys[s][c] = der[c] / f->ht;
             }
             for (int r = 0; r < 5; ++r)
               for (int c = 0; c < nc; ++c) q5[r][c] = LVAT(2 * s + 1, c, j - 2 + r, k);
-            recon_side(pp, q5, xi, ftf[s], R, L, val, der);
+            recon_side(pp, q5, xi, ftf[s], R[s], L[s], val, der);
             for (int c = 0; c < nc; ++c) Wxs[s][c] = val[c];
           }
           gp_flux(pp, Ws[0], Wxs[0], Wys[0], Ws[1], Wxs[1], Wys[1], dt, Fdg, Fhg, NULL);

@@ -275,3 +275,16 @@ def test_navier_stokes_heat_conduction_with_prandtl(Pr):
     A = np.array([[0, -1j * k, 0], [-1j * k, -nul * k ** 2, -1j * k], [0, -1j * k / cv, -kap * k ** 2 / cv]])
     ref = abs((expm(A * 0.5) @ np.array([1.0, 0, -1.0]))[0])
     assert amp == pytest.approx(ref, rel=3e-3)
+
+
+def test_viscous_shock_tube_runs():
+    """Sec. 3.6: the hybrid scheme passes the Re = 200 viscous shock tube (no-slip adiabatic walls,
+    symmetry top, density ratio 100) without a non-physical state; coarse 48 x 24 grid, 150 steps."""
+    nx, ny = 48, 24
+    P = O.Problem(nx=nx, ny=ny, y1=0.5, bc=(O.BC_NOSLIP, O.BC_NOSLIP, O.BC_NOSLIP, O.BC_REFLECT), eqn=O.NS,
+                  mu=1 / 200, Pr=0.73, cfl=0.3)
+    W0 = wl.viscous_shock_tube(nx, ny)
+    W, t, ns, _ = O.run(P, W0, 1.0, max_steps=150, nthreads=NT)
+    assert ns == 150 and t > 0.3
+    assert W[0].min() > 0
+    assert W[0].sum() == pytest.approx(W0[0].sum(), rel=1e-4)  # no-slip ghost walls: truncation-level
