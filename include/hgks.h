@@ -1,0 +1,150 @@
+/*
+ * hgks.h -- C ABI of the MI355X (gfx950) hot path of the two-stage fourth-order gas-kinetic scheme
+ * with hybrid WENO5-AO reconstruction (Mu, Zhuo, Zhang, Liu, Zhong, arXiv 2304.05572).
+ *
+ * The library advances one or many independent structured-grid problems (1D or 2D, Euler or
+ * Navier-Stokes) with:
+ *   - the troubled-cell indicator of Sec. 2.3.1 (Steps 1-4), evaluated in FP64 on cell averages;
+ *   - linear fifth-order upwind reconstruction (Step 5) or WENO-AO(5,3) in characteristic
+ *     variables for values and slopes, normal and tangential (Sec. 2.3.1, 2.3.3);
+ *   - the kinetic equilibrium state of Eq. (equ46)-(equ47);
+ *   - the gas-kinetic flux of Eq. (equ10) integrated over [0, dt] and [0, dt/2] (Eq. (equ12)),
+ *     turned into F and dF/dt (Sec. 2.2);
+ *   - the S2O4 time marching of Sec. 2.2 with the collision time and CFL step of Sec. 3.
+ *
+ * Conventions shared by every entry point:
+ *   - State arrays are FP64, structure of arrays, x fastest:
+ *       2D: W[c][j][i], c in {rho, rho*U, rho*V, rho*E}, 4*ny*nx doubles
+ *       1D: W[c][i],    c in {rho, rho*U, rho*E},        3*nx doubles
+ *   - Pointers flagged `on_device` are device addresses on the current HIP device (e.g. from a
+ *     torch tensor); otherwise host addresses. The caller owns every buffer it passes; the library
+ *     copies in and out and never keeps a caller pointer, except the workspace bound by
+ *     hgks_bind_workspace, which it borrows until hgks_destroy and never frees.
+ *   - Every call returns an hgks_status. Device-side failures (a non-physical state) are sticky:
+ *     they are reported by the next hgks_step / hgks_run / hgks_get_state of that handle.
+ *   - A handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef HGKS_H
+#define HGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HGKS_OK = 0,
+  HGKS_EINVAL = -1,    /* invalid argument or problem statement */
+  HGKS_ENOMEM = -2,    /* device or host allocation failed, or bound workspace too small */
+  HGKS_EDEVICE = -3,   /* a HIP runtime call failed */
+  HGKS_ENONPHYS = -4,  /* rho <= 0, p <= 0 or NaN appeared in an intermediate or new state */
+  HGKS_EDT = -5        /* the time step came out <= 0 or not finite */
+} hgks_status;
+
+typedef enum { HGKS_EULER = 0, HGKS_NS = 1 } hgks_eqn;
+
+/* Boundary conditions (Sec. 3): periodic; zero-gradient outflow ("non-reflecting"); reflecting
+ * slip wall / symmetry plane (normal momentum negated in the ghost cells); no-slip adiabatic wall
+ * (both momenta negated in the ghost cells). */
+typedef enum {
+  HGKS_BC_PERIODIC = 0,
+  HGKS_BC_OUTFLOW = 1,
+  HGKS_BC_REFLECT = 2,
+  HGKS_BC_NOSLIP_ADIABATIC = 3
+} hgks_bc;
+
+/* Reconstruction: the hybrid scheme, or every cell troubled (the WENO5-AO GKS the paper compares
+ * against), or no cell troubled (pure linear upwind). */
+typedef enum { HGKS_RECON_HYBRID = 0, HGKS_RECON_FORCE_WENOAO = 1, HGKS_RECON_FORCE_LINEAR = 2 } hgks_recon;
+
+/* HGKS_FP64: reconstruction and flux in FP64.
+ * HGKS_FP32_BULK: reconstruction and flux arithmetic in FP32; the stored state, the troubled-cell
+ * flags, the CFL reduction and the time-integration coefficients of Eq. (equ10) stay FP64. */
+typedef enum { HGKS_FP64 = 0, HGKS_FP32_BULK = 1 } hgks_precision;
+
+/* One problem (Sec. 2 statement; parameters of Sec. 3). */
+typedef struct {
+  int32_t dim, nx, ny;          /* dim 1 or 2; ny must be 1 when dim == 1; nx, ny >= 5 */
+  double x0, x1, y0, y1;        /* uniform Cartesian cells on [x0,x1] x [y0,y1] */
+  int32_t eqn;                  /* hgks_eqn: Euler (f = g) or Navier-Stokes (first-order expansion) */
+  double gamma, mu, Pr;         /* ratio of specific heats (> 1), dynamic viscosity, Prandtl number */
+  double cfl, c1, c2;           /* CFL number; collision time tau = c1 dt + c2 |pl-pr|/(pl+pr) dt
+                                   (Euler) or mu/p + c2 |pl-pr|/(pl+pr) dt (NS); c1 = c2 = 0: tau = 0 */
+  double fixed_dt;              /* > 0 overrides the CFL time step */
+  int32_t bc[4];                /* hgks_bc of x-low, x-high, y-low, y-high; periodic must be paired */
+  int32_t recon;                /* hgks_recon */
+  double gamma_hi, gamma_lo, weno_eps;  /* WENO-AO linear weights and epsilon (0.85, 0.85, 1e-8) */
+  int32_t zeta1_mode;           /* Step-1 threshold: 0 -> 5*h on the normalised quadratic, 1 -> 5*h^3 */
+  int32_t tangential_flag_mode; /* 0: tangential step uses the perpendicular-direction cell flag */
+} hgks_problem;
+
+typedef struct {
+  int32_t precision;  /* hgks_precision */
+  int32_t autotune;   /* 1: time the tile shapes on the first step and keep the fastest (cached on disk
+                         under $HGKS_AUTOTUNE_CACHE if set) */
+  int32_t use_graph;  /* 1: hgks_run replays one captured HIP graph per step */
+  int32_t tile;       /* tile-shape index when autotune == 0 (-1: library default) */
+  int32_t profile;    /* 1: bracket every kernel launch of hgks_step / hgks_run (without graphs) with
+                         HIP events on the library's stream; read with hgks_get_profile */
+  void* hip_stream;   /* borrowed hipStream_t (NULL: the library's own stream) */
+} hgks_opts;
+
+typedef struct hgks hgks_t;
+
+/* Validate the problems and prepare the device-side tables. nprob >= 1 independent problems are
+ * advanced together, each with its own time step. Device memory is allocated here unless the
+ * caller binds a workspace before the first hgks_set_ic (see hgks_workspace_bytes). */
+hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opts* opts, hgks_t** out);
+
+/* Bytes of device memory the handle needs (states, stage buffers, flags, fluxes, scalars). */
+size_t hgks_workspace_bytes(const hgks_t* h);
+
+/* Use caller-owned device memory (>= hgks_workspace_bytes, 256-byte aligned) instead of allocating.
+ * Must precede the first hgks_set_ic. */
+hgks_status hgks_bind_workspace(hgks_t* h, void* dev_ptr, size_t bytes);
+
+/* Upload the cell averages of problem `prob` and set its time to t0. */
+hgks_status hgks_set_ic(hgks_t* h, int32_t prob, const double* W, int32_t on_device, double t0);
+
+/* Advance every problem by one S2O4 step of its own CFL (or fixed) time step, with no end time.
+ * dt_taken: nprob entries (may be NULL). Synchronises the stream. */
+hgks_status hgks_step(hgks_t* h, double* dt_taken);
+
+/* Advance every problem to its t_end[p] (the last step is shortened to land on it), or until
+ * max_steps steps have been issued. steps_out: nprob entries (may be NULL). */
+hgks_status hgks_run(hgks_t* h, const double* t_end, int64_t max_steps, int64_t* steps_out);
+
+/* Copy the state of problem `prob` out; *t receives its time (t may be NULL). */
+hgks_status hgks_get_state(const hgks_t* h, int32_t prob, double* W, int32_t on_device, double* t);
+
+/* Widened troubled-cell flags (Steps 1-4) of the current state of problem `prob`, one byte per cell
+ * ([ny][nx]); fy is ignored in 1D. */
+hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy);
+
+/* Interface flux F and its time derivative dF/dt of the current state for time step dt, as used by
+ * the first stage (Sec. 2.2). Host arrays, FP64: Fx, Gx [nc][ny][nx+1]; Fy, Gy [nc][ny+1][nx] (2D). */
+hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx,
+                                    double* Fy, double* Gy);
+
+/* Statistics of problem `prob`: out[0] steps taken, out[1] cells, out[2] time, out[3] last dt,
+ * out[4] fraction of cells flagged in x at the last flag evaluation, out[5] the same in y. */
+hgks_status hgks_get_stats(const hgks_t* h, int32_t prob, double* out);
+
+/* Kernel timings gathered since the handle was created (opts.profile == 1), from HIP events recorded
+ * on the launching stream. out[2k] = total milliseconds and out[2k+1] = number of launches of kernel
+ * group k: 0 fused reconstruction + flux, 1 stage update, 2 troubled-cell flags, 3 scalar kernels
+ * (time step, commit). Synchronises the stream. */
+hgks_status hgks_get_profile(hgks_t* h, double* out /* 8 entries */);
+
+/* Tile shape in use: *tn interfaces along the normal, *tt rows along the tangential direction. */
+hgks_status hgks_get_tile(const hgks_t* h, int32_t* tn, int32_t* tt);
+
+void hgks_destroy(hgks_t* h);
+const char* hgks_status_str(hgks_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

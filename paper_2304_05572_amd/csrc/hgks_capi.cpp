@@ -1,0 +1,685 @@
+// Host runtime and C ABI (include/hgks.h): problem table, device workspace layout, launch sequence of
+// one S2O4 step (Sec. 2.2 of Mu et al., arXiv 2304.05572), HIP-graph replay, tile autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hgks.h"
+#include "hgks_launch.h"
+
+using namespace hk;
+
+#define HIPOK(x)                                  \
+  do {                                            \
+    hipError_t e_ = (x);                          \
+    if (e_ != hipSuccess) {                       \
+      last_hip_error = e_;                        \
+      return HGKS_EDEVICE;                        \
+    }                                             \
+  } while (0)
+
+static thread_local hipError_t last_hip_error = hipSuccess;
+
+struct hgks {
+  int nprob = 0, dim = 2, fp32 = 0, use_graph = 0, autotune = 0;
+  int tile = 0, tuned = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<hgks_problem> hp;
+  std::vector<ProbDev> pd;
+  std::vector<size_t> off_W, off_Ws, off_S, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_cnt;
+  size_t off_probs = 0, off_ts = 0, off_tab = 0, ws_bytes = 0;
+  char* ws = nullptr;
+  bool own_ws = false, ready = false;
+  std::vector<int> tab_cell, tab_ext, tab_flux[kNumTiles];
+  std::vector<char> ic_set;
+  hipGraphExec_t graph = nullptr;
+  int graph_tile = -1, graph_tend = -1;
+  std::vector<double> last_frac_x, last_frac_y;
+  // optional per-launch HIP-event timing
+  int profile = 0;
+  struct Rec {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> spare;
+  double prof_ms[4] = {0, 0, 0, 0};
+  long prof_n[4] = {0, 0, 0, 0};
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static hgks_status validate(const hgks_problem& p) {
+  if (p.dim != 1 && p.dim != 2) return HGKS_EINVAL;
+  if (p.nx < 5 || (p.dim == 2 && p.ny < 5) || (p.dim == 1 && p.ny != 1)) return HGKS_EINVAL;
+  if (!(p.gamma > 1.0) || !(p.x1 > p.x0) || (p.dim == 2 && !(p.y1 > p.y0))) return HGKS_EINVAL;
+  if (!(p.cfl > 0.0) && !(p.fixed_dt > 0.0)) return HGKS_EINVAL;
+  if (p.eqn != HGKS_EULER && p.eqn != HGKS_NS) return HGKS_EINVAL;
+  if (p.eqn == HGKS_NS && !(p.Pr > 0.0 && p.mu >= 0.0)) return HGKS_EINVAL;
+  if (p.c1 < 0.0 || p.c2 < 0.0 || p.recon < 0 || p.recon > 2 || p.tangential_flag_mode != 0) return HGKS_EINVAL;
+  if (!(p.gamma_hi > 0.0 && p.gamma_hi < 1.0) || !(p.gamma_lo > 0.0 && p.gamma_lo < 1.0) || !(p.weno_eps > 0.0))
+    return HGKS_EINVAL;
+  const int nb = p.dim == 2 ? 4 : 2;
+  for (int s = 0; s < nb; ++s)
+    if (p.bc[s] < 0 || p.bc[s] > 3) return HGKS_EINVAL;
+  for (int s = 0; s < nb; s += 2)
+    if ((p.bc[s] == HGKS_BC_PERIODIC) != (p.bc[s + 1] == HGKS_BC_PERIODIC)) return HGKS_EINVAL;
+  if ((size_t)p.nx * p.ny > (size_t)1 << 30) return HGKS_EINVAL;
+  return HGKS_OK;
+}
+
+static void plan(hgks* h) {
+  size_t o = 0;
+  const size_t ts = h->fp32 ? sizeof(float) : sizeof(double);
+  const int np = h->nprob;
+  h->off_W.resize(np); h->off_Ws.resize(np); h->off_S.resize(np); h->off_flags.resize(np);
+  h->off_Fx.resize(np); h->off_Gx.resize(np); h->off_Fy.resize(np); h->off_Gy.resize(np); h->off_cnt.resize(np);
+  for (int p = 0; p < np; ++p) {
+    const hgks_problem& q = h->hp[p];
+    const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny;
+    const size_t state = nc * nx * ny * sizeof(double);
+    h->off_W[p] = o; o = align256(o + state);
+    h->off_Ws[p] = o; o = align256(o + state);
+    h->off_S[p] = o; o = align256(o + state);
+    h->off_flags[p] = o; o = align256(o + (nx + 4) * (q.dim == 2 ? ny + 4 : 1));
+    h->off_Fx[p] = o; o = align256(o + nc * ny * (nx + 1) * ts);
+    h->off_Gx[p] = o; o = align256(o + nc * ny * (nx + 1) * ts);
+    if (q.dim == 2) {
+      h->off_Fy[p] = o; o = align256(o + nc * (ny + 1) * nx * ts);
+      h->off_Gy[p] = o; o = align256(o + nc * (ny + 1) * nx * ts);
+    } else {
+      h->off_Fy[p] = h->off_Gy[p] = 0;
+    }
+    h->off_cnt[p] = o; o = align256(o + 2 * sizeof(int));
+  }
+  h->off_probs = o; o = align256(o + np * sizeof(ProbDev));
+  h->off_ts = o; o = align256(o + np * sizeof(TimeDev));
+  // tables: cell, ext, and one flux table per tile shape, each nprob+1 ints
+  h->off_tab = o; o = align256(o + (size_t)(2 + kNumTiles) * (np + 1) * sizeof(int));
+  h->ws_bytes = o;
+  // prefix sums
+  h->tab_cell.assign(np + 1, 0);
+  h->tab_ext.assign(np + 1, 0);
+  for (int t = 0; t < kNumTiles; ++t) h->tab_flux[t].assign(np + 1, 0);
+  for (int p = 0; p < np; ++p) {
+    const hgks_problem& q = h->hp[p];
+    const long cells = (long)q.nx * q.ny;
+    const long ext = (long)(q.nx + 4) * (q.dim == 2 ? q.ny + 4 : 1);
+    h->tab_cell[p + 1] = h->tab_cell[p] + (int)((cells + 255) / 256);
+    h->tab_ext[p + 1] = h->tab_ext[p] + (int)((ext + 255) / 256);
+    for (int t = 0; t < kNumTiles; ++t) h->tab_flux[t][p + 1] = h->tab_flux[t][p] + flux_tiles(q.dim, q.nx, q.ny, t);
+  }
+}
+
+static int* tab_ptr(hgks* h, int which) {  // 0 cell, 1 ext, 2+t flux tile t
+  return reinterpret_cast<int*>(h->ws + h->off_tab) + (size_t)which * (h->nprob + 1);
+}
+
+static LaunchCtx ctx(hgks* h) {
+  LaunchCtx L;
+  L.stream = h->stream;
+  L.probs = reinterpret_cast<const ProbDev*>(h->ws + h->off_probs);
+  L.ts = reinterpret_cast<TimeDev*>(h->ws + h->off_ts);
+  L.off_cell = tab_ptr(h, 0);
+  L.off_ext = tab_ptr(h, 1);
+  L.off_flux = tab_ptr(h, 2 + h->tile);
+  L.nprob = h->nprob;
+  L.dim = h->dim;
+  L.fp32 = h->fp32;
+  L.tile = h->tile;
+  L.cell_blocks = h->tab_cell[h->nprob];
+  L.ext_blocks = h->tab_ext[h->nprob];
+  L.flux_blocks = h->tab_flux[h->tile][h->nprob];
+  return L;
+}
+
+static hgks_status materialise(hgks* h) {
+  if (h->ready) return HGKS_OK;
+  if (!h->ws) {
+    void* p = nullptr;
+    HIPOK(hipMalloc(&p, h->ws_bytes));
+    h->ws = static_cast<char*>(p);
+    h->own_ws = true;
+  }
+  HIPOK(hipMemsetAsync(h->ws, 0, h->ws_bytes, h->stream));
+  h->pd.resize(h->nprob);
+  for (int p = 0; p < h->nprob; ++p) {
+    const hgks_problem& q = h->hp[p];
+    ProbDev& d = h->pd[p];
+    std::memset(&d, 0, sizeof d);
+    d.dim = q.dim; d.nx = q.nx; d.ny = q.ny; d.ns = (q.eqn == HGKS_NS);
+    for (int s = 0; s < 4; ++s) d.bc[s] = q.bc[s];
+    d.recon = q.recon; d.zeta1_mode = q.zeta1_mode;
+    d.dx = (q.x1 - q.x0) / q.nx;
+    d.dy = q.dim == 2 ? (q.y1 - q.y0) / q.ny : 1.0;
+    d.h = q.dim == 2 ? std::min(d.dx, d.dy) : d.dx;
+    d.gamma = q.gamma;
+    // internal degrees of freedom of the 2D model (K + 2 = 2/(gamma-1)); a 1D problem runs as the 2D
+    // model with V = 0, which has the same u-moments as the 1D model with K + 1 = 2/(gamma-1)
+    d.K = (4.0 - 2.0 * q.gamma) / (q.gamma - 1.0);
+    d.mu = q.mu; d.Pr = q.Pr; d.c1 = q.c1; d.c2 = q.c2;
+    d.cfl = q.cfl; d.fixed_dt = q.fixed_dt;
+    d.ghi = q.gamma_hi; d.glo = q.gamma_lo; d.eps = q.weno_eps;
+    d.W = reinterpret_cast<double*>(h->ws + h->off_W[p]);
+    d.Ws = reinterpret_cast<double*>(h->ws + h->off_Ws[p]);
+    d.S = reinterpret_cast<double*>(h->ws + h->off_S[p]);
+    d.flags = reinterpret_cast<uint8_t*>(h->ws + h->off_flags[p]);
+    d.Fx = h->ws + h->off_Fx[p];
+    d.Gx = h->ws + h->off_Gx[p];
+    d.Fy = q.dim == 2 ? h->ws + h->off_Fy[p] : nullptr;
+    d.Gy = q.dim == 2 ? h->ws + h->off_Gy[p] : nullptr;
+    d.flag_count = reinterpret_cast<int*>(h->ws + h->off_cnt[p]);
+  }
+  HIPOK(hipMemcpyAsync(h->ws + h->off_probs, h->pd.data(), h->nprob * sizeof(ProbDev), hipMemcpyHostToDevice,
+                       h->stream));
+  std::vector<TimeDev> ts(h->nprob);
+  for (auto& s : ts) {
+    std::memset(&s, 0, sizeof s);
+    s.t_end = INFINITY;
+    s.qmin = 0x7ff0000000000000ull;
+  }
+  HIPOK(hipMemcpyAsync(h->ws + h->off_ts, ts.data(), h->nprob * sizeof(TimeDev), hipMemcpyHostToDevice, h->stream));
+  std::vector<int> tabs((size_t)(2 + kNumTiles) * (h->nprob + 1));
+  std::copy(h->tab_cell.begin(), h->tab_cell.end(), tabs.begin());
+  std::copy(h->tab_ext.begin(), h->tab_ext.end(), tabs.begin() + (h->nprob + 1));
+  for (int t = 0; t < kNumTiles; ++t)
+    std::copy(h->tab_flux[t].begin(), h->tab_flux[t].end(), tabs.begin() + (size_t)(2 + t) * (h->nprob + 1));
+  HIPOK(hipMemcpyAsync(h->ws + h->off_tab, tabs.data(), tabs.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIPOK(hipStreamSynchronize(h->stream));
+  h->ready = true;
+  return HGKS_OK;
+}
+
+static hgks_status read_ts(hgks* h, std::vector<TimeDev>& ts) {
+  ts.resize(h->nprob);
+  HIPOK(hipMemcpyAsync(ts.data(), h->ws + h->off_ts, h->nprob * sizeof(TimeDev), hipMemcpyDeviceToHost, h->stream));
+  HIPOK(hipStreamSynchronize(h->stream));
+  return HGKS_OK;
+}
+
+static hgks_status write_ts(hgks* h, const std::vector<TimeDev>& ts) {
+  HIPOK(hipMemcpyAsync(h->ws + h->off_ts, ts.data(), h->nprob * sizeof(TimeDev), hipMemcpyHostToDevice, h->stream));
+  HIPOK(hipStreamSynchronize(h->stream));
+  return HGKS_OK;
+}
+
+static hipEvent_t take_event(hgks* h) {
+  if (!h->spare.empty()) {
+    hipEvent_t e = h->spare.back();
+    h->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `fn` bracketed by events when profiling (kinds: 0 flux, 1 update, 2 flags, 3 scalar).
+template <typename Fn>
+static void timed(hgks* h, int kind, bool capturing, Fn fn) {
+  if (!h->profile || capturing) {
+    fn();
+    return;
+  }
+  hgks::Rec r{take_event(h), take_event(h), kind};
+  if (r.a) (void)hipEventRecord(r.a, h->stream);
+  fn();
+  if (r.b) (void)hipEventRecord(r.b, h->stream);
+  if (r.a && r.b) h->recs.push_back(r);
+}
+
+static void collect_profile(hgks* h) {
+  for (auto& r : h->recs) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      h->prof_ms[r.kind] += ms;
+      h->prof_n[r.kind] += 1;
+    }
+    h->spare.push_back(r.a);
+    h->spare.push_back(r.b);
+  }
+  h->recs.clear();
+}
+
+// The launches of one S2O4 step (everything stays on the device: dt, t and the CFL minimum).
+static void enqueue_step(hgks* h, int use_tend, bool capturing = false) {
+  const LaunchCtx L = ctx(h);
+  timed(h, 3, capturing, [&] { launch_dt_finalize(L, use_tend); });
+  timed(h, 2, capturing, [&] { launch_flags(L, 0, 1); });
+  timed(h, 0, capturing, [&] { launch_flux(L, 1); });
+  timed(h, 1, capturing, [&] { launch_update(L, 1); });
+  timed(h, 2, capturing, [&] { launch_flags(L, 1, 0); });
+  timed(h, 0, capturing, [&] { launch_flux(L, 2); });
+  timed(h, 1, capturing, [&] { launch_update(L, 2); });
+  timed(h, 3, capturing, [&] { launch_commit(L, use_tend); });
+  if (h->recs.size() > 4096) collect_profile(h);
+}
+
+static std::string tune_key(hgks* h) {
+  std::string k = h->fp32 ? "fp32" : "fp64";
+  k += "_d" + std::to_string(h->dim) + "_n" + std::to_string(h->nprob);
+  size_t cells = 0;
+  for (auto& q : h->hp) cells += (size_t)q.nx * q.ny;
+  k += "_c" + std::to_string(cells) + "_x" + std::to_string(h->hp[0].nx) + "_y" + std::to_string(h->hp[0].ny);
+  return k;
+}
+
+static bool tune_cache_lookup(const std::string& key, int& tile) {
+  const char* path = std::getenv("HGKS_AUTOTUNE_CACHE");
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char kbuf[256];
+  int t;
+  bool found = false;
+  while (std::fscanf(f, "%255s %d", kbuf, &t) == 2)
+    if (key == kbuf && t >= 0 && t < kNumTiles) { tile = t; found = true; }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_store(const std::string& key, int tile) {
+  const char* path = std::getenv("HGKS_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d\n", key.c_str(), tile);
+  std::fclose(f);
+}
+
+// Time the first-stage flux kernel of every tile shape on the current state (dt already set by the
+// step's finalize launch) and keep the fastest.
+static hgks_status autotune(hgks* h) {
+  h->tuned = 1;
+  const std::string key = tune_key(h);
+  int cached;
+  if (tune_cache_lookup(key, cached)) {
+    h->tile = cached;
+    return HGKS_OK;
+  }
+  hipEvent_t e0, e1;
+  HIPOK(hipEventCreate(&e0));
+  HIPOK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_t = h->tile;
+  {
+    LaunchCtx L = ctx(h);
+    launch_flags(L, 0, 0);
+  }
+  for (int t = 0; t < kNumTiles; ++t) {
+    h->tile = t;
+    LaunchCtx L = ctx(h);
+    launch_flux(L, 1);  // warm-up
+    HIPOK(hipEventRecord(e0, h->stream));
+    for (int r = 0; r < 3; ++r) launch_flux(L, 1);
+    HIPOK(hipEventRecord(e1, h->stream));
+    HIPOK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPOK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; best_t = t; }
+  }
+  h->tile = best_t;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tune_cache_store(key, best_t);
+  return HGKS_OK;
+}
+
+static hgks_status status_from(const std::vector<TimeDev>& ts) {
+  for (auto& s : ts) {
+    if (s.status & 1) return HGKS_ENONPHYS;
+    if (s.status & 2) return HGKS_EDT;
+  }
+  return HGKS_OK;
+}
+
+static hgks_status build_graph(hgks* h, int use_tend) {
+  if (h->graph && h->graph_tile == h->tile && h->graph_tend == use_tend) return HGKS_OK;
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  hipGraph_t g;
+  HIPOK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  enqueue_step(h, use_tend, true);
+  HIPOK(hipStreamEndCapture(h->stream, &g));
+  hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    last_hip_error = e;
+    h->graph = nullptr;
+    return HGKS_EDEVICE;
+  }
+  h->graph_tile = h->tile;
+  h->graph_tend = use_tend;
+  return HGKS_OK;
+}
+
+static hgks_status issue_steps(hgks* h, int use_tend, int64_t nsteps) {
+  if (h->autotune && !h->tuned) {
+    // first step: finalize once so that dt is valid, time the tile shapes on this state, then
+    // recompute the CFL minimum the finalize consumed (the state is unchanged) and run the step
+    launch_dt_finalize(ctx(h), use_tend);
+    hgks_status s = autotune(h);
+    if (s) return s;
+    launch_cfl(ctx(h));
+  }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (h->use_graph) {
+      hgks_status s = build_graph(h, use_tend);
+      if (s) return s;
+      HIPOK(hipGraphLaunch(h->graph, h->stream));
+    } else {
+      enqueue_step(h, use_tend);
+    }
+  }
+  HIPOK(hipGetLastError());
+  return HGKS_OK;
+}
+
+extern "C" {
+
+hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opts* opts, hgks_t** out) {
+  if (!probs || nprob < 1 || !out) return HGKS_EINVAL;
+  *out = nullptr;
+  for (int p = 0; p < nprob; ++p) {
+    hgks_status s = validate(probs[p]);
+    if (s) return s;
+    if (probs[p].dim != probs[0].dim) return HGKS_EINVAL;
+  }
+  hgks* h = new (std::nothrow) hgks;
+  if (!h) return HGKS_ENOMEM;
+  h->nprob = nprob;
+  h->dim = probs[0].dim;
+  h->hp.assign(probs, probs + nprob);
+  h->fp32 = opts ? (opts->precision == HGKS_FP32_BULK) : 0;
+  h->use_graph = opts ? opts->use_graph : 0;
+  h->autotune = opts ? opts->autotune : 0;
+  h->profile = opts ? opts->profile : 0;
+  h->tile = (opts && opts->tile >= 0 && opts->tile < kNumTiles) ? opts->tile : 0;
+  if (opts && (opts->precision < 0 || opts->precision > 1)) {
+    delete h;
+    return HGKS_EINVAL;
+  }
+  if (opts && opts->hip_stream) {
+    h->stream = static_cast<hipStream_t>(opts->hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return HGKS_EDEVICE;
+    }
+    h->own_stream = true;
+  }
+  h->ic_set.assign(nprob, 0);
+  h->last_frac_x.assign(nprob, 0.0);
+  h->last_frac_y.assign(nprob, 0.0);
+  plan(h);
+  *out = h;
+  return HGKS_OK;
+}
+
+size_t hgks_workspace_bytes(const hgks_t* h) { return h ? h->ws_bytes : 0; }
+
+hgks_status hgks_bind_workspace(hgks_t* h, void* dev_ptr, size_t bytes) {
+  if (!h || !dev_ptr) return HGKS_EINVAL;
+  if (h->ready || h->ws) return HGKS_EINVAL;
+  if (bytes < h->ws_bytes) return HGKS_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(dev_ptr) & 255) return HGKS_EINVAL;
+  h->ws = static_cast<char*>(dev_ptr);
+  h->own_ws = false;
+  return HGKS_OK;
+}
+
+hgks_status hgks_set_ic(hgks_t* h, int32_t prob, const double* W, int32_t on_device, double t0) {
+  if (!h || !W || prob < 0 || prob >= h->nprob || !std::isfinite(t0)) return HGKS_EINVAL;
+  hgks_status s = materialise(h);
+  if (s) return s;
+  const hgks_problem& q = h->hp[prob];
+  const size_t bytes = (size_t)(q.dim + 2) * q.nx * q.ny * sizeof(double);
+  HIPOK(hipMemcpyAsync(h->ws + h->off_W[prob], W, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       h->stream));
+  std::vector<TimeDev> ts;
+  s = read_ts(h, ts);
+  if (s) return s;
+  ts[prob].t = t0;
+  ts[prob].t_new = t0;
+  ts[prob].t_end = INFINITY;
+  ts[prob].active = 1;
+  ts[prob].status = 0;
+  ts[prob].steps = 0;
+  ts[prob].dt = 0.0;
+  s = write_ts(h, ts);
+  if (s) return s;
+  h->ic_set[prob] = 1;
+  launch_cfl(ctx(h));
+  HIPOK(hipGetLastError());
+  HIPOK(hipStreamSynchronize(h->stream));
+  return HGKS_OK;
+}
+
+static hgks_status require_ic(hgks* h) {
+  for (int p = 0; p < h->nprob; ++p)
+    if (!h->ic_set[p]) return HGKS_EINVAL;
+  return h->ready ? HGKS_OK : HGKS_EINVAL;
+}
+
+hgks_status hgks_step(hgks_t* h, double* dt_taken) {
+  if (!h) return HGKS_EINVAL;
+  hgks_status s = require_ic(h);
+  if (s) return s;
+  std::vector<TimeDev> ts;
+  s = read_ts(h, ts);
+  if (s) return s;
+  s = status_from(ts);
+  if (s) return s;
+  for (auto& x : ts) {
+    x.active = 1;
+    x.t_end = INFINITY;
+  }
+  s = write_ts(h, ts);
+  if (s) return s;
+  s = issue_steps(h, 0, 1);
+  if (s) return s;
+  s = read_ts(h, ts);
+  if (s) return s;
+  if (dt_taken)
+    for (int p = 0; p < h->nprob; ++p) dt_taken[p] = ts[p].dt;
+  return status_from(ts);
+}
+
+hgks_status hgks_run(hgks_t* h, const double* t_end, int64_t max_steps, int64_t* steps_out) {
+  if (!h || !t_end || max_steps < 0) return HGKS_EINVAL;
+  hgks_status s = require_ic(h);
+  if (s) return s;
+  std::vector<TimeDev> ts;
+  s = read_ts(h, ts);
+  if (s) return s;
+  s = status_from(ts);
+  if (s) return s;
+  std::vector<long long> steps0(h->nprob);
+  for (int p = 0; p < h->nprob; ++p) {
+    if (std::isnan(t_end[p])) return HGKS_EINVAL;
+    ts[p].t_end = t_end[p];
+    ts[p].active = ts[p].t < t_end[p] ? 1 : 0;
+    steps0[p] = ts[p].steps;
+  }
+  s = write_ts(h, ts);
+  if (s) return s;
+  int64_t issued = 0;
+  while (issued < max_steps) {
+    bool any = false;
+    for (auto& x : ts) any |= (x.active != 0);
+    if (!any) break;
+    const int64_t chunk = std::min<int64_t>(max_steps - issued, 16);
+    s = issue_steps(h, 1, chunk);
+    if (s) return s;
+    issued += chunk;
+    s = read_ts(h, ts);
+    if (s) return s;
+    s = status_from(ts);
+    if (s) return s;
+  }
+  if (steps_out)
+    for (int p = 0; p < h->nprob; ++p) steps_out[p] = ts[p].steps - steps0[p];
+  return HGKS_OK;
+}
+
+hgks_status hgks_get_state(const hgks_t* hc, int32_t prob, double* W, int32_t on_device, double* t) {
+  hgks* h = const_cast<hgks*>(hc);
+  if (!h || !W || prob < 0 || prob >= h->nprob || !h->ready) return HGKS_EINVAL;
+  const hgks_problem& q = h->hp[prob];
+  const size_t bytes = (size_t)(q.dim + 2) * q.nx * q.ny * sizeof(double);
+  HIPOK(hipMemcpyAsync(W, h->ws + h->off_W[prob], bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                       h->stream));
+  std::vector<TimeDev> ts;
+  hgks_status s = read_ts(h, ts);
+  if (s) return s;
+  if (t) *t = ts[prob].t;
+  return status_from(ts);
+}
+
+hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy) {
+  if (!h || !fx || prob < 0 || prob >= h->nprob) return HGKS_EINVAL;
+  if (!h->ready || !h->ic_set[prob]) return HGKS_EINVAL;
+  std::vector<TimeDev> ts, saved;
+  hgks_status s = read_ts(h, ts);
+  if (s) return s;
+  saved = ts;
+  for (int p = 0; p < h->nprob; ++p) ts[p].active = (p == prob);
+  s = write_ts(h, ts);
+  if (s) return s;
+  launch_flags(ctx(h), 0, 1);
+  HIPOK(hipGetLastError());
+  const hgks_problem& q = h->hp[prob];
+  const size_t ex = q.nx + 4, ey = q.dim == 2 ? q.ny + 4 : 1;
+  std::vector<uint8_t> buf(ex * ey);
+  HIPOK(hipMemcpyAsync(buf.data(), h->ws + h->off_flags[prob], buf.size(), hipMemcpyDeviceToHost, h->stream));
+  int cnt[2];
+  HIPOK(hipMemcpyAsync(cnt, h->ws + h->off_cnt[prob], sizeof cnt, hipMemcpyDeviceToHost, h->stream));
+  s = write_ts(h, saved);
+  if (s) return s;
+  const int jo = q.dim == 2 ? 2 : 0;
+  for (int j = 0; j < q.ny; ++j)
+    for (int i = 0; i < q.nx; ++i) {
+      const uint8_t v = buf[(size_t)(j + jo) * ex + i + 2];
+      fx[(size_t)j * q.nx + i] = v & 1;
+      if (fy && q.dim == 2) fy[(size_t)j * q.nx + i] = (v >> 1) & 1;
+    }
+  const double cells = (double)q.nx * q.ny;
+  h->last_frac_x[prob] = cnt[0] / cells;
+  h->last_frac_y[prob] = cnt[1] / cells;
+  return HGKS_OK;
+}
+
+hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx, double* Fy,
+                                    double* Gy) {
+  if (!h || prob < 0 || prob >= h->nprob || !Fx || !Gx || !(dt > 0.0)) return HGKS_EINVAL;
+  if (!h->ready || !h->ic_set[prob]) return HGKS_EINVAL;
+  const hgks_problem& q = h->hp[prob];
+  if (q.dim == 2 && (!Fy || !Gy)) return HGKS_EINVAL;
+  std::vector<TimeDev> ts, saved;
+  hgks_status s = read_ts(h, ts);
+  if (s) return s;
+  saved = ts;
+  for (int p = 0; p < h->nprob; ++p) {
+    ts[p].active = (p == prob);
+    ts[p].dt = dt;
+  }
+  s = write_ts(h, ts);
+  if (s) return s;
+  LaunchCtx L = ctx(h);
+  launch_flags(L, 0, 0);
+  launch_flux(L, 1);
+  HIPOK(hipGetLastError());
+  const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny;
+  const size_t nxf = nc * ny * (nx + 1), nyf = q.dim == 2 ? nc * (ny + 1) * nx : 0;
+  auto fetch = [&](size_t off, size_t n, double* dst) -> hgks_status {
+    if (h->fp32) {
+      std::vector<float> tmp(n);
+      HIPOK(hipMemcpyAsync(tmp.data(), h->ws + off, n * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+      HIPOK(hipStreamSynchronize(h->stream));
+      for (size_t k = 0; k < n; ++k) dst[k] = tmp[k];
+    } else {
+      HIPOK(hipMemcpyAsync(dst, h->ws + off, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIPOK(hipStreamSynchronize(h->stream));
+    }
+    return HGKS_OK;
+  };
+  if ((s = fetch(h->off_Fx[prob], nxf, Fx))) return s;
+  if ((s = fetch(h->off_Gx[prob], nxf, Gx))) return s;
+  if (q.dim == 2) {
+    if ((s = fetch(h->off_Fy[prob], nyf, Fy))) return s;
+    if ((s = fetch(h->off_Gy[prob], nyf, Gy))) return s;
+  }
+  return write_ts(h, saved);
+}
+
+hgks_status hgks_get_stats(const hgks_t* hc, int32_t prob, double* out) {
+  hgks* h = const_cast<hgks*>(hc);
+  if (!h || !out || prob < 0 || prob >= h->nprob || !h->ready) return HGKS_EINVAL;
+  std::vector<TimeDev> ts;
+  hgks_status s = read_ts(h, ts);
+  if (s) return s;
+  int cnt[2];
+  HIPOK(hipMemcpy(cnt, h->ws + h->off_cnt[prob], sizeof cnt, hipMemcpyDeviceToHost));
+  const hgks_problem& q = h->hp[prob];
+  const double cells = (double)q.nx * q.ny;
+  out[0] = (double)ts[prob].steps;
+  out[1] = cells;
+  out[2] = ts[prob].t;
+  out[3] = ts[prob].dt;
+  out[4] = cnt[0] / cells;
+  out[5] = cnt[1] / cells;
+  return HGKS_OK;
+}
+
+hgks_status hgks_get_profile(hgks_t* h, double* out) {
+  if (!h || !out) return HGKS_EINVAL;
+  if (h->stream) HIPOK(hipStreamSynchronize(h->stream));
+  collect_profile(h);
+  for (int k = 0; k < 4; ++k) {
+    out[2 * k] = h->prof_ms[k];
+    out[2 * k + 1] = (double)h->prof_n[k];
+  }
+  return HGKS_OK;
+}
+
+hgks_status hgks_get_tile(const hgks_t* h, int32_t* tn, int32_t* tt) {
+  if (!h || !tn || !tt) return HGKS_EINVAL;
+  *tn = kTiles[h->tile].tn;
+  *tt = kTiles[h->tile].tt;
+  return HGKS_OK;
+}
+
+void hgks_destroy(hgks_t* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  collect_profile(h);
+  for (auto e : h->spare) (void)hipEventDestroy(e);
+  if (h->own_ws && h->ws) (void)hipFree(h->ws);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+const char* hgks_status_str(hgks_status s) {
+  switch (s) {
+    case HGKS_OK: return "ok";
+    case HGKS_EINVAL: return "invalid argument";
+    case HGKS_ENOMEM: return "out of memory or workspace too small";
+    case HGKS_EDEVICE: return "HIP runtime error";
+    case HGKS_ENONPHYS: return "non-physical state (rho <= 0, p <= 0 or NaN)";
+    case HGKS_EDT: return "time step <= 0 or not finite";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

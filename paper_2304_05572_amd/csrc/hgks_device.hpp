@@ -1,0 +1,564 @@
+// Device-side arithmetic of the hybrid WENO5-AO gas-kinetic scheme (Mu et al., arXiv 2304.05572),
+// written for CDNA4 (gfx950): one thread evaluates one interface, everything in registers except the
+// LDS-staged stencil tiles owned by the kernels. Templated on the bulk precision T (double for the
+// FP64 path, float for the FP32-bulk path); the troubled-cell discriminant, the CFL quantity and the
+// time-integration coefficients are always FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hk {
+
+// ---------------------------------------------------------------------------------------------
+// Per-problem description and time state (device copies)
+// ---------------------------------------------------------------------------------------------
+struct ProbDev {
+  int dim, nx, ny, ns;
+  int bc[4];
+  int recon, zeta1_mode;
+  double dx, dy, h;          // cell sizes; h = min(dx, dy) for the CFL step
+  double gamma, K, mu, Pr, c1, c2;  // K: internal dof of the 2D model (1D problems embed into it)
+  double cfl, fixed_dt;
+  double ghi, glo, eps;
+  double* W;                 // state W^n        [nc][ny][nx]
+  double* Ws;                // stage state W*   [nc][ny][nx]
+  double* S;                 // partial sum W^n - dt L^n - dt^2/6 L_t^n
+  uint8_t* flags;            // [(ny+4)][(nx+4)] (2D) / [nx+4] (1D): bit 0 x-flag, bit 1 y-flag
+  void* Fx;                  // x-interfaces [4][ny][nx+1]: F (stage 1) / unused (stage 2)
+  void* Gx;                  // x-interfaces: dF/dt
+  void* Fy;                  // y-interfaces [4][ny+1][nx]
+  void* Gy;
+  int* flag_count;           // [2] troubled cells counted at the last flag evaluation
+};
+
+struct TimeDev {
+  double dt, t, t_new, t_end;
+  unsigned long long qmin;   // bit pattern of the positive FP64 minimum of the CFL quantity
+  int active;                // 1 while t < t_end
+  int status;                // sticky: 1 when a non-physical state appeared
+  long long steps;
+};
+
+// ---------------------------------------------------------------------------------------------
+// Boundary conditions: index of the interior cell a (ghost) index reads, and velocity sign flips
+// ---------------------------------------------------------------------------------------------
+__host__ __device__ inline int bc_index(int i, int n, int lo, int hi, int& flip) {
+  flip = 0;
+  if (i >= 0 && i < n) return i;
+  const int bc = (i < 0) ? lo : hi;
+  if (bc == 0) {  // periodic
+    int r = i % n;
+    return r < 0 ? r + n : r;
+  }
+  if (bc == 1) return (i < 0) ? 0 : n - 1;  // zero-gradient
+  flip = (bc == 2) ? 1 : 3;                  // 1: normal velocity, 3: both (no-slip)
+  int m = (i < 0) ? -1 - i : 2 * n - 1 - i;  // mirror about the wall face
+  return m < 0 ? 0 : (m >= n ? n - 1 : m);
+}
+
+// Cell (i, j) of state W with ghost synthesis; returns (rho, rho U, rho V, rho E) (rho V = 0 in 1D).
+__device__ inline void load_cell(const ProbDev& P, const double* __restrict__ W, int i, int j, double q[4]) {
+  int fx, fy = 0;
+  const int ii = bc_index(i, P.nx, P.bc[0], P.bc[1], fx);
+  const int jj = (P.dim == 2) ? bc_index(j, P.ny, P.bc[2], P.bc[3], fy) : 0;
+  const size_t plane = (size_t)P.nx * P.ny;
+  const size_t o = (size_t)jj * P.nx + ii;
+  q[0] = W[o];
+  q[1] = W[plane + o];
+  if (P.dim == 2) {
+    q[2] = W[2 * plane + o];
+    q[3] = W[3 * plane + o];
+  } else {
+    q[2] = 0.0;
+    q[3] = W[2 * plane + o];
+  }
+  const int negu = (fx & 1) ^ ((fy >> 1) & 1);  // x-walls flip U (and V if no-slip), y-walls the reverse
+  const int negv = ((fx >> 1) & 1) ^ (fy & 1);
+  if (negu) q[1] = -q[1];
+  if (negv) q[2] = -q[2];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Troubled-cell indicator, Sec. 2.3.1 Steps 1-3 (FP64, fixed expression tree, no contraction).
+// D1 = 10 a1 dx and D2 = 34 a2 dx^2 of the least-squares quadratic on the five cells; Step 1 smooth
+// if |D2| <= 5h (normalised reading of zeta1 = 5/17 dx); Step 2 smooth if the extreme point
+// xbar = -17 D1 / (10 D2) lies outside [-5/2, 5/2]; Step 3 smooth if it is within 1/4 of the
+// extreme point of the conservative quadratic on the three central cells.
+// ---------------------------------------------------------------------------------------------
+__device__ __attribute__((noinline)) int troubled5(double Qm2, double Qm1, double Q0, double Qp1, double Qp2,
+                                                   double thr) {
+#pragma clang fp contract(off)
+  const double D1 = (Qp1 - Qm1) + 2.0 * (Qp2 - Qm2);
+  const double D2 = (4.0 * (Qm2 + Qp2) + (Qm1 + Qp1)) - 10.0 * Q0;
+  if (fabs(D2) <= thr) return 0;
+  const double xbar = -(17.0 * D1) / (10.0 * D2);
+  if (fabs(xbar) > 2.5) return 0;
+  const double a1h = 0.5 * (Qp1 - Qm1);
+  const double a2h = 0.5 * ((Qm1 + Qp1) - 2.0 * Q0);
+  const double den = 2.0 * a2h + (a2h == 0.0 ? 1e-30 : 0.0);
+  const double xhat = -a1h / den;
+  return fabs(xbar - xhat) <= 0.25 ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Precision helpers
+// ---------------------------------------------------------------------------------------------
+template <typename T> __device__ inline T dsqrt(T x);
+template <> __device__ inline double dsqrt<double>(double x) { return sqrt(x); }
+template <> __device__ inline float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <typename T> __device__ inline T dexp(T x);
+template <> __device__ inline double dexp<double>(double x) { return exp(x); }
+template <> __device__ inline float dexp<float>(float x) { return __expf(x); }
+template <typename T> __device__ inline T derfc(T x);
+template <> __device__ inline double derfc<double>(double x) { return erfc(x); }
+template <> __device__ inline float derfc<float>(float x) { return erfcf(x); }
+// reciprocal: IEEE in FP64, the hardware approximation (1 ulp) in FP32
+template <typename T> __device__ inline T drcp(T x);
+template <> __device__ inline double drcp<double>(double x) { return 1.0 / x; }
+template <> __device__ inline float drcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ---------------------------------------------------------------------------------------------
+// Reconstruction (Sec. 2.3.1): WENO-AO(5,3) from sub-stencil values/derivatives and smoothness
+// indicators. q[0..4] are the averages of cells -2..2 about the reconstructing cell; derivatives are
+// with respect to the normalised coordinate xi = (x - x_i)/h.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__device__ inline void smoothness(const T q[5], T beta[4]) {
+  const T d0 = q[0] - 2 * q[1] + q[2], e0 = q[0] - 4 * q[1] + 3 * q[2];
+  const T d1 = q[1] - 2 * q[2] + q[3], e1 = q[1] - q[3];
+  const T d2 = q[2] - 2 * q[3] + q[4], e2 = 3 * q[2] - 4 * q[3] + q[4];
+  beta[0] = T(13.0 / 12.0) * d0 * d0 + T(0.25) * e0 * e0;
+  beta[1] = T(13.0 / 12.0) * d1 * d1 + T(0.25) * e1 * e1;
+  beta[2] = T(13.0 / 12.0) * d2 * d2 + T(0.25) * e2 * e2;
+  // quartic: Legendre-like coefficients of the cell-average interpolant
+  const T u1 = (T(11) * (q[0] - q[4]) + T(82) * (q[3] - q[1])) * T(1.0 / 120.0);
+  const T u2 = (T(-3) * (q[0] + q[4]) + T(40) * (q[1] + q[3]) - T(74) * q[2]) * T(1.0 / 56.0);
+  const T u3 = (-q[0] + 2 * q[1] - 2 * q[3] + q[4]) * T(1.0 / 12.0);
+  const T u4 = (q[0] - 4 * q[1] + 6 * q[2] - 4 * q[3] + q[4]) * T(1.0 / 24.0);
+  const T s1 = u1 + T(0.1) * u3, s2 = u2 + T(123.0 / 455.0) * u4;
+  beta[3] = s1 * s1 + T(13.0 / 3.0) * s2 * s2 + T(781.0 / 20.0) * u3 * u3 + T(1421461.0 / 2275.0) * u4 * u4;
+}
+
+// Nonlinear AO weights -> combine sub-polynomial values pv and derivatives pd (same weights).
+template <typename T>
+__device__ inline void ao_combine(const T beta[4], const T pv[4], const T pd[4], T ghi, T glo, T eps, T& v,
+                                  T& d) {
+  const T g3 = ghi, g0 = (1 - ghi) * (1 - glo) * T(0.5), g1 = (1 - ghi) * glo;
+  const T del = (fabs(beta[3] - beta[0]) + fabs(beta[3] - beta[1]) + fabs(beta[3] - beta[2])) * T(1.0 / 3.0);
+  const T w0 = g0 * (1 + del * drcp(beta[0] + eps));
+  const T w1 = g1 * (1 + del * drcp(beta[1] + eps));
+  const T w2 = g0 * (1 + del * drcp(beta[2] + eps));
+  const T w3 = g3 * (1 + del * drcp(beta[3] + eps));
+  const T inv = drcp(w0 + w1 + w2 + w3);
+  const T r3 = w3 * inv * drcp(g3);
+  v = r3 * (pv[3] - g0 * pv[0] - g1 * pv[1] - g0 * pv[2]) + inv * (w0 * pv[0] + w1 * pv[1] + w2 * pv[2]);
+  d = r3 * (pd[3] - g0 * pd[0] - g1 * pd[1] - g0 * pd[2]) + inv * (w0 * pd[0] + w1 * pd[1] + w2 * pd[2]);
+}
+
+// Sub-stencil values/derivatives at the cell faces xi = +1/2 (side = 0, left state of the interface to
+// the right of the cell) and xi = -1/2 (side = 1).
+template <typename T>
+__device__ inline void face_polys(const T q[5], int side, T pv[4], T pd[4]) {
+  if (side == 0) {
+    pv[0] = T(1.0 / 3.0) * q[0] - T(7.0 / 6.0) * q[1] + T(11.0 / 6.0) * q[2];
+    pv[1] = T(-1.0 / 6.0) * q[1] + T(5.0 / 6.0) * q[2] + T(1.0 / 3.0) * q[3];
+    pv[2] = T(1.0 / 3.0) * q[2] + T(5.0 / 6.0) * q[3] - T(1.0 / 6.0) * q[4];
+    pv[3] = (T(2) * q[0] - T(13) * q[1] + T(47) * q[2] + T(27) * q[3] - T(3) * q[4]) * T(1.0 / 60.0);
+    pd[0] = q[0] - T(3) * q[1] + T(2) * q[2];
+    pd[1] = q[3] - q[2];
+    pd[2] = q[3] - q[2];
+    pd[3] = (q[1] - T(15) * q[2] + T(15) * q[3] - q[4]) * T(1.0 / 12.0);
+  } else {
+    pv[0] = T(-1.0 / 6.0) * q[0] + T(5.0 / 6.0) * q[1] + T(1.0 / 3.0) * q[2];
+    pv[1] = T(1.0 / 3.0) * q[1] + T(5.0 / 6.0) * q[2] - T(1.0 / 6.0) * q[3];
+    pv[2] = T(11.0 / 6.0) * q[2] - T(7.0 / 6.0) * q[3] + T(1.0 / 3.0) * q[4];
+    pv[3] = (T(-3) * q[0] + T(27) * q[1] + T(47) * q[2] - T(13) * q[3] + T(2) * q[4]) * T(1.0 / 60.0);
+    pd[0] = q[2] - q[1];
+    pd[1] = q[2] - q[1];
+    pd[2] = T(-2) * q[2] + T(3) * q[3] - q[4];
+    pd[3] = (q[0] - T(15) * q[1] + T(15) * q[2] - q[3]) * T(1.0 / 12.0);
+  }
+}
+
+// Sub-stencil values/derivatives at the Gauss points xi = -1/(2 sqrt 3) (gp = 0) and +1/(2 sqrt 3)
+// (gp = 1). Coefficients derived from the cell-average interpolants; gp = 0 is the mirror image.
+#define S3 1.7320508075688772935
+template <typename T>
+__device__ inline void gauss_polys(const T q[5], int gp, T pv[4], T pd[4]) {
+  // stencil seen in the +eta orientation
+  T a0, a1, a2, a3, a4;
+  if (gp == 1) { a0 = q[0]; a1 = q[1]; a2 = q[2]; a3 = q[3]; a4 = q[4]; }
+  else { a0 = q[4]; a1 = q[3]; a2 = q[2]; a3 = q[1]; a4 = q[0]; }
+  // p0 on (a0,a1,a2), p1 on (a1,a2,a3), p2 on (a2,a3,a4), quartic on all five, at eta = +1/(2 sqrt 3)
+  pv[0] = T(S3 / 12) * a0 - T(S3 / 3) * a1 + T(1 + S3 / 4) * a2;
+  pv[1] = T(-S3 / 12) * a1 + a2 + T(S3 / 12) * a3;
+  pv[2] = T(1 - S3 / 4) * a2 + T(S3 / 3) * a3 - T(S3 / 12) * a4;
+  pv[3] = T(-1.0 / 4320 + 7 * S3 / 432) * a0 + T(1.0 / 1080 - 25 * S3 / 216) * a1 + T(719.0 / 720) * a2 +
+          T(1.0 / 1080 + 25 * S3 / 216) * a3 + T(-1.0 / 4320 - 7 * S3 / 432) * a4;
+  pd[0] = T(0.5 + S3 / 6) * a0 + T(-2 - S3 / 3) * a1 + T(1.5 + S3 / 6) * a2;
+  pd[1] = T(-0.5 + S3 / 6) * a1 + T(-S3 / 3) * a2 + T(0.5 + S3 / 6) * a3;
+  pd[2] = T(-1.5 + S3 / 6) * a2 + T(2 - S3 / 3) * a3 + T(-0.5 + S3 / 6) * a4;
+  pd[3] = T(1.0 / 12 - S3 / 54) * a0 + T(-2.0 / 3 + 13 * S3 / 54) * a1 + T(-4 * S3 / 9) * a2 +
+          T(2.0 / 3 + 13 * S3 / 54) * a3 + T(-1.0 / 12 - S3 / 54) * a4;
+  if (gp == 0) {  // mirrored stencil: p0 <-> p2 and derivatives change sign
+    T t = pv[0]; pv[0] = pv[2]; pv[2] = t;
+    t = pd[0]; pd[0] = -pd[2]; pd[2] = -t;
+    pd[1] = -pd[1];
+    pd[3] = -pd[3];
+  }
+}
+
+// Linear fifth-order (quartic) value only at a Gauss point, and its derivative.
+template <typename T>
+__device__ inline void gauss_linear(const T q[5], int gp, T& v, T& d) {
+  T a0, a1, a2, a3, a4;
+  if (gp == 1) { a0 = q[0]; a1 = q[1]; a2 = q[2]; a3 = q[3]; a4 = q[4]; }
+  else { a0 = q[4]; a1 = q[3]; a2 = q[2]; a3 = q[1]; a4 = q[0]; }
+  v = T(-1.0 / 4320 + 7 * S3 / 432) * a0 + T(1.0 / 1080 - 25 * S3 / 216) * a1 + T(719.0 / 720) * a2 +
+      T(1.0 / 1080 + 25 * S3 / 216) * a3 + T(-1.0 / 4320 - 7 * S3 / 432) * a4;
+  d = T(1.0 / 12 - S3 / 54) * a0 + T(-2.0 / 3 + 13 * S3 / 54) * a1 + T(-4 * S3 / 9) * a2 +
+      T(2.0 / 3 + 13 * S3 / 54) * a3 + T(-1.0 / 12 - S3 / 54) * a4;
+  if (gp == 0) d = -d;
+}
+#undef S3
+
+// ---------------------------------------------------------------------------------------------
+// Characteristic variables (Sec. 2.3.1): right eigenvectors R of the Euler flux Jacobian along the
+// direction whose momentum sits in slot `nslot` (1 or 2; the other velocity slot is tangential),
+// columns ordered u_n - c, u_n (entropy), u_n (shear), u_n + c; L = R^{-1} in closed form.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+struct CharMat {
+  T R[4][4], L[4][4];
+};
+
+template <typename T>
+__device__ inline void char_matrices(const T w[4], T gamma, int nslot, CharMat<T>& m) {
+  const int tslot = 3 - nslot;
+  const T ir = drcp(w[0]);
+  const T u[3] = {T(0), w[1] * ir, w[2] * ir};
+  const T un = u[nslot], ut = u[tslot];
+  const T q2 = u[1] * u[1] + u[2] * u[2];
+  const T p = (gamma - 1) * (w[3] - T(0.5) * w[0] * q2);
+  const T c = dsqrt(gamma * p * ir);
+  const T ic = drcp(c);
+  const T H = (w[3] + p) * ir;
+  const T b1 = (gamma - 1) * ic * ic, b2 = T(0.5) * q2 * b1;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) { m.R[a][b] = 0; m.L[a][b] = 0; }
+  m.R[0][0] = 1; m.R[nslot][0] = un - c; m.R[tslot][0] = ut; m.R[3][0] = H - un * c;
+  m.R[0][1] = 1; m.R[nslot][1] = un;     m.R[tslot][1] = ut; m.R[3][1] = T(0.5) * q2;
+  m.R[tslot][2] = 1; m.R[3][2] = ut;
+  m.R[0][3] = 1; m.R[nslot][3] = un + c; m.R[tslot][3] = ut; m.R[3][3] = H + un * c;
+  m.L[0][0] = T(0.5) * (b2 + un * ic); m.L[0][nslot] = T(-0.5) * (b1 * un + ic); m.L[0][tslot] = T(-0.5) * b1 * ut; m.L[0][3] = T(0.5) * b1;
+  m.L[1][0] = 1 - b2;                 m.L[1][nslot] = b1 * un;                  m.L[1][tslot] = b1 * ut;            m.L[1][3] = -b1;
+  m.L[2][0] = -ut;                                                              m.L[2][tslot] = 1;
+  m.L[3][0] = T(0.5) * (b2 - un * ic); m.L[3][nslot] = T(-0.5) * (b1 * un - ic); m.L[3][tslot] = T(-0.5) * b1 * ut; m.L[3][3] = T(0.5) * b1;
+}
+
+// WENO-AO of a vector (4 conserved variables) in characteristic space; `ev` chooses the evaluation:
+// ev 0/1: face xi = +1/2 / -1/2, ev 2/3: Gauss point -eta / +eta. Returns value and xi-derivative.
+template <typename T>
+__device__ inline void ao_vector(const T qc[5][4], const CharMat<T>& m, int ev, T ghi, T glo, T eps, T val[4],
+                                 T der[4]) {
+  T cv[4], cd[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T q[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+      q[r] = m.L[k][0] * qc[r][0] + m.L[k][1] * qc[r][1] + m.L[k][2] * qc[r][2] + m.L[k][3] * qc[r][3];
+    T beta[4], pv[4], pd[4];
+    smoothness(q, beta);
+    if (ev < 2) face_polys(q, ev, pv, pd);
+    else gauss_polys(q, ev - 2, pv, pd);
+    ao_combine(beta, pv, pd, ghi, glo, eps, cv[k], cd[k]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    val[a] = m.R[a][0] * cv[0] + m.R[a][1] * cv[1] + m.R[a][2] * cv[2] + m.R[a][3] * cv[3];
+    der[a] = m.R[a][0] * cd[0] + m.R[a][1] * cd[1] + m.R[a][2] * cd[2] + m.R[a][3] * cd[3];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kinetic part (Sec. 2.1). Moments of the normalised Maxwellian: <u^n> from the Gaussian recurrence
+// (full line, or the half line u > 0 / u < 0 started from erfc and exp), <v^n>, <xi^2k>.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+struct Maxw {
+  T rho, U, V, lam;
+  T Mu[7];  // <u^n>, n <= 6, over the full line or a half line
+  T Mv[6];  // <v^n>, n <= 5
+  T X1, X2; // <xi^2>, <xi^4>
+};
+
+template <typename T>
+__device__ inline void maxw_prims(const T w[4], T gamma, Maxw<T>& g) {
+  g.rho = w[0];
+  const T ir = drcp(w[0]);
+  g.U = w[1] * ir;
+  g.V = w[2] * ir;
+  const T p = (gamma - 1) * (w[3] - T(0.5) * w[0] * (g.U * g.U + g.V * g.V));
+  g.lam = T(0.5) * w[0] * drcp(p);
+}
+
+// Full-line moments in u (half = 0) or half-line moments (half = +1: u > 0, -1: u < 0).
+template <typename T>
+__device__ inline void maxw_moments(Maxw<T>& g, T K, int half) {
+  const T s = T(0.5) * drcp(g.lam);  // 1/(2 lam)
+  if (half == 0) {
+    g.Mu[0] = 1;
+    g.Mu[1] = g.U;
+  } else {
+    const T sl = dsqrt(g.lam);
+    const T hs = T(half);
+    g.Mu[0] = T(0.5) * derfc(-hs * sl * g.U);
+    g.Mu[1] = g.U * g.Mu[0] + hs * T(0.5) * dexp(-g.lam * g.U * g.U) * drcp(sl * T(1.7724538509055160273));
+  }
+#pragma unroll
+  for (int n = 0; n < 5; ++n) g.Mu[n + 2] = g.U * g.Mu[n + 1] + T(n + 1) * s * g.Mu[n];
+  g.Mv[0] = 1;
+  g.Mv[1] = g.V;
+#pragma unroll
+  for (int n = 0; n < 4; ++n) g.Mv[n + 2] = g.V * g.Mv[n + 1] + T(n + 1) * s * g.Mv[n];
+  g.X1 = K * s;
+  g.X2 = K * (K + 2) * s * s;
+}
+
+// <u^n v^m a psi> for a = a0 + a1 u + a2 v + a3 (u^2 + v^2 + xi^2)/2 (n, m compile-time), using
+// <u^n v^m> = Mu[n] Mv[m], <.. psi_4> and <.. psi_4^2> expanded through <xi^2>, <xi^4>.
+template <int N, int M, typename T>
+__device__ inline void mom_a(const Maxw<T>& g, const T a[4], T out[4]) {
+#define G(n, m) (g.Mu[n] * g.Mv[m])
+#define SS(n, m) (T(0.5) * (G((n) + 2, m) + G(n, (m) + 2) + G(n, m) * g.X1))
+  const T S00 = SS(N, M), S10 = SS(N + 1, M), S01 = SS(N, M + 1);
+  const T TT = T(0.25) * (G(N + 4, M) + G(N, M + 4) + G(N, M) * g.X2 +
+                          T(2) * (G(N + 2, M + 2) + (G(N + 2, M) + G(N, M + 2)) * g.X1));
+  out[0] = a[0] * G(N, M) + a[1] * G(N + 1, M) + a[2] * G(N, M + 1) + a[3] * S00;
+  out[1] = a[0] * G(N + 1, M) + a[1] * G(N + 2, M) + a[2] * G(N + 1, M + 1) + a[3] * S10;
+  out[2] = a[0] * G(N, M + 1) + a[1] * G(N + 1, M + 1) + a[2] * G(N, M + 2) + a[3] * S01;
+  out[3] = a[0] * S00 + a[1] * S10 + a[2] * S01 + a[3] * TT;
+#undef SS
+#undef G
+}
+
+// <u^n v^m psi> (a = (1, 0, 0, 0)).
+template <int N, int M, typename T>
+__device__ inline void mom_psi(const Maxw<T>& g, T out[4]) {
+  out[0] = g.Mu[N] * g.Mv[M];
+  out[1] = g.Mu[N + 1] * g.Mv[M];
+  out[2] = g.Mu[N] * g.Mv[M + 1];
+  out[3] = T(0.5) * (g.Mu[N + 2] * g.Mv[M] + g.Mu[N] * g.Mv[M + 2] + g.Mu[N] * g.Mv[M] * g.X1);
+}
+
+// Microscopic slope a with <a psi> = b (closed-form inverse of the 4x4 moment matrix of g).
+template <typename T>
+__device__ inline void solve_slope(const Maxw<T>& g, T Kp2, const T b[4], T a[4]) {
+  const T U = g.U, V = g.V, l = g.lam;
+  const T q2 = U * U + V * V;
+  const T ni = Kp2 * T(0.5) * drcp(l);  // (K+2)/(2 lam)
+  a[3] = T(4) * l * l * drcp(Kp2) * (T(2) * b[3] - T(2) * U * b[1] - T(2) * V * b[2] + (q2 - ni) * b[0]);
+  a[2] = T(2) * l * (b[2] - V * b[0]) - V * a[3];
+  a[1] = T(2) * l * (b[1] - U * b[0]) - U * a[3];
+  a[0] = b[0] - U * a[1] - V * a[2] - T(0.5) * a[3] * (q2 + ni);
+}
+
+// Time integrals over [0, delta] of the five coefficient functions of Eq. (equ10) (FP64):
+// 1 - e, (t+tau) e - tau, t - tau + tau e, e, (t+tau) e with e = exp(-t/tau); series below delta/tau = 1.
+__device__ inline void time_integrals(double d, double tau, double C[5]) {
+  if (tau == 0.0) {
+    C[0] = d; C[1] = 0.0; C[2] = 0.5 * d * d; C[3] = 0.0; C[4] = 0.0;
+    return;
+  }
+  const double x = d / tau;
+  if (x < 1.0) {
+    // sum_k (-1)^k x^k/k! weighted per coefficient, Horner-free accumulation of 24 terms
+    double tk = 1.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+    for (int k = 1; k <= 24; ++k) {
+      tk *= x / k;
+      const double sg = (k & 1) ? -tk : tk;
+      if (k >= 2) s1 += sg;
+      if (k >= 3) { s2 += (k - 2) * sg; s3 -= sg; }
+      s4 -= sg;
+    }
+    C[0] = tau * s1; C[1] = tau * tau * s2; C[2] = tau * tau * s3; C[3] = tau * s4; C[4] = tau * tau * (x + s2);
+    return;
+  }
+  const double e = exp(-x);
+  C[0] = d - tau * (1.0 - e);
+  C[1] = 2.0 * tau * tau - tau * d - tau * (d + 2.0 * tau) * e;
+  C[2] = 0.5 * d * d - tau * d + tau * tau * (1.0 - e);
+  C[3] = tau * (1.0 - e);
+  C[4] = 2.0 * tau * tau - tau * (2.0 * tau + d) * e;
+}
+
+struct FluxParams {
+  double gamma, K, mu, Pr, c1, c2, dt;
+  int ns;
+  int want_F;  // 0: only dF/dt (second stage)
+};
+
+// Gas-kinetic flux at one Gauss point in the local frame (slot 1 = normal momentum): from the
+// reconstructed states W^{l,r} and their normal (x) and tangential (y) derivatives, accumulate
+// wgt * F and wgt * dF/dt (Sec. 2.1-2.2, equilibrium state Eq. (equ46)-(equ47)).
+template <typename T>
+__device__ inline void gks_flux_gp(const T Wl[4], const T Wxl[4], const T Wyl[4], const T Wr[4], const T Wxr[4],
+                                   const T Wyr[4], const FluxParams& fp, T wgt, T F[4], T dF[4]) {
+  const T gamma = T(fp.gamma), K = T(fp.K), Kp2 = K + T(2);
+  T Wc[4] = {0, 0, 0, 0}, Wxc[4] = {0, 0, 0, 0}, Wyc[4] = {0, 0, 0, 0};
+  T M4a[4] = {0, 0, 0, 0}, M4b[4] = {0, 0, 0, 0}, M5[4] = {0, 0, 0, 0};
+  T N4b[4] = {0, 0, 0, 0}, N5[4] = {0, 0, 0, 0};  // heat-flux (Prandtl) moments
+  const bool prfix = fp.ns && fp.Pr != 1.0;
+  T p_side[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const T* W = s ? Wr : Wl;
+    const T* Wx = s ? Wxr : Wxl;
+    const T* Wy = s ? Wyr : Wyl;
+    Maxw<T> g;
+    maxw_prims(W, gamma, g);
+    p_side[s] = T(0.5) * g.rho * drcp(g.lam);
+    const T ir = drcp(g.rho);
+    T b[4], ax[4], ay[4], A[4], t1[4], t2[4];
+    // full-line moments: slopes and the compatibility condition <a1 u + a2 v + A> = 0
+    maxw_moments(g, K, 0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = Wx[c] * ir;
+    solve_slope(g, Kp2, b, ax);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = Wy[c] * ir;
+    solve_slope(g, Kp2, b, ay);
+    mom_a<1, 0>(g, ax, t1);
+    mom_a<0, 1>(g, ay, t2);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = -(t1[c] + t2[c]);
+    solve_slope(g, Kp2, b, A);
+    // half-line moments: g_l over u > 0, g_r over u < 0
+    maxw_moments(g, K, s ? -1 : 1);
+    const T rho = g.rho;
+    mom_psi<0, 0>(g, t1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Wc[c] += rho * t1[c];
+    mom_a<0, 0>(g, ax, t1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Wxc[c] += rho * t1[c];
+    mom_a<0, 0>(g, ay, t1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Wyc[c] += rho * t1[c];
+    mom_psi<1, 0>(g, t1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) M4a[c] += rho * t1[c];
+    mom_a<1, 0>(g, A, t1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) M4b[c] += rho * t1[c];
+    mom_a<2, 0>(g, ax, t1);
+    mom_a<1, 1>(g, ay, t2);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) M5[c] += rho * (t1[c] + t2[c]);
+    if (prfix) {
+      mom_a<0, 0>(g, A, t1);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) N4b[c] += rho * t1[c];
+      mom_a<1, 0>(g, ax, t1);
+      mom_a<0, 1>(g, ay, t2);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) N5[c] += rho * (t1[c] + t2[c]);
+    }
+  }
+  // equilibrium g0 at the interface and its slopes
+  Maxw<T> g0;
+  maxw_prims(Wc, gamma, g0);
+  maxw_moments(g0, K, 0);
+  const T ir0 = drcp(g0.rho);
+  T b[4], a0[4], b0[4], A0[4], t1[4], t2[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) b[c] = Wxc[c] * ir0;
+  solve_slope(g0, Kp2, b, a0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) b[c] = Wyc[c] * ir0;
+  solve_slope(g0, Kp2, b, b0);
+  mom_a<1, 0>(g0, a0, t1);
+  mom_a<0, 1>(g0, b0, t2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) b[c] = -(t1[c] + t2[c]);  // = <(a0 u + b0 v) psi> with the opposite sign
+  solve_slope(g0, Kp2, b, A0);
+  T M1[4], M2[4], M3[4];
+  mom_psi<1, 0>(g0, M1);
+  mom_a<2, 0>(g0, a0, t1);
+  mom_a<1, 1>(g0, b0, t2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    M1[c] *= g0.rho;
+    M2[c] = g0.rho * (t1[c] + t2[c]);
+  }
+  mom_a<1, 0>(g0, A0, M3);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) M3[c] *= g0.rho;
+
+  // collision time (Sec. 3)
+  const double pl = double(p_side[0]), pr = double(p_side[1]);
+  const double jump = fabs((pl - pr) / (pl + pr));
+  double tau;
+  if (fp.ns) {
+    const double p0 = double(T(0.5) * g0.rho * drcp(g0.lam));
+    tau = fp.mu / p0 + fp.c2 * jump * fp.dt;
+  } else {
+    tau = fp.c1 * fp.dt + fp.c2 * jump * fp.dt;
+  }
+
+  if (prfix) {
+    // heat flux q = int (u-U0)((u-U0)^2+(v-V0)^2+xi^2)/2 f, written through the flux moments (u psi)
+    // and the conserved moments (psi) of every term of f; the energy flux gains (1/Pr - 1) q.
+    const T U0 = g0.U, V0 = g0.V;
+    const T cA = T(1.5) * U0 * U0 + T(0.5) * V0 * V0, cB = T(0.5) * U0 * (U0 * U0 + V0 * V0);
+    const T kpr = T(1.0 / fp.Pr - 1.0);
+    // conserved moments of each term: N1 = rho0 <psi>, N2 = rho0 <(a0 u + b0 v) psi> = -rho0 <A0 psi>,
+    // N3 = rho0 <A0 psi>, N4a = Wc, N4b, N5
+    T N3[4];
+    mom_a<0, 0>(g0, A0, N3);
+    T N1[4];
+    mom_psi<0, 0>(g0, N1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { N1[c] *= g0.rho; N3[c] *= g0.rho; }
+#define QOF(Mv_, Nv_) (Mv_[3] - U0 * Mv_[1] - V0 * Mv_[2] + cA * Mv_[0] + U0 * V0 * Nv_[2] - U0 * Nv_[3] - cB * Nv_[0])
+    const T q1 = QOF(M1, N1);
+    const T q2 = M2[3] - U0 * M2[1] - V0 * M2[2] + cA * M2[0] - (U0 * V0 * N3[2] - U0 * N3[3] - cB * N3[0]);
+    const T q3 = QOF(M3, N3);
+    const T q4a = QOF(M4a, Wc);
+    const T q4b = QOF(M4b, N4b);
+    const T q5 = QOF(M5, N5);
+#undef QOF
+    M1[3] += kpr * q1;
+    M2[3] += kpr * q2;
+    M3[3] += kpr * q3;
+    M4a[3] += kpr * q4a;
+    M4b[3] += kpr * q4b;
+    M5[3] += kpr * q5;
+  }
+
+  double Cd[5], Ch[5];
+  time_integrals(fp.dt, tau, Cd);
+  time_integrals(0.5 * fp.dt, tau, Ch);
+  const double idt = 1.0 / fp.dt;
+  if (fp.want_F) {
+    // F = (4 F(dt/2) - F(dt)) / dt
+    const T f1 = T((4.0 * Ch[0] - Cd[0]) * idt), f2 = T((4.0 * Ch[1] - Cd[1]) * idt);
+    const T f3 = T((4.0 * Ch[2] - Cd[2]) * idt), f4 = T((4.0 * Ch[3] - Cd[3]) * idt);
+    const T f5 = T((4.0 * Ch[4] - Cd[4]) * idt), f4t = T(tau * (4.0 * Ch[3] - Cd[3]) * idt);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      F[c] += wgt * (f1 * M1[c] + f2 * M2[c] + f3 * M3[c] + f4 * M4a[c] - f4t * M4b[c] - f5 * M5[c]);
+  }
+  // dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2
+  const double idt2 = 4.0 * idt * idt;
+  const T d1 = T((Cd[0] - 2.0 * Ch[0]) * idt2), d2 = T((Cd[1] - 2.0 * Ch[1]) * idt2);
+  const T d3 = T((Cd[2] - 2.0 * Ch[2]) * idt2), d4 = T((Cd[3] - 2.0 * Ch[3]) * idt2);
+  const T d5 = T((Cd[4] - 2.0 * Ch[4]) * idt2), d4t = T(tau * (Cd[3] - 2.0 * Ch[3]) * idt2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    dF[c] += wgt * (d1 * M1[c] + d2 * M2[c] + d3 * M3[c] + d4 * M4a[c] - d4t * M4b[c] - d5 * M5[c]);
+}
+
+}  // namespace hk

@@ -1,0 +1,539 @@
+// HIP kernels of the hybrid WENO5-AO gas-kinetic scheme (Mu et al., arXiv 2304.05572) for gfx950.
+//
+// One step of one or many problems (each with its own time step) is
+//   k_dt_finalize -> [k_flags -> k_flux(stage 1) -> k_update(stage 1)]
+//                 -> [k_flags -> k_flux(stage 2) -> k_update(stage 2, + CFL partials)] -> k_commit
+// Work is split into tiles; a prefix-sum table maps a flat block index to (problem, tile), so a batch
+// of uneven problems runs in the same launches as a single problem.
+#include <hip/hip_runtime.h>
+
+#include "hgks_device.hpp"
+#include "hgks_launch.h"
+
+namespace hk {
+
+__device__ inline int find_prob(const int* __restrict__ off, int nprob, int b) {
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD receives a contiguous
+// range of tiles and neighbouring tiles share its L2.
+__device__ inline int xcd_swizzle(int b, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int x = b & 7, idx = b >> 3;
+  return x * q + (x < r ? x : r) + idx;
+}
+
+// ---------------------------------------------------------------------------------------------
+// CFL quantity of one cell: min(h / (|U| + c), h^2 / (4 mu / rho)) (Sec. 3), FP64, no contraction,
+// the same expression tree as the reference evaluation so the minimum is reproducible bit for bit.
+// ---------------------------------------------------------------------------------------------
+__device__ __attribute__((noinline)) double cfl_quantity(const ProbDev& P, double rho, double mu_, double mv,
+                                                         double E) {
+#pragma clang fp contract(off)
+  const double U = mu_ / rho;
+  const double V = (P.dim == 2) ? mv / rho : 0.0;
+  const double pr = (P.gamma - 1.0) * (E - 0.5 * rho * (U * U + V * V));
+  const double c = sqrt(P.gamma * pr / rho);
+  const double sp = sqrt(U * U + V * V) + c;
+  double q = P.h / sp;
+  if (P.ns) {
+    const double qv = (P.h * P.h) / (4.0 * (P.mu / rho));
+    q = fmin(q, qv);
+  }
+  return q;
+}
+
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide minimum, then one atomic per block on the problem's bit pattern (positive doubles order
+// like their bit patterns).
+__device__ inline void block_min_atomic(double q, unsigned long long* dst) {
+  __shared__ double red[16];
+  q = wave_min(q);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 1; k < nw; ++k) m = fmin(m, red[k]);
+    if (m < __builtin_inf()) atomicMin(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_cfl(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
+                                             const int* __restrict__ off, int nprob) {
+  const int p = find_prob(off, nprob, blockIdx.x);
+  const ProbDev& P = probs[p];
+  const size_t ncell = (size_t)P.nx * P.ny;
+  const size_t cell = (size_t)(blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
+  double q = __builtin_inf();
+  if (cell < ncell) {
+    const double* W = P.W;
+    const double mv = (P.dim == 2) ? W[2 * ncell + cell] : 0.0;
+    q = cfl_quantity(P, W[cell], W[ncell + cell], mv, W[(P.dim + 1) * ncell + cell]);
+  }
+  block_min_atomic(q, &ts[p].qmin);
+}
+
+__global__ void k_dt_finalize(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts, int nprob,
+                              int use_tend) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  TimeDev& s = ts[p];
+  const ProbDev& P = probs[p];
+  const double q = __longlong_as_double((long long)s.qmin);
+  s.qmin = 0x7ff0000000000000ull;  // +inf for the next reduction
+  if (!s.active) {
+    s.dt = 0.0;
+    return;
+  }
+  double dt = (P.fixed_dt > 0.0) ? P.fixed_dt : P.cfl * q;
+  if (!(dt > 0.0) || !(dt < __builtin_inf())) {
+    s.status |= 2;
+    s.active = 0;
+    s.dt = 0.0;
+    return;
+  }
+  if (use_tend && s.t + dt >= s.t_end) {
+    dt = s.t_end - s.t;
+    s.t_new = s.t_end;
+  } else {
+    s.t_new = s.t + dt;
+  }
+  s.dt = dt;
+}
+
+__global__ void k_commit(TimeDev* __restrict__ ts, int nprob, int use_tend) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  TimeDev& s = ts[p];
+  if (!s.active) return;
+  s.t = s.t_new;
+  s.steps += 1;
+  if (use_tend && s.t >= s.t_end) s.active = 0;
+}
+
+__global__ void k_reset_qmin(TimeDev* __restrict__ ts, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nprob) ts[p].qmin = 0x7ff0000000000000ull;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Troubled-cell flags (Sec. 2.3.1 Steps 1-4) of every cell of the extended range [-2, n+1]:
+// T of the cell and both neighbours, OR over the four conserved components, per direction.
+// ---------------------------------------------------------------------------------------------
+__device__ inline int troubled_cell(const double q[5][4], double thr) {
+  int t = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) t |= troubled5(q[0][c], q[1][c], q[2][c], q[3][c], q[4][c], thr);
+  return t;
+}
+
+__device__ inline int widened_flag(const ProbDev& P, const double* W, int i, int j, int dir, double thr) {
+  double q[7][4];
+#pragma unroll
+  for (int r = 0; r < 7; ++r) {
+    if (dir == 0) load_cell(P, W, i - 3 + r, j, q[r]);
+    else load_cell(P, W, i, j - 3 + r, q[r]);
+  }
+  int f = 0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    double w[5][4];
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) w[r][c] = q[s + r][c];
+    f |= troubled_cell(w, thr);
+  }
+  return f;
+}
+
+__global__ void __launch_bounds__(256) k_flags(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
+                                               const int* __restrict__ off, int nprob, int use_stage_state,
+                                               int count) {
+  const int p = find_prob(off, nprob, blockIdx.x);
+  const ProbDev& P = probs[p];
+  if (!ts[p].active) return;
+  const int ex = P.nx + 4, ey = (P.dim == 2) ? P.ny + 4 : 1;
+  const int e = (blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
+  int fl = 0, interior = 0;
+  if (e < ex * ey) {
+    const int i = e % ex - 2, j = (P.dim == 2) ? e / ex - 2 : 0;
+    const double* W = use_stage_state ? P.Ws : P.W;
+    if (P.recon == 1) {
+      fl = (P.dim == 2) ? 3 : 1;
+    } else if (P.recon == 0) {
+      const double tx = (P.zeta1_mode == 0) ? 5.0 * P.dx : 5.0 * P.dx * P.dx * P.dx;
+      fl = widened_flag(P, W, i, j, 0, tx);
+      if (P.dim == 2) {
+        const double ty = (P.zeta1_mode == 0) ? 5.0 * P.dy : 5.0 * P.dy * P.dy * P.dy;
+        fl |= widened_flag(P, W, i, j, 1, ty) << 1;
+      }
+    }
+    P.flags[e] = (uint8_t)fl;
+    interior = (i >= 0 && i < P.nx && j >= 0 && j < P.ny);
+  }
+  if (count) {
+    const unsigned long long bx = __ballot(interior && (fl & 1));
+    const unsigned long long by = __ballot(interior && (fl & 2));
+    if ((threadIdx.x & 63) == 0) {
+      if (bx) atomicAdd(&P.flag_count[0], __popcll(bx));
+      if (by) atomicAdd(&P.flag_count[1], __popcll(by));
+    }
+  }
+}
+
+__global__ void k_clear_counts(const ProbDev* __restrict__ probs, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nprob) {
+    probs[p].flag_count[0] = 0;
+    probs[p].flag_count[1] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fused reconstruction + gas-kinetic flux. A block owns TN interfaces along the normal direction of
+// TT rows (2D) and stages in LDS:
+//   sW  : cell averages, normal -3..TN+1 around the interfaces, rows -2..TT+1 (ghosts synthesised)
+//   sF  : flags of the cells adjacent to each interface (bit 0 normal, bit 1 tangential)
+//   sNR : normal reconstruction of every row: W^l, W^l_x, W^r, W^r_x (16 values per interface)
+// then each thread takes one interface through the tangential reconstruction at the two Gauss
+// points, the equilibrium state and the flux (Sec. 2.3.3 Steps 1-3, Sec. 2.1-2.2).
+// Frame: slot 1 holds the normal momentum, slot 2 the tangential one (y-interfaces swap U and V).
+// ---------------------------------------------------------------------------------------------
+template <typename T, int TN, int TT, int DIM>
+__global__ void __launch_bounds__(TN * TT) k_flux(const ProbDev* __restrict__ probs,
+                                                  const TimeDev* __restrict__ ts,
+                                                  const int* __restrict__ off, int nprob, int stage) {
+  constexpr int R = (DIM == 2) ? TT + 4 : 1;  // rows with halo
+  constexpr int RO = (DIM == 2) ? 2 : 0;      // halo rows below
+  constexpr int C = TN + 5;                   // cells along the normal: -3 .. TN+1
+  constexpr int NT = TN * TT;
+  __shared__ T sW[4][R][C];
+  __shared__ uint8_t sF[R][TN + 1];
+  __shared__ T sNR[R][TN][16];
+
+  const int nblocks = gridDim.x;
+  const int b = xcd_swizzle(blockIdx.x, nblocks);
+  const int p = find_prob(off, nprob, b);
+  const ProbDev& P = probs[p];
+  const TimeDev& tsp = ts[p];
+  if (!tsp.active) return;
+  const int tid = threadIdx.x;
+
+  // direction and tile of this block: x-interface tiles come first, then y-interface tiles
+  const int nxt = (P.nx + 1 + TN - 1) / TN * ((P.ny + TT - 1) / TT);
+  int lt = b - off[p];
+  const int dir = (DIM == 2 && lt >= nxt) ? 1 : 0;
+  if (dir) lt -= nxt;
+  const int nn = dir ? P.ny : P.nx, nt = dir ? P.nx : P.ny;
+  const int tilesn = (nn + 1 + TN - 1) / TN;
+  const int n0 = (lt % tilesn) * TN, t0 = (lt / tilesn) * TT;
+  const double hn = dir ? P.dy : P.dx, ht = dir ? P.dx : P.dy;
+
+  // ---- phase 1: load cells (with ghost synthesis) and flags
+  const double* __restrict__ Wsrc = (stage == 1) ? P.W : P.Ws;
+  for (int e = tid; e < R * C; e += NT) {
+    int r, c;
+    if (dir == 0) { r = e / C; c = e % C; }  // consecutive threads along x
+    else { c = e / R; r = e % R; }          // consecutive threads along x (= tangential)
+    const int n = n0 - 3 + c, t = (DIM == 2) ? t0 - RO + r : 0;
+    double q[4];
+    const bool ok = n >= -4 && n <= nn + 3 && (DIM == 1 || (t >= -4 && t <= nt + 3));
+    if (ok) {
+      if (dir == 0) load_cell(P, Wsrc, n, t, q);
+      else load_cell(P, Wsrc, t, n, q);
+      if (dir) { const double s = q[1]; q[1] = q[2]; q[2] = s; }
+    } else {
+      q[0] = 1.0; q[1] = 0.0; q[2] = 0.0; q[3] = 2.5;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sW[k][r][c] = T(q[k]);
+  }
+  const int ex = P.nx + 4;
+  for (int e = tid; e < R * (TN + 1); e += NT) {
+    const int r = e / (TN + 1), c = e % (TN + 1);
+    const int n = n0 - 1 + c, t = (DIM == 2) ? t0 - RO + r : 0;
+    const int gi = dir ? t : n, gj = dir ? n : t;
+    uint8_t f = 0;
+    if (gi >= -2 && gi <= P.nx + 1 && (DIM == 1 || (gj >= -2 && gj <= P.ny + 1))) {
+      const uint8_t raw = P.flags[(DIM == 2 ? (size_t)(gj + 2) * ex : 0) + (gi + 2)];
+      f = dir ? (uint8_t)(((raw >> 1) & 1) | ((raw & 1) << 1)) : raw;
+    }
+    sF[r][c] = f;
+  }
+  __syncthreads();
+
+  // ---- phase 2: normal reconstruction of every row (Sec. 2.3.1; line averages in 2D)
+  const T ihn = T(1.0 / hn);
+  const T gam = T(P.gamma), ghi = T(P.ghi), glo = T(P.glo), eps = T(P.eps);
+  for (int e = tid; e < R * TN; e += NT) {
+    const int r = e / TN, k = e % TN;
+    T q6[6][4];
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) q6[m][v] = sW[v][r][k + m];  // cells n0+k-3 .. n0+k+2
+    const int fl = sF[r][k] & 1, fr = sF[r][k + 1] & 1;
+    T out[16];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      out[v] = (T(2) * q6[0][v] - T(13) * q6[1][v] + T(47) * q6[2][v] + T(27) * q6[3][v] - T(3) * q6[4][v]) *
+               T(1.0 / 60.0);
+      const T sl = (q6[1][v] - T(15) * q6[2][v] + T(15) * q6[3][v] - q6[4][v]) * (T(1.0 / 12.0) * ihn);
+      out[4 + v] = sl;
+      out[12 + v] = sl;
+      out[8 + v] = (T(-3) * q6[1][v] + T(27) * q6[2][v] + T(47) * q6[3][v] - T(13) * q6[4][v] + T(2) * q6[5][v]) *
+                   T(1.0 / 60.0);
+    }
+    if (fl | fr) {
+      CharMat<T> m;
+      T avg[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) avg[v] = T(0.5) * (q6[2][v] + q6[3][v]);
+      char_matrices(avg, gam, 1, m);
+      T val[4], der[4];
+      if (fl) {
+        ao_vector(reinterpret_cast<const T(*)[4]>(&q6[0][0]), m, 0, ghi, glo, eps, val, der);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { out[v] = val[v]; out[4 + v] = der[v] * ihn; }
+      }
+      if (fr) {
+        ao_vector(reinterpret_cast<const T(*)[4]>(&q6[1][0]), m, 1, ghi, glo, eps, val, der);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { out[8 + v] = val[v]; out[12 + v] = der[v] * ihn; }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) sNR[r][k][v] = out[v];
+  }
+  __syncthreads();
+
+  // ---- phase 3: tangential reconstruction at the Gauss points, equilibrium state and GKS flux
+  int k, tt;
+  if (dir == 0) { k = tid % TN; tt = tid / TN; }
+  else { tt = tid % TT; k = tid / TT; }
+  const int n = n0 + k, t = t0 + tt;
+  if (n > nn || (DIM == 2 && t >= nt)) return;
+
+  FluxParams fp;
+  fp.gamma = P.gamma; fp.K = P.K; fp.mu = P.mu; fp.Pr = P.Pr; fp.c1 = P.c1; fp.c2 = P.c2;
+  fp.dt = tsp.dt; fp.ns = P.ns; fp.want_F = (stage == 1);
+  T F[4] = {0, 0, 0, 0}, dF[4] = {0, 0, 0, 0};
+  if (DIM == 1) {
+    T Wl[4], Wxl[4], Wr[4], Wxr[4];
+    const T z[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wl[v] = sNR[0][k][v]; Wxl[v] = sNR[0][k][4 + v];
+      Wr[v] = sNR[0][k][8 + v]; Wxr[v] = sNR[0][k][12 + v];
+    }
+    gks_flux_gp(Wl, Wxl, z, Wr, Wxr, z, fp, T(1), F, dF);
+  } else {
+    const int ftl = (sF[tt + 2][k] >> 1) & 1, ftr = (sF[tt + 2][k + 1] >> 1) & 1;
+    const T iht = T(1.0 / ht);
+    for (int gp = 0; gp < 2; ++gp) {
+      T Ws[2][4], Wxs[2][4], Wys[2][4];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int ft = s ? ftr : ftl;
+        const int ov = 8 * s, od = 8 * s + 4;
+        if (ft) {
+          // characteristic variables of the tangential direction about this side's own line-averaged
+          // state of the centre segment (the state of the cell being reconstructed)
+          CharMat<T> m;
+          T own[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) own[v] = sNR[tt + 2][k][ov + v];
+          char_matrices(own, gam, 2, m);
+          T qv[5][4], qd[5][4], val[4], der[4];
+#pragma unroll
+          for (int r = 0; r < 5; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) { qv[r][v] = sNR[tt + r][k][ov + v]; qd[r][v] = sNR[tt + r][k][od + v]; }
+          ao_vector(qv, m, 2 + gp, ghi, glo, eps, val, der);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) { Ws[s][v] = val[v]; Wys[s][v] = der[v] * iht; }
+          ao_vector(qd, m, 2 + gp, ghi, glo, eps, val, der);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Wxs[s][v] = val[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            T q[5], qx[5], vv, dd, vx, dx_;
+#pragma unroll
+            for (int r = 0; r < 5; ++r) { q[r] = sNR[tt + r][k][ov + v]; qx[r] = sNR[tt + r][k][od + v]; }
+            gauss_linear(q, gp, vv, dd);
+            gauss_linear(qx, gp, vx, dx_);
+            Ws[s][v] = vv;
+            Wys[s][v] = dd * iht;
+            Wxs[s][v] = vx;
+          }
+        }
+      }
+      gks_flux_gp(Ws[0], Wxs[0], Wys[0], Ws[1], Wxs[1], Wys[1], fp, T(0.5), F, dF);
+    }
+  }
+
+  // ---- write F (stage 1) and dF/dt in the grid's component order
+  T* Fo = reinterpret_cast<T*>(dir ? P.Fy : P.Fx);
+  T* Go = reinterpret_cast<T*>(dir ? P.Gy : P.Gx);
+  size_t o, plane;
+  if (dir == 0) { plane = (size_t)P.ny * (P.nx + 1); o = (size_t)t * (P.nx + 1) + n; }
+  else { plane = (size_t)(P.ny + 1) * P.nx; o = (size_t)n * P.nx + t; }
+  const int nc = (DIM == 2) ? 4 : 3;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    // frame slot -> grid component: y-interfaces swap the momenta back; 1D drops the V slot
+    int gc = v;
+    if (dir && (v == 1 || v == 2)) gc = 3 - v;
+    if (DIM == 1) {
+      if (v == 2) continue;
+      if (v == 3) gc = 2;
+    }
+    if (gc >= nc) continue;
+    if (stage == 1) Fo[gc * plane + o] = F[v];
+    Go[gc * plane + o] = dF[v];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// S2O4 stage updates (Sec. 2.2), FP64 state:
+//   stage 1: W* = W^n - sum_dir [F(dt/2)_{+} - F(dt/2)_{-}]/h,  F(dt/2) = dt/2 F + dt^2/8 dF/dt
+//            S  = W^n - dt sum_dir [(F + dt/6 dF/dt)_{+} - (...)_{-}]/h
+//   stage 2: W^{n+1} = S - dt^2/3 sum_dir [dF*/dt_{+} - dF*/dt_{-}]/h, then the CFL quantity of
+//            W^{n+1} for the next step.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
+                                                const int* __restrict__ off, int nprob, int stage) {
+  const int p = find_prob(off, nprob, blockIdx.x);
+  const ProbDev& P = probs[p];
+  TimeDev& tsp = ts[p];
+  if (!tsp.active) return;
+  const size_t ncell = (size_t)P.nx * P.ny;
+  const size_t cell = (size_t)(blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
+  double q = __builtin_inf();
+  if (cell < ncell) {
+    const int i = (int)(cell % P.nx), j = (int)(cell / P.nx);
+    const int nc = P.dim + 2;
+    const double dt = tsp.dt;
+    const double idx = 1.0 / P.dx, idy = (P.dim == 2) ? 1.0 / P.dy : 0.0;
+    const T* Fx = reinterpret_cast<const T*>(P.Fx);
+    const T* Gx = reinterpret_cast<const T*>(P.Gx);
+    const T* Fy = reinterpret_cast<const T*>(P.Fy);
+    const T* Gy = reinterpret_cast<const T*>(P.Gy);
+    const size_t px = (size_t)P.ny * (P.nx + 1), py = (size_t)(P.ny + 1) * P.nx;
+    const size_t ox = (size_t)j * (P.nx + 1) + i, oy = (size_t)j * P.nx + i;
+    double wn[4] = {0, 0, 0, 0};
+    bool bad = false;
+    for (int c = 0; c < nc; ++c) {
+      const double gx = (double(Gx[c * px + ox + 1]) - double(Gx[c * px + ox])) * idx;
+      const double gy = (P.dim == 2) ? (double(Gy[c * py + oy + P.nx]) - double(Gy[c * py + oy])) * idy : 0.0;
+      const double w = P.W[c * ncell + cell];
+      if (stage == 1) {
+        const double fx = (double(Fx[c * px + ox + 1]) - double(Fx[c * px + ox])) * idx;
+        const double fy = (P.dim == 2) ? (double(Fy[c * py + oy + P.nx]) - double(Fy[c * py + oy])) * idy : 0.0;
+        const double ws = w - (dt * (0.5 * fx + 0.125 * dt * gx) + dt * (0.5 * fy + 0.125 * dt * gy));
+        const double s = w - (dt * (fx + dt / 6.0 * gx) + dt * (fy + dt / 6.0 * gy));
+        P.Ws[c * ncell + cell] = ws;
+        P.S[c * ncell + cell] = s;
+        wn[c == nc - 1 ? 3 : c] = ws;
+      } else {
+        const double wnew = P.S[c * ncell + cell] - dt * dt / 3.0 * (gx + gy);
+        P.W[c * ncell + cell] = wnew;
+        wn[c == nc - 1 ? 3 : c] = wnew;
+      }
+    }
+    const double rho = wn[0];
+    const double ke = 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / rho;
+    const double pr = (P.gamma - 1.0) * (wn[3] - ke);
+    bad = !(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf());
+    if (bad) atomicOr(&tsp.status, 1);
+    if (stage == 2) q = cfl_quantity(P, wn[0], wn[1], wn[2], wn[3]);
+  }
+  if (stage == 2) block_min_atomic(q, &tsp.qmin);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------------------------
+static inline unsigned nblk(int n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_cfl(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_reset_qmin, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.ts, L.nprob);
+  hipLaunchKernelGGL(k_cfl, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell, L.nprob);
+}
+
+void launch_dt_finalize(const LaunchCtx& L, int use_tend) {
+  hipLaunchKernelGGL(k_dt_finalize, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.probs, L.ts, L.nprob,
+                     use_tend);
+}
+
+void launch_commit(const LaunchCtx& L, int use_tend) {
+  hipLaunchKernelGGL(k_commit, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.ts, L.nprob, use_tend);
+}
+
+void launch_flags(const LaunchCtx& L, int stage_state, int count) {
+  if (count) hipLaunchKernelGGL(k_clear_counts, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.probs, L.nprob);
+  hipLaunchKernelGGL(k_flags, dim3(L.ext_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_ext, L.nprob,
+                     stage_state, count);
+}
+
+template <typename T, int TN, int TT>
+static void flux_variant(const LaunchCtx& L, int stage) {
+  if (L.dim == 1)
+    hipLaunchKernelGGL((k_flux<T, TN * TT, 1, 1>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream, L.probs,
+                       L.ts, L.off_flux, L.nprob, stage);
+  else
+    hipLaunchKernelGGL((k_flux<T, TN, TT, 2>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream, L.probs, L.ts,
+                       L.off_flux, L.nprob, stage);
+}
+
+// tile shapes (interfaces along the normal x rows along the tangential direction)
+const TileShape kTiles[kNumTiles] = {{16, 16}, {32, 8}, {64, 4}, {16, 8}, {8, 8}};
+
+void launch_flux(const LaunchCtx& L, int stage) {
+  const int t = L.tile;
+  if (L.fp32) {
+    switch (t) {
+      case 0: flux_variant<float, 16, 16>(L, stage); break;
+      case 1: flux_variant<float, 32, 8>(L, stage); break;
+      case 2: flux_variant<float, 64, 4>(L, stage); break;
+      case 3: flux_variant<float, 16, 8>(L, stage); break;
+      default: flux_variant<float, 8, 8>(L, stage); break;
+    }
+  } else {
+    switch (t) {
+      case 0: flux_variant<double, 16, 16>(L, stage); break;
+      case 1: flux_variant<double, 32, 8>(L, stage); break;
+      case 2: flux_variant<double, 64, 4>(L, stage); break;
+      case 3: flux_variant<double, 16, 8>(L, stage); break;
+      default: flux_variant<double, 8, 8>(L, stage); break;
+    }
+  }
+}
+
+void launch_update(const LaunchCtx& L, int stage) {
+  if (L.fp32)
+    hipLaunchKernelGGL(k_update<float>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
+                       L.nprob, stage);
+  else
+    hipLaunchKernelGGL(k_update<double>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
+                       L.nprob, stage);
+}
+
+}  // namespace hk

@@ -1,0 +1,330 @@
+"""Python binding of the HIP library libhgks.so (C ABI in include/hgks.h).
+
+Argument marshalling only: every step of the scheme runs in the library's HIP kernels. The functions
+``hgks_create`` ... ``hgks_status_str`` mirror the C entry points one to one; ``Solver`` is a small
+convenience wrapper over them. Device buffers may be torch tensors on the GPU (passed by address with
+``on_device=1``); host buffers are numpy arrays.
+
+Importing this module does not touch the GPU. Loading the library fails loudly (``HgksLibraryMissing``)
+if ``libhgks.so`` has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgks.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EDT = 0, -1, -2, -3, -4, -5
+EULER, NS = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_NOSLIP = 0, 1, 2, 3
+RECON_HYBRID, RECON_WENOAO, RECON_LINEAR = 0, 1, 2
+FP64, FP32_BULK = 0, 1
+
+ENTRY_POINTS = ("hgks_create", "hgks_workspace_bytes", "hgks_bind_workspace", "hgks_set_ic", "hgks_step",
+                "hgks_run", "hgks_get_state", "hgks_debug_flags", "hgks_debug_stage_fluxes", "hgks_get_stats",
+                "hgks_get_tile", "hgks_get_profile", "hgks_destroy", "hgks_status_str")
+
+
+class HgksLibraryMissing(ImportError):
+    pass
+
+
+class HgksError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {hgks_status_str(code)} ({code})")
+        self.code = code
+
+
+class hgks_problem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+        ("eqn", C.c_int32), ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
+        ("cfl", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("fixed_dt", C.c_double),
+        ("bc", C.c_int32 * 4), ("recon", C.c_int32),
+        ("gamma_hi", C.c_double), ("gamma_lo", C.c_double), ("weno_eps", C.c_double),
+        ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32),
+    ]
+
+
+class hgks_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("autotune", C.c_int32), ("use_graph", C.c_int32),
+                ("tile", C.c_int32), ("profile", C.c_int32), ("hip_stream", C.c_void_p)]
+
+
+@dataclasses.dataclass
+class Problem:
+    """Problem statement (paper Sec. 2; parameters of Sec. 3)."""
+    dim: int = 2
+    nx: int = 64
+    ny: int = 64
+    x0: float = 0.0
+    x1: float = 1.0
+    y0: float = 0.0
+    y1: float = 1.0
+    eqn: int = EULER
+    gamma: float = 1.4
+    mu: float = 0.0
+    Pr: float = 1.0
+    cfl: float = 0.5
+    c1: float = 0.01
+    c2: float = 1.0
+    fixed_dt: float = 0.0
+    bc: tuple = (BC_OUTFLOW,) * 4
+    recon: int = RECON_HYBRID
+    gamma_hi: float = 0.85
+    gamma_lo: float = 0.85
+    weno_eps: float = 1e-8
+    zeta1_mode: int = 0
+    tangential_flag_mode: int = 0
+
+    @property
+    def nc(self):
+        return self.dim + 2
+
+    @property
+    def shape(self):
+        return (self.nc, self.nx) if self.dim == 1 else (self.nc, self.ny, self.nx)
+
+    @property
+    def cells(self):
+        return self.nx * (self.ny if self.dim == 2 else 1)
+
+    def c_struct(self) -> hgks_problem:
+        s = hgks_problem()
+        for f in dataclasses.fields(self):
+            v = getattr(self, f.name)
+            if f.name == "bc":
+                s.bc = (C.c_int32 * 4)(*[int(b) for b in (list(v) + [0] * 4)[:4]])
+            else:
+                setattr(s, f.name, v)
+        return s
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhgks.so; raises HgksLibraryMissing if it was never built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HgksLibraryMissing(f"{LIB_PATH} is missing: build it with paper_2304_05572_amd/build.py "
+                                     "(hipcc, gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "hgks_create": (i32, [C.POINTER(hgks_problem), i32, C.POINTER(hgks_opts), C.POINTER(vp)]),
+            "hgks_workspace_bytes": (C.c_size_t, [vp]),
+            "hgks_bind_workspace": (i32, [vp, vp, C.c_size_t]),
+            "hgks_set_ic": (i32, [vp, i32, vp, i32, d]),
+            "hgks_step": (i32, [vp, vp]),
+            "hgks_run": (i32, [vp, vp, i64, vp]),
+            "hgks_get_state": (i32, [vp, i32, vp, i32, vp]),
+            "hgks_debug_flags": (i32, [vp, i32, vp, vp]),
+            "hgks_debug_stage_fluxes": (i32, [vp, i32, d, vp, vp, vp, vp]),
+            "hgks_get_stats": (i32, [vp, i32, vp]),
+            "hgks_get_tile": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+            "hgks_get_profile": (i32, [vp, vp]),
+            "hgks_destroy": (None, [vp]),
+            "hgks_status_str": (C.c_char_p, [i32]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------------ one-to-one wrappers of the C ABI
+def _addr(buf):
+    """(address, on_device) of a numpy array or a torch tensor."""
+    if hasattr(buf, "data_ptr"):
+        return C.c_void_p(buf.data_ptr()), int(buf.is_cuda)
+    return buf.ctypes.data_as(C.c_void_p), 0
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise HgksError(code, where)
+
+
+def hgks_status_str(code: int) -> str:
+    return lib().hgks_status_str(int(code)).decode()
+
+
+def hgks_create(problems: Sequence[Problem], precision=FP64, autotune=0, use_graph=0, tile=-1, hip_stream=None,
+                profile=0):
+    arr = (hgks_problem * len(problems))(*[p.c_struct() for p in problems])
+    opts = hgks_opts(int(precision), int(autotune), int(use_graph), int(tile), int(profile),
+                     C.c_void_p(hip_stream) if hip_stream else None)
+    h = C.c_void_p()
+    _check(lib().hgks_create(arr, len(problems), C.byref(opts), C.byref(h)), "hgks_create")
+    return h
+
+
+def hgks_workspace_bytes(h) -> int:
+    return int(lib().hgks_workspace_bytes(h))
+
+
+def hgks_bind_workspace(h, buf, nbytes: int):
+    ptr, _ = _addr(buf)
+    _check(lib().hgks_bind_workspace(h, ptr, int(nbytes)), "hgks_bind_workspace")
+
+
+def hgks_set_ic(h, prob: int, W, t0: float = 0.0):
+    if not hasattr(W, "data_ptr"):
+        W = np.ascontiguousarray(W, dtype=np.float64)
+    ptr, dev = _addr(W)
+    _check(lib().hgks_set_ic(h, int(prob), ptr, dev, float(t0)), "hgks_set_ic")
+
+
+def hgks_step(h, nprob: int):
+    dt = np.zeros(nprob)
+    _check(lib().hgks_step(h, dt.ctypes.data_as(C.c_void_p)), "hgks_step")
+    return dt
+
+
+def hgks_run(h, t_end, max_steps: int):
+    t_end = np.ascontiguousarray(t_end, dtype=np.float64)
+    steps = np.zeros(len(t_end), np.int64)
+    _check(lib().hgks_run(h, t_end.ctypes.data_as(C.c_void_p), int(max_steps), steps.ctypes.data_as(C.c_void_p)),
+           "hgks_run")
+    return steps
+
+
+def hgks_get_state(h, prob: int, out):
+    t = C.c_double()
+    ptr, dev = _addr(out)
+    _check(lib().hgks_get_state(h, int(prob), ptr, dev, C.byref(t)), "hgks_get_state")
+    return t.value
+
+
+def hgks_debug_flags(h, prob: int, fx: np.ndarray, fy: np.ndarray | None):
+    _check(lib().hgks_debug_flags(h, int(prob), fx.ctypes.data_as(C.c_void_p),
+                                  fy.ctypes.data_as(C.c_void_p) if fy is not None else None), "hgks_debug_flags")
+
+
+def hgks_debug_stage_fluxes(h, prob: int, dt: float, Fx, Gx, Fy, Gy):
+    ptrs = [a.ctypes.data_as(C.c_void_p) if a is not None else None for a in (Fx, Gx, Fy, Gy)]
+    _check(lib().hgks_debug_stage_fluxes(h, int(prob), float(dt), *ptrs), "hgks_debug_stage_fluxes")
+
+
+def hgks_get_stats(h, prob: int):
+    out = np.zeros(6)
+    _check(lib().hgks_get_stats(h, int(prob), out.ctypes.data_as(C.c_void_p)), "hgks_get_stats")
+    return out
+
+
+def hgks_get_tile(h):
+    tn, tt = C.c_int32(), C.c_int32()
+    _check(lib().hgks_get_tile(h, C.byref(tn), C.byref(tt)), "hgks_get_tile")
+    return tn.value, tt.value
+
+
+def hgks_get_profile(h):
+    out = np.zeros(8)
+    _check(lib().hgks_get_profile(h, out.ctypes.data_as(C.c_void_p)), "hgks_get_profile")
+    return out
+
+
+def hgks_destroy(h):
+    lib().hgks_destroy(h)
+
+
+# ------------------------------------------------------------------ convenience wrapper
+class Solver:
+    """Owns one library handle for a list of problems advanced together."""
+
+    def __init__(self, problems: Sequence[Problem] | Problem, precision=FP64, autotune=False, use_graph=False,
+                 tile=-1, stream=None, workspace=None, profile=False):
+        if isinstance(problems, Problem):
+            problems = [problems]
+        self.problems = list(problems)
+        sp = None
+        if stream is not None:
+            sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self.h = hgks_create(self.problems, precision, int(autotune), int(use_graph), tile, sp, int(profile))
+        self.workspace = None
+        if workspace is not None:
+            self.bind_workspace(workspace)
+
+    @property
+    def nprob(self):
+        return len(self.problems)
+
+    def workspace_bytes(self):
+        return hgks_workspace_bytes(self.h)
+
+    def bind_workspace(self, buf):
+        """Use caller-owned device memory, e.g. torch.empty(n, dtype=torch.uint8, device='cuda')."""
+        hgks_bind_workspace(self.h, buf, buf.numel() * buf.element_size())
+        self.workspace = buf  # keep the owner alive
+
+    def set_ic(self, prob: int, W, t0: float = 0.0):
+        hgks_set_ic(self.h, prob, W, t0)
+
+    def step(self):
+        return hgks_step(self.h, self.nprob)
+
+    def run(self, t_end, max_steps: int = 2 ** 62):
+        if np.isscalar(t_end):
+            t_end = [t_end] * self.nprob
+        return hgks_run(self.h, t_end, max_steps)
+
+    def get_state(self, prob: int = 0, out=None):
+        if out is None:
+            out = np.zeros(self.problems[prob].shape)
+        t = hgks_get_state(self.h, prob, out)
+        return out, t
+
+    def flags(self, prob: int = 0):
+        P = self.problems[prob]
+        shp = (P.nx,) if P.dim == 1 else (P.ny, P.nx)
+        fx = np.zeros(shp, np.uint8)
+        fy = np.zeros(shp, np.uint8) if P.dim == 2 else None
+        hgks_debug_flags(self.h, prob, fx, fy)
+        return fx, fy
+
+    def stage_fluxes(self, prob: int, dt: float):
+        P = self.problems[prob]
+        nc, nx, ny = P.nc, P.nx, (P.ny if P.dim == 2 else 1)
+        Fx = np.zeros((nc, ny, nx + 1))
+        Gx = np.zeros_like(Fx)
+        Fy = np.zeros((nc, ny + 1, nx)) if P.dim == 2 else None
+        Gy = np.zeros_like(Fy) if P.dim == 2 else None
+        hgks_debug_stage_fluxes(self.h, prob, dt, Fx, Gx, Fy, Gy)
+        if P.dim == 1:
+            return Fx[:, 0, :], Gx[:, 0, :], None, None
+        return Fx, Gx, Fy, Gy
+
+    def stats(self, prob: int = 0):
+        s = hgks_get_stats(self.h, prob)
+        return dict(steps=int(s[0]), cells=int(s[1]), t=s[2], dt=s[3], flagged_x=s[4], flagged_y=s[5])
+
+    def tile(self):
+        return hgks_get_tile(self.h)
+
+    def profile(self):
+        """Per kernel group: (total ms, launches) for flux, update, flags, scalar kernels."""
+        o = hgks_get_profile(self.h)
+        names = ("flux", "update", "flags", "scalar")
+        return {n: (o[2 * k], int(o[2 * k + 1])) for k, n in enumerate(names)}
+
+    def close(self):
+        if self.h:
+            hgks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
