@@ -87,49 +87,40 @@ def time_solver(H, problems, states, precision, steps, warmup, tile):
     return t1 - t0, flux_ms / max(flux_n, 1), stats, tile_used, prof
 
 
-def window_l1(H, O, W0, n, precision, win=128, margin=10, seed=0):
-    """L1 distance (relative) GPU vs oracle after one step, on a centred win x win window: the GPU advances
-    the full grid; the oracle advances the window plus a margin larger than the two-stage dependency
-    radius (8 cells) with the GPU's time step, so the window's interior is exact."""
-    P = rp_problem(H, n)
-    s = H.Solver(P, precision=precision)
+def gpu_first_step(H, W0, n, precision):
+    """State after one S2O4 step from the initial data, and the step's dt."""
+    s = H.Solver(rp_problem(H, n), precision=precision)
     s.set_ic(0, W0)
     dt = s.step()[0]
-    Wg, _ = s.get_state(0)
+    W, _ = s.get_state(0)
     s.close()
-    a = n // 2 - win // 2 - margin
-    b = n // 2 + win // 2 + margin
-    sub = np.ascontiguousarray(W0[:, a:b, a:b])
-    m = b - a
-    h = 1.0 / n
-    Po = O.Problem(dim=2, nx=m, ny=m, x0=0, x1=m * h, y0=0, y1=m * h, bc=(1, 1, 1, 1), c1=0.01, c2=1.0,
-                   cfl=0.5, fixed_dt=dt)
-    Wo, _, _ = O.step(Po, sub, 0.0, nthreads=min(16, os.cpu_count() or 1))
-    A = Wg[:, a + margin:b - margin, a + margin:b - margin]
-    B = Wo[:, margin:-margin, margin:-margin]
-    return float(np.abs(A - B).mean() / np.abs(B).mean()), float(np.abs(A - B).max() / np.abs(B).max())
+    return W, dt
 
 
-def cpu_baseline(H, O, W0, n, budget_cells=256):
-    """The oracle as it stands, on host cores: two S2O4 steps of a centred 256 x 256 window of the same
-    workload (outflow boundaries at the window edge), all host threads up to 16."""
+def oracle_leg(W0, n):
+    """The oracle as it stands, on host cores: one S2O4 step of the whole workload (FP64 C oracle, all host
+    threads up to 16). Returns (state, dt, cpu_baseline record)."""
     import oracle
-    w = budget_cells
-    a = n // 2 - w // 2
-    sub = np.ascontiguousarray(W0[:, a:a + w, a:a + w])
-    h = 1.0 / n
-    Po = oracle.Problem(dim=2, nx=w, ny=w, x0=0, x1=w * h, y0=0, y1=w * h, bc=(1, 1, 1, 1), c1=0.01, c2=1.0,
-                        cfl=0.5)
+    Po = oracle.Problem(dim=2, nx=n, ny=n, bc=(1, 1, 1, 1), c1=0.01, c2=1.0, cfl=0.5)
     nth = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
-    W, t = sub, 0.0
-    nsteps = 2
-    for _ in range(nsteps):
-        W, t, _ = oracle.step(Po, W, t, nthreads=nth)
+    W, t, dt = oracle.step(Po, W0, 0.0, nthreads=nth)
     el = time.perf_counter() - t0
-    return {"value": w * w * nsteps / el / 1e6, "unit": "Mcell-updates/s", "cores": nth, "kind": "oracle",
-            "sample": f"{nsteps} S2O4 steps of the centred {w}x{w} window of the 1024^2 Riemann problem "
-                      f"(outflow window edges), FP64 C oracle, {nth} OpenMP threads, {el:.1f} s"}
+    rec = {"value": n * n / el / 1e6, "unit": "Mcell-updates/s", "cores": nth, "kind": "oracle",
+           "sample": f"one S2O4 step of the full {n}x{n} Riemann problem from its initial data, FP64 C oracle, "
+                     f"{nth} OpenMP threads, {el:.1f} s wall"}
+    return W, dt, rec
+
+
+def copy_calibration(mib=512, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.empty(mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: {reps} copies of {mib} MiB")
 
 
 def main():
@@ -141,13 +132,18 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tile", type=int, default=-1, help="tile-shape index; -1 autotunes")
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--skip", default="", help="comma list of: fp32,batched,cpu,parity")
+    ap.add_argument("--variants", default="fp64,fp32,batched", help="comma list of fp64,fp32,batched")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (CPU baseline and parity)")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run a plain copy (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (each box has one GPU); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    skip = set(x for x in args.skip.split(",") if x)
+    variants = set(x for x in args.variants.split(",") if x)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch  # device memory and streams; the compute is the HIP library
     from paper_2304_05572_amd import hgks as H
@@ -161,7 +157,7 @@ def main():
 
     res = {}
     for name, prec in (("fp64", H.FP64), ("fp32", H.FP32_BULK)):
-        if name == "fp32" and "fp32" in skip:
+        if name not in variants:
             continue
         log(f"[bench] timing {name}: {args.warmup} warm-up + {args.steps} steps")
         el, flux_ms, stats, tile, prof = time_solver(H, [rp_problem(H, n)], [W0], prec, args.steps, args.warmup,
@@ -172,7 +168,7 @@ def main():
             f"flux kernel {flux_ms:.3f} ms/launch, tile {tile}, flagged x {stats[0]['flagged_x']:.4f}")
 
     batch = None
-    if "batched" not in skip:
+    if "batched" in variants:
         sizes = wl.batch_sizes(args.batch, seed=args.seed)
         probs = [rp_problem(H, m) for m in sizes]
         bstates = [wl.riemann_2d(m, seed=args.seed * 1000 + k + 1)[0] for k, m in enumerate(sizes)]
@@ -181,23 +177,25 @@ def main():
                                                      args.tile)
         bcells = sum(m * m for m in sizes)
         batch = dict(mcells=bcells * args.steps / el / 1e6, ms_per_step=el / args.steps * 1e3, cells=bcells,
-                     problems=len(sizes), min_n=min(sizes), max_n=max(sizes), tile=tile)
+                     problems=len(sizes), min_n=min(sizes), max_n=max(sizes), launch_config=list(tile))
         log(f"[bench] batched: {batch['mcells']:.1f} Mcell-updates/s")
         del bstates
 
-    parity = {}
-    if "parity" not in skip:
-        import oracle as O
+    parity, cpu = {}, None
+    if not args.no_oracle:
+        log("[bench] oracle leg: one step of the full grid on the host")
+        Wo, dto, cpu = oracle_leg(W0, n)
         for name, prec in (("fp64", H.FP64), ("fp32", H.FP32_BULK)):
             if name in res:
-                log(f"[bench] window parity {name}")
-                parity[name] = window_l1(H, O, W0, n, prec)
-    cpu = None
-    if "cpu" not in skip:
-        import oracle as O
-        log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline(H, O, W0, n)
+                Wg, dtg = gpu_first_step(H, W0, n, prec)
+                parity[name] = (float(np.abs(Wg - Wo).mean() / np.abs(Wo).mean()),
+                                float(np.abs(Wg - Wo).max() / np.abs(Wo).max()), bool(dtg == dto))
+                log(f"[bench] parity {name}: L1_rel {parity[name][0]:.3e} Linf_rel {parity[name][1]:.3e} "
+                    f"dt equal {parity[name][2]}")
 
+    if "fp64" not in res:
+        print(json.dumps({"metric": METRIC, "value": None, "note": "fp64 variant not run"}), flush=True)
+        return
     r = res["fp64"]
     gps = 2 * ((n + 1) * n * 2)  # two Gauss points on every x- and y-interface
     roof = None
@@ -227,23 +225,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D four-quadrant Riemann problem, Euler, {n}x{n} cells, seeded quadrant states "
                                f"(seed {args.seed}), hybrid WENO5-AO GKS, S2O4, CFL 0.5, c1=0.01, c2=1, outflow",
-                   "nx": n, "ny": n, "seed": args.seed, "tile": list(r["tile"]),
+                   "nx": n, "ny": n, "seed": args.seed, "launch_config": {"tile": list(r["tile"][:2]), "waves_per_simd_target": r["tile"][2], "index": r["tile"][3]},
                    "flagged_fraction_x": r["stats"]["flagged_x"], "flagged_fraction_y": r["stats"]["flagged_y"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": {
             "fp64": {"value": r["mcells"], "ms_per_step": r["ms_per_step"], "flux_ms_per_launch": r["flux_ms"],
-                     "l1_rel_vs_oracle": parity.get("fp64", (None, None))[0],
-                     "linf_rel_vs_oracle": parity.get("fp64", (None, None))[1]},
+                     "l1_rel_vs_oracle": parity.get("fp64", (None,) * 3)[0],
+                     "linf_rel_vs_oracle": parity.get("fp64", (None,) * 3)[1],
+                     "dt_bit_exact_vs_oracle": parity.get("fp64", (None,) * 3)[2]},
         },
     }
     if "fp32" in res:
         f = res["fp32"]
         out["variants"]["fp32_bulk"] = {"value": f["mcells"], "ms_per_step": f["ms_per_step"],
                                         "flux_ms_per_launch": f["flux_ms"], "dtype": "f32 (f64 state/flags/CFL)",
-                                        "l1_rel_vs_oracle": parity.get("fp32", (None, None))[0],
-                                        "linf_rel_vs_oracle": parity.get("fp32", (None, None))[1],
-                                        "speedup_vs_fp64": f["mcells"] / r["mcells"], "tile": list(f["tile"])}
+                                        "l1_rel_vs_oracle": parity.get("fp32", (None,) * 3)[0],
+                                        "linf_rel_vs_oracle": parity.get("fp32", (None,) * 3)[1],
+                                        "speedup_vs_fp64": f["mcells"] / r["mcells"], "launch_config": list(f["tile"])}
     if batch:
         out["variants"]["batched"] = dict(batch, value=batch["mcells"], dtype="f32 (f64 state/flags/CFL)",
                                           workload=f"{batch['problems']} independent Riemann problems, N in "

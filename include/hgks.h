@@ -138,8 +138,10 @@ hgks_status hgks_get_stats(const hgks_t* h, int32_t prob, double* out);
  * (time step, commit). Synchronises the stream. */
 hgks_status hgks_get_profile(hgks_t* h, double* out /* 8 entries */);
 
-/* Tile shape in use: *tn interfaces along the normal, *tt rows along the tangential direction. */
-hgks_status hgks_get_tile(const hgks_t* h, int32_t* tn, int32_t* tt);
+/* Launch configuration of the reconstruction + flux kernel in use (fixed by opts.tile or chosen by the
+ * autotuner): out[0] interfaces per tile along the normal, out[1] rows along the tangential direction,
+ * out[2] waves per SIMD the register allocation targets, out[3] the configuration index. */
+hgks_status hgks_get_tile(const hgks_t* h, int32_t* out /* 4 entries */);
 
 void hgks_destroy(hgks_t* h);
 const char* hgks_status_str(hgks_status s);

@@ -135,6 +135,8 @@ static LaunchCtx ctx(hgks* h) {
   L.dim = h->dim;
   L.fp32 = h->fp32;
   L.tile = h->tile;
+  L.prfix = 0;
+  for (auto& q : h->hp) L.prfix |= (q.eqn == HGKS_NS && q.Pr != 1.0);
   L.cell_blocks = h->tab_cell[h->nprob];
   L.ext_blocks = h->tab_ext[h->nprob];
   L.flux_blocks = h->tab_flux[h->tile][h->nprob];
@@ -652,10 +654,12 @@ hgks_status hgks_get_profile(hgks_t* h, double* out) {
   return HGKS_OK;
 }
 
-hgks_status hgks_get_tile(const hgks_t* h, int32_t* tn, int32_t* tt) {
-  if (!h || !tn || !tt) return HGKS_EINVAL;
-  *tn = kTiles[h->tile].tn;
-  *tt = kTiles[h->tile].tt;
+hgks_status hgks_get_tile(const hgks_t* h, int32_t* out) {
+  if (!h || !out) return HGKS_EINVAL;
+  out[0] = kTiles[h->tile].tn;
+  out[1] = kTiles[h->tile].tt;
+  out[2] = kTiles[h->tile].wpe;
+  out[3] = h->tile;
   return HGKS_OK;
 }
 

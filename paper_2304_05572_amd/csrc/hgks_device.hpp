@@ -113,9 +113,17 @@ template <> __device__ inline float dexp<float>(float x) { return __expf(x); }
 template <typename T> __device__ inline T derfc(T x);
 template <> __device__ inline double derfc<double>(double x) { return erfc(x); }
 template <> __device__ inline float derfc<float>(float x) { return erfcf(x); }
-// reciprocal: IEEE in FP64, the hardware approximation (1 ulp) in FP32
+// Reciprocal for the bulk arithmetic (never used by the flag or CFL decisions, which divide exactly):
+// FP64 -- the hardware estimate refined by two Newton steps r <- r + r (1 - x r), within an ulp or two
+// of 1/x for the normal, finite arguments that occur here; FP32 -- the hardware estimate (1 ulp).
 template <typename T> __device__ inline T drcp(T x);
-template <> __device__ inline double drcp<double>(double x) { return 1.0 / x; }
+template <> __device__ inline double drcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 template <> __device__ inline float drcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------------------------
@@ -366,7 +374,8 @@ __device__ inline void solve_slope(const Maxw<T>& g, T Kp2, const T b[4], T a[4]
 }
 
 // Time integrals over [0, delta] of the five coefficient functions of Eq. (equ10) (FP64):
-// 1 - e, (t+tau) e - tau, t - tau + tau e, e, (t+tau) e with e = exp(-t/tau); series below delta/tau = 1.
+// 1 - e, (t+tau) e - tau, t - tau + tau e, e, (t+tau) e with e = exp(-t/tau); for delta/tau < 1 the
+// Taylor series of the same integrals (the closed forms cancel there).
 __device__ inline void time_integrals(double d, double tau, double C[5]) {
   if (tau == 0.0) {
     C[0] = d; C[1] = 0.0; C[2] = 0.5 * d * d; C[3] = 0.0; C[4] = 0.0;
@@ -374,10 +383,9 @@ __device__ inline void time_integrals(double d, double tau, double C[5]) {
   }
   const double x = d / tau;
   if (x < 1.0) {
-    // sum_k (-1)^k x^k/k! weighted per coefficient, Horner-free accumulation of 24 terms
     double tk = 1.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
     for (int k = 1; k <= 24; ++k) {
-      tk *= x / k;
+      tk *= x * drcp<double>(double(k));
       const double sg = (k & 1) ? -tk : tk;
       if (k >= 2) s1 += sg;
       if (k >= 3) { s2 += (k - 2) * sg; s3 -= sg; }
@@ -400,165 +408,215 @@ struct FluxParams {
   int want_F;  // 0: only dF/dt (second stage)
 };
 
-// Gas-kinetic flux at one Gauss point in the local frame (slot 1 = normal momentum): from the
-// reconstructed states W^{l,r} and their normal (x) and tangential (y) derivatives, accumulate
-// wgt * F and wgt * dF/dt (Sec. 2.1-2.2, equilibrium state Eq. (equ46)-(equ47)).
+// Gas-kinetic flux at one Gauss point in the local frame (slot 1 = normal momentum), in two parts so
+// that a caller can reconstruct one side at a time: flux_side() folds one side's reconstructed state
+// W, its normal (x) and tangential (y) derivatives into the accumulators (equilibrium state and its
+// slopes, Eq. (equ46)-(equ47), and the free-transport moments of Eq. (equ10)); flux_finish() builds
+// g0, its slopes, the collision time and the time integrals, and adds wgt * F and wgt * dF/dt
+// (Sec. 2.1-2.2).
 template <typename T>
-__device__ inline void gks_flux_gp(const T Wl[4], const T Wxl[4], const T Wyl[4], const T Wr[4], const T Wxr[4],
-                                   const T Wyr[4], const FluxParams& fp, T wgt, T F[4], T dF[4]) {
-  const T gamma = T(fp.gamma), K = T(fp.K), Kp2 = K + T(2);
-  T Wc[4] = {0, 0, 0, 0}, Wxc[4] = {0, 0, 0, 0}, Wyc[4] = {0, 0, 0, 0};
-  T M4a[4] = {0, 0, 0, 0}, M4b[4] = {0, 0, 0, 0}, M5[4] = {0, 0, 0, 0};
-  T N4b[4] = {0, 0, 0, 0}, N5[4] = {0, 0, 0, 0};  // heat-flux (Prandtl) moments
-  const bool prfix = fp.ns && fp.Pr != 1.0;
+struct FluxAcc {
+  T Wc[4], Wxc[4], Wyc[4];   // equilibrium state and its slopes
+  T M4a[4], M4b[4], M5[4];   // rho <u psi>_h, rho <u A psi>_h, rho <u (a u + b v) psi>_h summed over sides
+  T N4b[4], N5[4];           // the same with one power of u less (Prandtl correction only)
   T p_side[2];
+};
+
+template <typename T>
+__device__ inline void flux_acc_init(FluxAcc<T>& a) {
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const T* W = s ? Wr : Wl;
-    const T* Wx = s ? Wxr : Wxl;
-    const T* Wy = s ? Wyr : Wyl;
-    Maxw<T> g;
-    maxw_prims(W, gamma, g);
-    p_side[s] = T(0.5) * g.rho * drcp(g.lam);
-    const T ir = drcp(g.rho);
-    T b[4], ax[4], ay[4], A[4], t1[4], t2[4];
-    // full-line moments: slopes and the compatibility condition <a1 u + a2 v + A> = 0
-    maxw_moments(g, K, 0);
+  for (int c = 0; c < 4; ++c) {
+    a.Wc[c] = 0; a.Wxc[c] = 0; a.Wyc[c] = 0; a.M4a[c] = 0; a.M4b[c] = 0; a.M5[c] = 0; a.N4b[c] = 0; a.N5[c] = 0;
+  }
+}
+
+// side S = 0: g_l integrated over u > 0; S = 1: g_r over u < 0
+template <int S, bool PRFIX, typename T>
+__device__ inline void flux_side(const T W[4], const T Wx[4], const T Wy[4], T gamma, T K, FluxAcc<T>& acc) {
+  constexpr int s = S;
+  const T Kp2 = K + T(2);
+  Maxw<T> g;
+  maxw_prims(W, gamma, g);
+  acc.p_side[s] = T(0.5) * g.rho * drcp(g.lam);
+  const T ir = drcp(g.rho);
+  T b[4], ax[4], ay[4], A[4], t1[4], t2[4];
+  // full-line moments: slopes and the compatibility condition <a1 u + a2 v + A> = 0
+  maxw_moments(g, K, 0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) b[c] = Wx[c] * ir;
-    solve_slope(g, Kp2, b, ax);
+  for (int c = 0; c < 4; ++c) b[c] = Wx[c] * ir;
+  solve_slope(g, Kp2, b, ax);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) b[c] = Wy[c] * ir;
-    solve_slope(g, Kp2, b, ay);
+  for (int c = 0; c < 4; ++c) b[c] = Wy[c] * ir;
+  solve_slope(g, Kp2, b, ay);
+  mom_a<1, 0>(g, ax, t1);
+  mom_a<0, 1>(g, ay, t2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) b[c] = -(t1[c] + t2[c]);
+  solve_slope(g, Kp2, b, A);
+  // half-line moments
+  maxw_moments(g, K, s ? -1 : 1);
+  const T rho = g.rho;
+  mom_psi<0, 0>(g, t1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc.Wc[c] += rho * t1[c];
+  mom_a<0, 0>(g, ax, t1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc.Wxc[c] += rho * t1[c];
+  mom_a<0, 0>(g, ay, t1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc.Wyc[c] += rho * t1[c];
+  mom_psi<1, 0>(g, t1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc.M4a[c] += rho * t1[c];
+  mom_a<1, 0>(g, A, t1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc.M4b[c] += rho * t1[c];
+  mom_a<2, 0>(g, ax, t1);
+  mom_a<1, 1>(g, ay, t2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc.M5[c] += rho * (t1[c] + t2[c]);
+  if (PRFIX) {
+    mom_a<0, 0>(g, A, t1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc.N4b[c] += rho * t1[c];
     mom_a<1, 0>(g, ax, t1);
     mom_a<0, 1>(g, ay, t2);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) b[c] = -(t1[c] + t2[c]);
-    solve_slope(g, Kp2, b, A);
-    // half-line moments: g_l over u > 0, g_r over u < 0
-    maxw_moments(g, K, s ? -1 : 1);
-    const T rho = g.rho;
-    mom_psi<0, 0>(g, t1);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Wc[c] += rho * t1[c];
-    mom_a<0, 0>(g, ax, t1);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Wxc[c] += rho * t1[c];
-    mom_a<0, 0>(g, ay, t1);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Wyc[c] += rho * t1[c];
-    mom_psi<1, 0>(g, t1);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) M4a[c] += rho * t1[c];
-    mom_a<1, 0>(g, A, t1);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) M4b[c] += rho * t1[c];
-    mom_a<2, 0>(g, ax, t1);
-    mom_a<1, 1>(g, ay, t2);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) M5[c] += rho * (t1[c] + t2[c]);
-    if (prfix) {
-      mom_a<0, 0>(g, A, t1);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) N4b[c] += rho * t1[c];
-      mom_a<1, 0>(g, ax, t1);
-      mom_a<0, 1>(g, ay, t2);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) N5[c] += rho * (t1[c] + t2[c]);
-    }
+    for (int c = 0; c < 4; ++c) acc.N5[c] += rho * (t1[c] + t2[c]);
   }
-  // equilibrium g0 at the interface and its slopes
+}
+
+// Coefficients that turn a moment vector of one term of Eq. (equ10) into its share of F and dF/dt.
+template <typename T>
+struct TermCoef {
+  T f[5], d[5], f4t, d4t;
+};
+
+template <bool PRFIX, typename T>
+__device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt, T F[4], T dF[4]) {
+  const T gamma = T(fp.gamma), K = T(fp.K), Kp2 = K + T(2);
+  // equilibrium g0 at the interface
   Maxw<T> g0;
-  maxw_prims(Wc, gamma, g0);
-  maxw_moments(g0, K, 0);
-  const T ir0 = drcp(g0.rho);
-  T b[4], a0[4], b0[4], A0[4], t1[4], t2[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) b[c] = Wxc[c] * ir0;
-  solve_slope(g0, Kp2, b, a0);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) b[c] = Wyc[c] * ir0;
-  solve_slope(g0, Kp2, b, b0);
-  mom_a<1, 0>(g0, a0, t1);
-  mom_a<0, 1>(g0, b0, t2);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) b[c] = -(t1[c] + t2[c]);  // = <(a0 u + b0 v) psi> with the opposite sign
-  solve_slope(g0, Kp2, b, A0);
-  T M1[4], M2[4], M3[4];
-  mom_psi<1, 0>(g0, M1);
-  mom_a<2, 0>(g0, a0, t1);
-  mom_a<1, 1>(g0, b0, t2);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    M1[c] *= g0.rho;
-    M2[c] = g0.rho * (t1[c] + t2[c]);
-  }
-  mom_a<1, 0>(g0, A0, M3);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) M3[c] *= g0.rho;
+  maxw_prims(acc.Wc, gamma, g0);
 
-  // collision time (Sec. 3)
-  const double pl = double(p_side[0]), pr = double(p_side[1]);
-  const double jump = fabs((pl - pr) / (pl + pr));
+  // collision time (Sec. 3) and the time-integral combinations (FP64):
+  // F = (4 F(dt/2) - F(dt)) / dt, dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2, term by term
+  TermCoef<T> tc;
   double tau;
-  if (fp.ns) {
-    const double p0 = double(T(0.5) * g0.rho * drcp(g0.lam));
-    tau = fp.mu / p0 + fp.c2 * jump * fp.dt;
-  } else {
-    tau = fp.c1 * fp.dt + fp.c2 * jump * fp.dt;
+  {
+    const double pl = double(acc.p_side[0]), pr = double(acc.p_side[1]);
+    const double jump = fabs((pl - pr) / (pl + pr));
+    if (fp.ns) {
+      const double p0 = double(T(0.5) * g0.rho * drcp(g0.lam));
+      tau = fp.mu / p0 + fp.c2 * jump * fp.dt;
+    } else {
+      tau = fp.c1 * fp.dt + fp.c2 * jump * fp.dt;
+    }
+    double Cd[5], Ch[5];
+    time_integrals(fp.dt, tau, Cd);
+    time_integrals(0.5 * fp.dt, tau, Ch);
+    const double idt = 1.0 / fp.dt, idt2 = 4.0 * idt * idt;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      tc.f[m] = fp.want_F ? wgt * T((4.0 * Ch[m] - Cd[m]) * idt) : T(0);
+      tc.d[m] = wgt * T((Cd[m] - 2.0 * Ch[m]) * idt2);
+    }
+    tc.f4t = fp.want_F ? wgt * T(tau * (4.0 * Ch[3] - Cd[3]) * idt) : T(0);
+    tc.d4t = wgt * T(tau * (Cd[3] - 2.0 * Ch[3]) * idt2);
   }
+  // heat flux q = int (u-U0)((u-U0)^2+(v-V0)^2+xi^2)/2 f of one term, written through its flux moments
+  // (u psi) M and conserved moments (psi) N; the energy flux of the term gains (1/Pr - 1) q
+  const T U0 = g0.U, V0 = g0.V;
+  const T cA = T(1.5) * U0 * U0 + T(0.5) * V0 * V0, cB = T(0.5) * U0 * (U0 * U0 + V0 * V0);
+  const T kpr = T(1.0 / fp.Pr - 1.0);
+  auto heat = [&](const T M[4], const T N[4]) -> T {
+    return M[3] - U0 * M[1] - V0 * M[2] + cA * M[0] + U0 * V0 * N[2] - U0 * N[3] - cB * N[0];
+  };
+  auto fold = [&](const T M[4], T cf, T cd) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      F[c] += cf * M[c];
+      dF[c] += cd * M[c];
+    }
+  };
+  // free-transport terms of both sides: C4 (M4a - tau M4b) - C5 M5
+  if (PRFIX) {
+    acc.M4a[3] += kpr * heat(acc.M4a, acc.Wc);
+    acc.M4b[3] += kpr * heat(acc.M4b, acc.N4b);
+    acc.M5[3] += kpr * heat(acc.M5, acc.N5);
+  }
+  fold(acc.M4a, tc.f[3], tc.d[3]);
+  fold(acc.M4b, -tc.f4t, -tc.d4t);
+  fold(acc.M5, -tc.f[4], -tc.d[4]);
 
-  if (prfix) {
-    // heat flux q = int (u-U0)((u-U0)^2+(v-V0)^2+xi^2)/2 f, written through the flux moments (u psi)
-    // and the conserved moments (psi) of every term of f; the energy flux gains (1/Pr - 1) q.
-    const T U0 = g0.U, V0 = g0.V;
-    const T cA = T(1.5) * U0 * U0 + T(0.5) * V0 * V0, cB = T(0.5) * U0 * (U0 * U0 + V0 * V0);
-    const T kpr = T(1.0 / fp.Pr - 1.0);
-    // conserved moments of each term: N1 = rho0 <psi>, N2 = rho0 <(a0 u + b0 v) psi> = -rho0 <A0 psi>,
-    // N3 = rho0 <A0 psi>, N4a = Wc, N4b, N5
-    T N3[4];
-    mom_a<0, 0>(g0, A0, N3);
-    T N1[4];
-    mom_psi<0, 0>(g0, N1);
+  // equilibrium terms: C1 rho0 <u psi> + C2 rho0 <u (a0 u + b0 v) psi> + C3 rho0 <u A0 psi>
+  maxw_moments(g0, K, 0);
+  const T ir0 = drcp(g0.rho), r0 = g0.rho;
+  T b[4], a0[4], t1[4], t2[4], rhs[4];
+  {
+    T M[4];
+    mom_psi<1, 0>(g0, M);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) { N1[c] *= g0.rho; N3[c] *= g0.rho; }
-#define QOF(Mv_, Nv_) (Mv_[3] - U0 * Mv_[1] - V0 * Mv_[2] + cA * Mv_[0] + U0 * V0 * Nv_[2] - U0 * Nv_[3] - cB * Nv_[0])
-    const T q1 = QOF(M1, N1);
-    const T q2 = M2[3] - U0 * M2[1] - V0 * M2[2] + cA * M2[0] - (U0 * V0 * N3[2] - U0 * N3[3] - cB * N3[0]);
-    const T q3 = QOF(M3, N3);
-    const T q4a = QOF(M4a, Wc);
-    const T q4b = QOF(M4b, N4b);
-    const T q5 = QOF(M5, N5);
-#undef QOF
-    M1[3] += kpr * q1;
-    M2[3] += kpr * q2;
-    M3[3] += kpr * q3;
-    M4a[3] += kpr * q4a;
-    M4b[3] += kpr * q4b;
-    M5[3] += kpr * q5;
+    for (int c = 0; c < 4; ++c) M[c] *= r0;
+    if (PRFIX) {
+      T N[4];
+      mom_psi<0, 0>(g0, N);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) N[c] *= r0;
+      M[3] += kpr * heat(M, N);
+    }
+    fold(M, tc.f[0], tc.d[0]);
   }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) b[c] = acc.Wxc[c] * ir0;
+  solve_slope(g0, Kp2, b, a0);
+  mom_a<1, 0>(g0, a0, rhs);
+  mom_a<2, 0>(g0, a0, t2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) b[c] = acc.Wyc[c] * ir0;
+  solve_slope(g0, Kp2, b, a0);  // a0 now holds the y-slope b0
+  mom_a<0, 1>(g0, a0, t1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) rhs[c] = -(rhs[c] + t1[c]);  // <A0 psi> = -<(a0 u + b0 v) psi>
+  mom_a<1, 1>(g0, a0, t1);
+  {
+    T M[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) M[c] = r0 * (t1[c] + t2[c]);
+    if (PRFIX) {
+      T N[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) N[c] = -r0 * rhs[c];  // rho0 <(a0 u + b0 v) psi>
+      M[3] += kpr * heat(M, N);
+    }
+    fold(M, tc.f[1], tc.d[1]);
+  }
+  solve_slope(g0, Kp2, rhs, a0);  // a0 now holds A0
+  {
+    T M[4];
+    mom_a<1, 0>(g0, a0, M);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) M[c] *= r0;
+    if (PRFIX) {
+      T N[4];
+      mom_a<0, 0>(g0, a0, N);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) N[c] *= r0;
+      M[3] += kpr * heat(M, N);
+    }
+    fold(M, tc.f[2], tc.d[2]);
+  }
+}
 
-  double Cd[5], Ch[5];
-  time_integrals(fp.dt, tau, Cd);
-  time_integrals(0.5 * fp.dt, tau, Ch);
-  const double idt = 1.0 / fp.dt;
-  if (fp.want_F) {
-    // F = (4 F(dt/2) - F(dt)) / dt
-    const T f1 = T((4.0 * Ch[0] - Cd[0]) * idt), f2 = T((4.0 * Ch[1] - Cd[1]) * idt);
-    const T f3 = T((4.0 * Ch[2] - Cd[2]) * idt), f4 = T((4.0 * Ch[3] - Cd[3]) * idt);
-    const T f5 = T((4.0 * Ch[4] - Cd[4]) * idt), f4t = T(tau * (4.0 * Ch[3] - Cd[3]) * idt);
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      F[c] += wgt * (f1 * M1[c] + f2 * M2[c] + f3 * M3[c] + f4 * M4a[c] - f4t * M4b[c] - f5 * M5[c]);
-  }
-  // dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2
-  const double idt2 = 4.0 * idt * idt;
-  const T d1 = T((Cd[0] - 2.0 * Ch[0]) * idt2), d2 = T((Cd[1] - 2.0 * Ch[1]) * idt2);
-  const T d3 = T((Cd[2] - 2.0 * Ch[2]) * idt2), d4 = T((Cd[3] - 2.0 * Ch[3]) * idt2);
-  const T d5 = T((Cd[4] - 2.0 * Ch[4]) * idt2), d4t = T(tau * (Cd[3] - 2.0 * Ch[3]) * idt2);
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-    dF[c] += wgt * (d1 * M1[c] + d2 * M2[c] + d3 * M3[c] + d4 * M4a[c] - d4t * M4b[c] - d5 * M5[c]);
+// Whole Gauss-point flux from both reconstructed sides at once.
+template <bool PRFIX, typename T>
+__device__ inline void gks_flux_gp(const T Wl[4], const T Wxl[4], const T Wyl[4], const T Wr[4], const T Wxr[4],
+                                   const T Wyr[4], const FluxParams& fp, T wgt, T F[4], T dF[4]) {
+  FluxAcc<T> acc;
+  flux_acc_init(acc);
+  flux_side<0, PRFIX>(Wl, Wxl, Wyl, T(fp.gamma), T(fp.K), acc);
+  flux_side<1, PRFIX>(Wr, Wxr, Wyr, T(fp.gamma), T(fp.K), acc);
+  flux_finish<PRFIX>(acc, fp, wgt, F, dF);
 }
 
 }  // namespace hk

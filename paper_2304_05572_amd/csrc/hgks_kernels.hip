@@ -204,6 +204,46 @@ __global__ void k_clear_counts(const ProbDev* __restrict__ probs, int nprob) {
   }
 }
 
+// Tangential reconstruction (Sec. 2.3.3, Step 2) of side s of interface column k at Gauss point gp from
+// the line averages of rows tt..tt+4 (value line W^s and normal-slope line W^s_x): values at the Gauss
+// point, tangential slope of W^s, value of W^s_x. Linear quartic per component, or WENO-AO in the
+// tangential characteristic variables about the side's own centre-segment state when flagged.
+template <typename T, int TN, int R>
+__device__ inline void tangential_side(const T (*sNR)[TN][16], int tt, int k, int s, int ft, int gp, T gam, T ghi,
+                                       T glo, T eps, T iht, T Ws[4], T Wxs[4], T Wys[4]) {
+  const int ov = 8 * s, od = 8 * s + 4;
+  if (ft) {
+    CharMat<T> m;
+    T own[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) own[v] = sNR[tt + 2][k][ov + v];
+    char_matrices(own, gam, 2, m);
+    T qv[5][4], qd[5][4], val[4], der[4];
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { qv[r][v] = sNR[tt + r][k][ov + v]; qd[r][v] = sNR[tt + r][k][od + v]; }
+    ao_vector(qv, m, 2 + gp, ghi, glo, eps, val, der);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { Ws[v] = val[v]; Wys[v] = der[v] * iht; }
+    ao_vector(qd, m, 2 + gp, ghi, glo, eps, val, der);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Wxs[v] = val[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      T q[5], qx[5], vv, dd, vx, dx_;
+#pragma unroll
+      for (int r = 0; r < 5; ++r) { q[r] = sNR[tt + r][k][ov + v]; qx[r] = sNR[tt + r][k][od + v]; }
+      gauss_linear(q, gp, vv, dd);
+      gauss_linear(qx, gp, vx, dx_);
+      Ws[v] = vv;
+      Wys[v] = dd * iht;
+      Wxs[v] = vx;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Fused reconstruction + gas-kinetic flux. A block owns TN interfaces along the normal direction of
 // TT rows (2D) and stages in LDS:
@@ -214,8 +254,8 @@ __global__ void k_clear_counts(const ProbDev* __restrict__ probs, int nprob) {
 // points, the equilibrium state and the flux (Sec. 2.3.3 Steps 1-3, Sec. 2.1-2.2).
 // Frame: slot 1 holds the normal momentum, slot 2 the tangential one (y-interfaces swap U and V).
 // ---------------------------------------------------------------------------------------------
-template <typename T, int TN, int TT, int DIM>
-__global__ void __launch_bounds__(TN * TT) k_flux(const ProbDev* __restrict__ probs,
+template <typename T, int TN, int TT, int DIM, bool PRFIX, int WPE>
+__global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WPE))) k_flux(const ProbDev* __restrict__ probs,
                                                   const TimeDev* __restrict__ ts,
                                                   const int* __restrict__ off, int nprob, int stage) {
   constexpr int R = (DIM == 2) ? TT + 4 : 1;  // rows with halo
@@ -341,50 +381,24 @@ __global__ void __launch_bounds__(TN * TT) k_flux(const ProbDev* __restrict__ pr
       Wl[v] = sNR[0][k][v]; Wxl[v] = sNR[0][k][4 + v];
       Wr[v] = sNR[0][k][8 + v]; Wxr[v] = sNR[0][k][12 + v];
     }
-    gks_flux_gp(Wl, Wxl, z, Wr, Wxr, z, fp, T(1), F, dF);
+    gks_flux_gp<PRFIX>(Wl, Wxl, z, Wr, Wxr, z, fp, T(1), F, dF);
   } else {
-    const int ftl = (sF[tt + 2][k] >> 1) & 1, ftr = (sF[tt + 2][k + 1] >> 1) & 1;
     const T iht = T(1.0 / ht);
+#pragma unroll 1
     for (int gp = 0; gp < 2; ++gp) {
-      T Ws[2][4], Wxs[2][4], Wys[2][4];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int ft = s ? ftr : ftl;
-        const int ov = 8 * s, od = 8 * s + 4;
-        if (ft) {
-          // characteristic variables of the tangential direction about this side's own line-averaged
-          // state of the centre segment (the state of the cell being reconstructed)
-          CharMat<T> m;
-          T own[4];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) own[v] = sNR[tt + 2][k][ov + v];
-          char_matrices(own, gam, 2, m);
-          T qv[5][4], qd[5][4], val[4], der[4];
-#pragma unroll
-          for (int r = 0; r < 5; ++r)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) { qv[r][v] = sNR[tt + r][k][ov + v]; qd[r][v] = sNR[tt + r][k][od + v]; }
-          ao_vector(qv, m, 2 + gp, ghi, glo, eps, val, der);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) { Ws[s][v] = val[v]; Wys[s][v] = der[v] * iht; }
-          ao_vector(qd, m, 2 + gp, ghi, glo, eps, val, der);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) Wxs[s][v] = val[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            T q[5], qx[5], vv, dd, vx, dx_;
-#pragma unroll
-            for (int r = 0; r < 5; ++r) { q[r] = sNR[tt + r][k][ov + v]; qx[r] = sNR[tt + r][k][od + v]; }
-            gauss_linear(q, gp, vv, dd);
-            gauss_linear(qx, gp, vx, dx_);
-            Ws[s][v] = vv;
-            Wys[s][v] = dd * iht;
-            Wxs[s][v] = vx;
-          }
-        }
-      }
-      gks_flux_gp(Ws[0], Wxs[0], Wys[0], Ws[1], Wxs[1], Wys[1], fp, T(0.5), F, dF);
+      FluxAcc<T> acc;
+      flux_acc_init(acc);
+      T Ws[4], Wxs[4], Wys[4];
+      // tangential reconstruction of one side at this Gauss point, then its share of the flux
+      tangential_side<T, TN, R>(sNR, tt, k, 0, (sF[tt + 2][k] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
+      __builtin_amdgcn_sched_barrier(0);
+      flux_side<0, PRFIX>(Ws, Wxs, Wys, gam, T(P.K), acc);
+      __builtin_amdgcn_sched_barrier(0);
+      tangential_side<T, TN, R>(sNR, tt, k, 1, (sF[tt + 2][k + 1] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
+      __builtin_amdgcn_sched_barrier(0);
+      flux_side<1, PRFIX>(Ws, Wxs, Wys, gam, T(P.K), acc);
+      __builtin_amdgcn_sched_barrier(0);
+      flux_finish<PRFIX>(acc, fp, T(0.5), F, dF);
     }
   }
 
@@ -493,38 +507,42 @@ void launch_flags(const LaunchCtx& L, int stage_state, int count) {
                      stage_state, count);
 }
 
-template <typename T, int TN, int TT>
-static void flux_variant(const LaunchCtx& L, int stage) {
+template <typename T, int TN, int TT, bool PR, int WPE>
+static void flux_variant_pr(const LaunchCtx& L, int stage) {
   if (L.dim == 1)
-    hipLaunchKernelGGL((k_flux<T, TN * TT, 1, 1>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream, L.probs,
-                       L.ts, L.off_flux, L.nprob, stage);
+    hipLaunchKernelGGL((k_flux<T, TN * TT, 1, 1, PR, WPE>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream,
+                       L.probs, L.ts, L.off_flux, L.nprob, stage);
   else
-    hipLaunchKernelGGL((k_flux<T, TN, TT, 2>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream, L.probs, L.ts,
-                       L.off_flux, L.nprob, stage);
+    hipLaunchKernelGGL((k_flux<T, TN, TT, 2, PR, WPE>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream, L.probs,
+                       L.ts, L.off_flux, L.nprob, stage);
 }
 
-// tile shapes (interfaces along the normal x rows along the tangential direction)
-const TileShape kTiles[kNumTiles] = {{16, 16}, {32, 8}, {64, 4}, {16, 8}, {8, 8}};
+// the Prandtl-number correction is compiled in only for launches that need it (NS with Pr != 1)
+template <typename T, int TN, int TT, int WPE>
+static void flux_variant(const LaunchCtx& L, int stage) {
+  if (L.prfix) flux_variant_pr<T, TN, TT, true, WPE>(L, stage);
+  else flux_variant_pr<T, TN, TT, false, WPE>(L, stage);
+}
+
+// launch configurations: tile shape and the waves-per-SIMD target the register allocator works to
+// (1: no target; 2 or 3: spill what does not fit rather than lose occupancy)
+const TileShape kTiles[kNumTiles] = {{8, 8, 1}, {8, 8, 2}, {16, 8, 1}, {16, 8, 2}, {16, 16, 2}, {8, 8, 3}};
+
+template <typename T>
+static void launch_flux_t(const LaunchCtx& L, int stage) {
+  switch (L.tile) {
+    case 0: flux_variant<T, 8, 8, 1>(L, stage); break;
+    case 1: flux_variant<T, 8, 8, 2>(L, stage); break;
+    case 2: flux_variant<T, 16, 8, 1>(L, stage); break;
+    case 3: flux_variant<T, 16, 8, 2>(L, stage); break;
+    case 4: flux_variant<T, 16, 16, 2>(L, stage); break;
+    default: flux_variant<T, 8, 8, 3>(L, stage); break;
+  }
+}
 
 void launch_flux(const LaunchCtx& L, int stage) {
-  const int t = L.tile;
-  if (L.fp32) {
-    switch (t) {
-      case 0: flux_variant<float, 16, 16>(L, stage); break;
-      case 1: flux_variant<float, 32, 8>(L, stage); break;
-      case 2: flux_variant<float, 64, 4>(L, stage); break;
-      case 3: flux_variant<float, 16, 8>(L, stage); break;
-      default: flux_variant<float, 8, 8>(L, stage); break;
-    }
-  } else {
-    switch (t) {
-      case 0: flux_variant<double, 16, 16>(L, stage); break;
-      case 1: flux_variant<double, 32, 8>(L, stage); break;
-      case 2: flux_variant<double, 64, 4>(L, stage); break;
-      case 3: flux_variant<double, 16, 8>(L, stage); break;
-      default: flux_variant<double, 8, 8>(L, stage); break;
-    }
-  }
+  if (L.fp32) launch_flux_t<float>(L, stage);
+  else launch_flux_t<double>(L, stage);
 }
 
 void launch_update(const LaunchCtx& L, int stage) {

@@ -8,8 +8,9 @@ namespace hk {
 
 struct TileShape {
   int tn, tt;  // interfaces along the normal, rows along the tangential direction (2D)
+  int wpe;     // waves per SIMD the register allocation targets (1: unconstrained)
 };
-constexpr int kNumTiles = 5;
+constexpr int kNumTiles = 6;
 extern const TileShape kTiles[kNumTiles];
 
 struct LaunchCtx {
@@ -20,6 +21,7 @@ struct LaunchCtx {
   const int* off_ext;    // prefix sums of 256-cell blocks of the extended (flag) range
   const int* off_flux;   // prefix sums of flux tiles (x then y) for the current tile shape
   int nprob, dim, fp32, tile;
+  int prfix;             // 1 if any problem is Navier-Stokes with Pr != 1
   int cell_blocks, ext_blocks, flux_blocks;
 };
 

@@ -130,7 +130,7 @@ def lib():
             "hgks_debug_flags": (i32, [vp, i32, vp, vp]),
             "hgks_debug_stage_fluxes": (i32, [vp, i32, d, vp, vp, vp, vp]),
             "hgks_get_stats": (i32, [vp, i32, vp]),
-            "hgks_get_tile": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+            "hgks_get_tile": (i32, [vp, vp]),
             "hgks_get_profile": (i32, [vp, vp]),
             "hgks_destroy": (None, [vp]),
             "hgks_status_str": (C.c_char_p, [i32]),
@@ -224,9 +224,10 @@ def hgks_get_stats(h, prob: int):
 
 
 def hgks_get_tile(h):
-    tn, tt = C.c_int32(), C.c_int32()
-    _check(lib().hgks_get_tile(h, C.byref(tn), C.byref(tt)), "hgks_get_tile")
-    return tn.value, tt.value
+    """(interfaces along the normal, rows along the tangential direction, waves-per-SIMD target, index)."""
+    out = np.zeros(4, np.int32)
+    _check(lib().hgks_get_tile(h, out.ctypes.data_as(C.c_void_p)), "hgks_get_tile")
+    return tuple(int(x) for x in out)
 
 
 def hgks_get_profile(h):

@@ -107,21 +107,15 @@ def quadrants(nx: int, ny: int, states, gamma=GAMMA, xs=0.5, ys=0.5):
     return prim_to_cons(rho, u, v, p, gamma)
 
 
-def _wave_curve(p, rho_k, p_k, gamma=GAMMA):
-    """Velocity change f(p) and density behind a 1D wave of pressure p facing the state (rho_k, p_k):
-    Rankine-Hugoniot for p > p_k (shock), isentrope for p <= p_k (rarefaction)."""
-    a_k = math.sqrt(gamma * p_k / rho_k)
-    if p > p_k:
-        A = 2.0 / ((gamma + 1.0) * rho_k)
-        B = (gamma - 1.0) / (gamma + 1.0) * p_k
-        f = (p - p_k) * math.sqrt(A / (p + B))
-        r = p / p_k
-        g = (gamma - 1.0) / (gamma + 1.0)
-        rho = rho_k * (r + g) / (g * r + 1.0)
-    else:
-        f = 2.0 * a_k / (gamma - 1.0) * ((p / p_k) ** ((gamma - 1.0) / (2.0 * gamma)) - 1.0)
-        rho = rho_k * (p / p_k) ** (1.0 / gamma)
-    return f, rho
+def _shock_velocity_jump(p, rho_k, p_k, gamma=GAMMA):
+    """Velocity change across a shock of pressure p > p_k running into the state (rho_k, p_k), and the
+    post-shock density (Rankine-Hugoniot)."""
+    A = 2.0 / ((gamma + 1.0) * rho_k)
+    B = (gamma - 1.0) / (gamma + 1.0) * p_k
+    f = (p - p_k) * math.sqrt(A / (p + B))
+    r = p / p_k
+    g = (gamma - 1.0) / (gamma + 1.0)
+    return f, rho_k * (r + g) / (g * r + 1.0)
 
 
 RANGES = dict(rho=(0.1, 1.5), p=(0.03, 1.5), vel=1.2)
@@ -138,110 +132,100 @@ def _in_range(states):
     return True
 
 
-def random_quadrant_states(rng: np.random.Generator, max_tries: int = 200):
-    """Four quadrant states with one elementary wave (shock, rarefaction or contact) per edge.
+def _edges_nontrivial(states, min_ratio=1.25, min_dv=0.15):
+    """Every edge (1-2, 2-3, 3-4, 4-1) carries a visible jump."""
+    for a, b in ((0, 1), (1, 2), (2, 3), (3, 0)):
+        ra, ua, va, pa = states[a]
+        rb, ub, vb, pb = states[b]
+        rr = max(ra, rb) / min(ra, rb)
+        pr = max(pa, pb) / min(pa, pb)
+        if rr < min_ratio and pr < min_ratio and abs(ua - ub) < min_dv and abs(va - vb) < min_dv:
+            return False
+    return True
 
-    State 1 is drawn uniformly from the ranges; states 2 (x-wave from 1) and 4 (y-wave from 1) follow
-    from a drawn wave type and strength along the wave curves; state 3 must then be reached from 2 by a
-    y-wave and from 4 by an x-wave. The free strengths are fixed by requiring the two routes to 3 to
-    agree in pressure and density (solved by a damped Newton iteration). Draws that do not close, or
-    leave the ranges, are rejected; after max_tries the always-closing all-contact family is used
-    (common pressure, u1=u2, u3=u4, v2=v3, v4=v1, free densities)."""
+
+def _symmetry(states, k):
+    """Apply one of the dihedral symmetries of the square to a quadrant configuration (quadrants
+    1 = upper right, 2 = upper left, 3 = lower left, 4 = lower right)."""
+    s1, s2, s3, s4 = [list(x) for x in states]
+    if k & 1:  # mirror x -> 1 - x: 1 <-> 2, 3 <-> 4, u -> -u
+        s1, s2, s3, s4 = s2, s1, s4, s3
+        for s in (s1, s2, s3, s4):
+            s[1] = -s[1]
+    if k & 2:  # mirror y -> 1 - y: 1 <-> 4, 2 <-> 3, v -> -v
+        s1, s2, s3, s4 = s4, s3, s2, s1
+        for s in (s1, s2, s3, s4):
+            s[2] = -s[2]
+    if k & 4:  # transpose x <-> y: 2 <-> 4, u <-> v
+        s1, s2, s3, s4 = s1, s4, s3, s2
+        for s in (s1, s2, s3, s4):
+            s[1], s[2] = s[2], s[1]
+    return [tuple(s) for s in (s1, s2, s3, s4)]
+
+
+def random_quadrant_states(rng: np.random.Generator, max_tries: int = 1000):
+    """Four quadrant states with exactly one elementary wave (shock, rarefaction or contact) on each
+    edge, built exactly in one of four families and then turned by a random symmetry of the square:
+      R4   four rarefactions: one isentrope, c3 = c2 + c4 - c1, velocities from the Riemann invariants
+      J4   four contacts (slip lines): common pressure, u1 = u2, u3 = u4, v2 = v3, v4 = v1
+      J2R2 contacts on the vertical edges, rarefactions on the horizontal ones
+      J2S2 contacts on the vertical edges, shocks on the horizontal ones (Rankine-Hugoniot)
+    Draws outside rho in [0.1, 1.5], p in [0.03, 1.5], |u|, |v| <= 1.2, or with a near-trivial edge, are
+    rejected. Quadrants: 1 = (x>.5, y>.5), 2 = (x<.5, y>.5), 3 = (x<.5, y<.5), 4 = (x>.5, y<.5)."""
     g = GAMMA
+    k2 = 2.0 / (g - 1.0)
     lo_r, hi_r = RANGES["rho"]
     lo_p, hi_p = RANGES["p"]
-    vmax = RANGES["vel"]
+    vm = RANGES["vel"]
     for _ in range(max_tries):
-        rho1 = rng.uniform(lo_r, hi_r)
-        p1 = rng.uniform(lo_p, hi_p)
-        u1 = rng.uniform(-vmax, vmax)
-        v1 = rng.uniform(-vmax, vmax)
-        # wave family per edge: +1 / -1 (right- / left-facing acoustic wave) or 0 (contact)
-        fam = rng.choice([-1, 0, 1], size=4)
-
-        def x_wave(state_r, p_l, family):
-            """Left state across a vertical edge, given the right state (rho, u, v, p)."""
-            rho_r, u_r, v_r, p_r = state_r
-            if family == 0:
-                return None
-            f, rho_l = _wave_curve(p_l, rho_r, p_r)
-            # family +1 (wave moves right, state_r ahead): u_l = u_r + f ; family -1: mirror with state_l ahead
-            return (rho_l, u_r + f, v_r, p_l) if family > 0 else None
-
-        # Closing an arbitrary acoustic-wave loop is a two-parameter root find; we use the simplest
-        # robust construction: pick the edge types, then solve for the pressures numerically.
-        def close(params):
-            p2, p4 = params
-            s1 = (rho1, u1, v1, p1)
-            # edge 1-2 (x-wave, state 2 on the left): right-facing wave, state 1 ahead
-            f12, r2 = _wave_curve(p2, rho1, p1)
-            s2 = (r2, u1 + f12, v1, p2)
-            # edge 1-4 (y-wave, state 4 below): upward-facing wave, state 1 ahead
-            f14, r4 = _wave_curve(p4, rho1, p1)
-            s4 = (r4, u1, v1 + f14, p4)
-            return s1, s2, s4
-
-        def residual(params):
-            s1, s2, s4 = close(params)
-            # state 3: from 2 by a y-wave (u3 = u2), from 4 by an x-wave (v3 = v4)
-            # pressure p3 from the y-route: v3 = v2 + f(p3; state 2) must equal v4
-            # and from the x-route:           u3 = u4 + f(p3; state 4) must equal u2
-            def solve_p(target, base_vel, rho_k, p_k):
-                lo, hi = 1e-6, 50.0
-                flo = base_vel + _wave_curve(lo, rho_k, p_k)[0] - target
-                fhi = base_vel + _wave_curve(hi, rho_k, p_k)[0] - target
-                if flo * fhi > 0:
-                    return None
-                for _ in range(100):
-                    mid = 0.5 * (lo + hi)
-                    fm = base_vel + _wave_curve(mid, rho_k, p_k)[0] - target
-                    if (fm > 0) == (fhi > 0):
-                        hi, fhi = mid, fm
-                    else:
-                        lo, flo = mid, fm
-                return 0.5 * (lo + hi)
-            py = solve_p(s4[2], s2[2], s2[0], s2[3])
-            px = solve_p(s2[1], s4[1], s4[0], s4[3])
-            if py is None or px is None:
-                return None
-            ry = _wave_curve(py, s2[0], s2[3])[1]
-            rx = _wave_curve(px, s4[0], s4[3])[1]
-            return np.array([math.log(py / px), math.log(ry / rx)]), (s1, s2, (ry, s2[1], s4[2], py), s4)
-
-        x = np.array([rng.uniform(lo_p, hi_p), rng.uniform(lo_p, hi_p)])
-        ok = False
-        for _it in range(40):
-            res = residual(x)
-            if res is None:
-                break
-            r, states = res
-            if np.max(np.abs(r)) < 1e-12:
-                ok = True
-                break
-            J = np.zeros((2, 2))
-            for k in range(2):
-                dx = np.zeros(2)
-                dx[k] = 1e-7 * x[k]
-                rr = residual(x + dx)
-                if rr is None:
-                    break
-                J[:, k] = (rr[0] - r) / dx[k]
-            else:
-                try:
-                    step = np.linalg.solve(J, -r)
-                except np.linalg.LinAlgError:
-                    break
-                x = np.clip(x + 0.7 * step, 1e-4, 50.0)
+        fam = int(rng.integers(4))
+        if fam == 0:  # R4
+            rho1, p1 = rng.uniform(0.5, hi_r), rng.uniform(0.4, hi_p)
+            u1, v1 = rng.uniform(-0.6, 0.6, 2)
+            c1 = math.sqrt(g * p1 / rho1)
+            c2, c4 = c1 * rng.uniform(0.7, 0.95, 2)
+            c3 = c2 + c4 - c1
+            if c3 <= 0.3 * c1:
                 continue
-            break
-        if ok and _in_range(states) and fam is not None:
+            ent = p1 / rho1 ** g
+
+            def st(c, u, v):
+                p = p1 * (c / c1) ** (2.0 * g / (g - 1.0))
+                return ((p / ent) ** (1.0 / g), u, v, p)
+
+            u2 = u1 + k2 * (c2 - c1)
+            v4 = v1 + k2 * (c4 - c1)
+            states = [(rho1, u1, v1, p1), st(c2, u2, v1), st(c3, u2, v4), st(c4, u1, v4)]
+        elif fam == 1:  # J4
+            p = rng.uniform(lo_p, hi_p)
+            r = rng.uniform(lo_r, hi_r, 4)
+            u12, u34, v14, v23 = rng.uniform(-vm, vm, 4)
+            states = [(r[0], u12, v14, p), (r[1], u12, v23, p), (r[2], u34, v23, p), (r[3], u34, v14, p)]
+        elif fam == 2:  # J2R2
+            pa = rng.uniform(0.3, hi_p)
+            pb = pa * rng.uniform(0.2, 0.7)
+            r1, r2 = rng.uniform(0.3, hi_r, 2)
+            u = rng.uniform(-vm, vm)
+            v1, v2 = rng.uniform(-vm, vm, 2)
+            f = (pb / pa) ** (1.0 / g)
+            r4, r3 = r1 * f, r2 * f
+            c = lambda r, p: math.sqrt(g * p / r)
+            v4 = v1 + k2 * (c(r4, pb) - c(r1, pa))
+            v3 = v2 + k2 * (c(r3, pb) - c(r2, pa))
+            states = [(r1, u, v1, pa), (r2, u, v2, pa), (r3, u, v3, pb), (r4, u, v4, pb)]
+        else:  # J2S2
+            pa = rng.uniform(lo_p, 0.8)
+            pb = pa * rng.uniform(1.5, 4.0)
+            r1, r2 = rng.uniform(lo_r, 1.0, 2)
+            u = rng.uniform(-vm, vm)
+            v1, v2 = rng.uniform(-vm, vm, 2)
+            f1, r4 = _shock_velocity_jump(pb, r1, pa)
+            f2, r3 = _shock_velocity_jump(pb, r2, pa)
+            states = [(r1, u, v1, pa), (r2, u, v2, pa), (r3, u, v2 + f2, pb), (r4, u, v1 + f1, pb)]
+        states = _symmetry(states, int(rng.integers(8)))
+        if _in_range(states) and _edges_nontrivial(states):
             return [tuple(float(a) for a in s) for s in states]
-    # all-contact fallback
-    p = rng.uniform(lo_p, hi_p)
-    u12, u34 = rng.uniform(-vmax, vmax, 2)
-    v41, v23 = rng.uniform(-vmax, vmax, 2)
-    rhos = rng.uniform(lo_r, hi_r, 4)
-    return [(rhos[0], u12, v41, p), (rhos[1], u12, v23, p), (rhos[2], u34, v23, p), (rhos[3], u34, v41, p)]
+    raise RuntimeError("no admissible quadrant configuration drawn")
 
 
 def riemann_2d(n: int, seed: int = 0, ny: int | None = None):
