@@ -114,6 +114,12 @@ def lib():
     """The loaded libhgks.so; raises HgksLibraryMissing if it was never built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname; load it first so that the process holds
+        # one runtime, which libhgks.so then binds to (device memory and streams are torch's)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise HgksLibraryMissing(f"{LIB_PATH} is missing: build it with paper_2304_05572_amd/build.py "
                                      "(hipcc, gfx950); there is no CPU fallback")
