@@ -60,13 +60,18 @@ def read_profile_table(name):
     return out
 
 
-def rp_problem(H, n, precision_cfl=0.5):
-    return H.Problem(dim=2, nx=n, ny=n, bc=(H.BC_OUTFLOW,) * 4, cfl=precision_cfl, c1=0.01, c2=1.0)
+def rp_problem(H, n, recon=0):
+    return H.Problem(dim=2, nx=n, ny=n, bc=(H.BC_OUTFLOW,) * 4, cfl=0.5, c1=0.01, c2=1.0, recon=recon)
 
 
-def time_solver(H, problems, states, precision, steps, warmup, tile):
+def launch_config(tile):
+    return {"tile": list(tile[:2]), "waves_per_simd_target": tile[2], "index": tile[3],
+            "persistent_blocks": tile[4] if tile[4] else None}
+
+
+def time_solver(H, problems, states, precision, steps, warmup, tile, compensated=False):
     import torch
-    s = H.Solver(problems, precision=precision, tile=tile, profile=True, autotune=(tile < 0))
+    s = H.Solver(problems, precision=precision, tile=tile, profile=1, autotune=(tile < 0), compensated=compensated)
     for p, W in enumerate(states):
         s.set_ic(p, W)
     s.run(np.inf, warmup)
@@ -85,6 +90,33 @@ def time_solver(H, problems, states, precision, steps, warmup, tile):
     prof = {k: (prof1[k][0] - prof0[k][0], prof1[k][1] - prof0[k][1]) for k in prof1}
     s.close()
     return t1 - t0, flux_ms / max(flux_n, 1), stats, tile_used, prof
+
+
+def side_windows(H, problems, states, precision, tile, compensated=False, steps=10):
+    """Two short windows beside the timed one, with the launch configuration it used: every kernel group
+    timed with events (ms per step per group), and the same steps replayed as one HIP graph per step with
+    no events (ms per step)."""
+    import torch
+    out = {}
+    for mode in ("groups", "graph"):
+        s = H.Solver(problems, precision=precision, tile=tile, compensated=compensated,
+                     profile=2 if mode == "groups" else 0, use_graph=(mode == "graph"))
+        for p, W in enumerate(states):
+            s.set_ic(p, W)
+        s.run(np.inf, 2)
+        torch.cuda.synchronize()
+        p0 = s.profile()
+        t0 = time.perf_counter()
+        s.run(np.inf, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if mode == "groups":
+            p1 = s.profile()
+            out["kernel_ms_per_step"] = {k: (p1[k][0] - p0[k][0]) / steps for k in p1}
+        else:
+            out["graph_ms_per_step"] = el / steps * 1e3
+        s.close()
+    return out
 
 
 def gpu_first_step(H, W0, n, precision):
@@ -132,7 +164,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tile", type=int, default=-1, help="tile-shape index; -1 autotunes")
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--variants", default="fp64,fp32,batched", help="comma list of fp64,fp32,batched")
+    ap.add_argument("--variants", default="fp64,fp32,batched,wenoao,fp32c",
+                    help="comma list of fp64, fp32, batched, wenoao (FP64 with every cell troubled), "
+                         "fp32c (FP32-bulk with compensated state)")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (CPU baseline and parity)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a plain copy (counter scaling)")
     args = ap.parse_args()
@@ -156,14 +190,19 @@ def main():
     cells = n * n
 
     res = {}
-    for name, prec in (("fp64", H.FP64), ("fp32", H.FP32_BULK)):
+    for name, prec, recon, comp in (("fp64", H.FP64, H.RECON_HYBRID, False),
+                                    ("fp32", H.FP32_BULK, H.RECON_HYBRID, False),
+                                    ("wenoao", H.FP64, H.RECON_WENOAO, False),
+                                    ("fp32c", H.FP32_BULK, H.RECON_HYBRID, True)):
         if name not in variants:
             continue
         log(f"[bench] timing {name}: {args.warmup} warm-up + {args.steps} steps")
-        el, flux_ms, stats, tile, prof = time_solver(H, [rp_problem(H, n)], [W0], prec, args.steps, args.warmup,
-                                                     args.tile)
+        el, flux_ms, stats, tile, prof = time_solver(H, [rp_problem(H, n, recon)], [W0], prec, args.steps,
+                                                     args.warmup, args.tile, comp)
         res[name] = dict(seconds=el, flux_ms=flux_ms, stats=stats[0], tile=tile, prof=prof,
                          mcells=cells * args.steps / el / 1e6, ms_per_step=el / args.steps * 1e3)
+        if name in ("fp64", "fp32", "fp32c"):
+            res[name].update(side_windows(H, [rp_problem(H, n, recon)], [W0], prec, tile[3], comp))
         log(f"[bench] {name}: {res[name]['mcells']:.1f} Mcell-updates/s, {res[name]['ms_per_step']:.3f} ms/step, "
             f"flux kernel {flux_ms:.3f} ms/launch, tile {tile}, flagged x {stats[0]['flagged_x']:.4f}")
 
@@ -177,7 +216,7 @@ def main():
                                                      args.tile)
         bcells = sum(m * m for m in sizes)
         batch = dict(mcells=bcells * args.steps / el / 1e6, ms_per_step=el / args.steps * 1e3, cells=bcells,
-                     problems=len(sizes), min_n=min(sizes), max_n=max(sizes), launch_config=list(tile))
+                     problems=len(sizes), min_n=min(sizes), max_n=max(sizes), launch_config=launch_config(tile))
         log(f"[bench] batched: {batch['mcells']:.1f} Mcell-updates/s")
         del bstates
 
@@ -225,12 +264,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D four-quadrant Riemann problem, Euler, {n}x{n} cells, seeded quadrant states "
                                f"(seed {args.seed}), hybrid WENO5-AO GKS, S2O4, CFL 0.5, c1=0.01, c2=1, outflow",
-                   "nx": n, "ny": n, "seed": args.seed, "launch_config": {"tile": list(r["tile"][:2]), "waves_per_simd_target": r["tile"][2], "index": r["tile"][3]},
+                   "nx": n, "ny": n, "seed": args.seed, "launch_config": launch_config(r["tile"]),
                    "flagged_fraction_x": r["stats"]["flagged_x"], "flagged_fraction_y": r["stats"]["flagged_y"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": {
             "fp64": {"value": r["mcells"], "ms_per_step": r["ms_per_step"], "flux_ms_per_launch": r["flux_ms"],
+                     "kernel_ms_per_step": r["kernel_ms_per_step"], "graph_ms_per_step": r["graph_ms_per_step"],
                      "l1_rel_vs_oracle": parity.get("fp64", (None,) * 3)[0],
                      "linf_rel_vs_oracle": parity.get("fp64", (None,) * 3)[1],
                      "dt_bit_exact_vs_oracle": parity.get("fp64", (None,) * 3)[2]},
@@ -242,7 +282,23 @@ def main():
                                         "flux_ms_per_launch": f["flux_ms"], "dtype": "f32 (f64 state/flags/CFL)",
                                         "l1_rel_vs_oracle": parity.get("fp32", (None,) * 3)[0],
                                         "linf_rel_vs_oracle": parity.get("fp32", (None,) * 3)[1],
-                                        "speedup_vs_fp64": f["mcells"] / r["mcells"], "launch_config": list(f["tile"])}
+                                        "speedup_vs_fp64": f["mcells"] / r["mcells"],
+                                        "kernel_ms_per_step": f["kernel_ms_per_step"],
+                                        "graph_ms_per_step": f["graph_ms_per_step"],
+                                        "launch_config": launch_config(f["tile"])}
+    if "wenoao" in res:
+        f = res["wenoao"]
+        out["variants"]["fp64_forced_wenoao"] = {
+            "value": f["mcells"], "ms_per_step": f["ms_per_step"], "flux_ms_per_launch": f["flux_ms"],
+            "note": "every cell troubled: the WENO5-AO GKS the hybrid scheme is compared against",
+            "hybrid_speedup": r["mcells"] / f["mcells"], "flux_kernel_speedup": f["flux_ms"] / r["flux_ms"],
+            "launch_config": launch_config(f["tile"])}
+    if "fp32c" in res:
+        f = res["fp32c"]
+        out["variants"]["fp32_bulk_compensated"] = {
+            "value": f["mcells"], "ms_per_step": f["ms_per_step"], "kernel_ms_per_step": f["kernel_ms_per_step"],
+            "graph_ms_per_step": f["graph_ms_per_step"], "dtype": "f32 (f64 state + f64 compensation)",
+            "launch_config": launch_config(f["tile"])}
     if batch:
         out["variants"]["batched"] = dict(batch, value=batch["mcells"], dtype="f32 (f64 state/flags/CFL)",
                                           workload=f"{batch['problems']} independent Riemann problems, N in "

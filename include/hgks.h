@@ -64,6 +64,10 @@ typedef enum { HGKS_RECON_HYBRID = 0, HGKS_RECON_FORCE_WENOAO = 1, HGKS_RECON_FO
  * flags, the CFL reduction and the time-integration coefficients of Eq. (equ10) stay FP64. */
 typedef enum { HGKS_FP64 = 0, HGKS_FP32_BULK = 1 } hgks_precision;
 
+/* Launch configurations of the fused reconstruction + flux kernel: 6 tile shapes, each launched with
+ * one block per tile or as a persistent grid of co-resident blocks. */
+#define HGKS_NUM_LAUNCH_CONFIGS 12
+
 /* One problem (Sec. 2 statement; parameters of Sec. 3). */
 typedef struct {
   int32_t dim, nx, ny;          /* dim 1 or 2; ny must be 1 when dim == 1; nx, ny >= 5 */
@@ -85,9 +89,16 @@ typedef struct {
   int32_t autotune;   /* 1: time the tile shapes on the first step and keep the fastest (cached on disk
                          under $HGKS_AUTOTUNE_CACHE if set) */
   int32_t use_graph;  /* 1: hgks_run replays one captured HIP graph per step */
-  int32_t tile;       /* tile-shape index when autotune == 0 (-1: library default) */
-  int32_t profile;    /* 1: bracket every kernel launch of hgks_step / hgks_run (without graphs) with
-                         HIP events on the library's stream; read with hgks_get_profile */
+  int32_t tile;       /* flux launch configuration when autotune == 0 (-1: library default):
+                         c % 6 picks the tile shape, c >= 6 the persistent form */
+  int32_t profile;    /* bracket kernel launches of hgks_step / hgks_run (without graphs) with HIP events
+                         on the library's stream, read with hgks_get_profile: 1 the reconstruction + flux
+                         launches only (two per step), 2 every launch; 0 none */
+  int32_t compensated; /* 1: compensated stage accumulation -- a second FP64 array per problem keeps the
+                          rounding error of the stored state (error-free two-sum of the S2O4 stage
+                          sums of Sec. 2.2), so the state is carried to about twice FP64 precision
+                          across steps; the fluxes still read the rounded state. Costs 4 more FP64
+                          accesses per conserved variable and step. 0: plain FP64 sums. */
   void* hip_stream;   /* borrowed hipStream_t (NULL: the library's own stream) */
 } hgks_opts;
 
@@ -119,6 +130,10 @@ hgks_status hgks_run(hgks_t* h, const double* t_end, int64_t max_steps, int64_t*
 /* Copy the state of problem `prob` out; *t receives its time (t may be NULL). */
 hgks_status hgks_get_state(const hgks_t* h, int32_t prob, double* W, int32_t on_device, double* t);
 
+/* Low-order part E of the carried state W + E of problem `prob` ([nc][ny][nx], FP64) when the handle
+ * was created with opts.compensated == 1; zeros otherwise. Synchronises the stream. */
+hgks_status hgks_get_state_lo(const hgks_t* h, int32_t prob, double* E, int32_t on_device);
+
 /* Widened troubled-cell flags (Steps 1-4) of the current state of problem `prob`, one byte per cell
  * ([ny][nx]); fy is ignored in 1D. */
 hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy);
@@ -132,7 +147,7 @@ hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* 
  * out[4] fraction of cells flagged in x at the last flag evaluation, out[5] the same in y. */
 hgks_status hgks_get_stats(const hgks_t* h, int32_t prob, double* out);
 
-/* Kernel timings gathered since the handle was created (opts.profile == 1), from HIP events recorded
+/* Kernel timings gathered since the handle was created (opts.profile > 0), from HIP events recorded
  * on the launching stream. out[2k] = total milliseconds and out[2k+1] = number of launches of kernel
  * group k: 0 fused reconstruction + flux, 1 stage update, 2 troubled-cell flags, 3 scalar kernels
  * (time step, commit). Synchronises the stream. */
@@ -140,8 +155,10 @@ hgks_status hgks_get_profile(hgks_t* h, double* out /* 8 entries */);
 
 /* Launch configuration of the reconstruction + flux kernel in use (fixed by opts.tile or chosen by the
  * autotuner): out[0] interfaces per tile along the normal, out[1] rows along the tangential direction,
- * out[2] waves per SIMD the register allocation targets, out[3] the configuration index. */
-hgks_status hgks_get_tile(const hgks_t* h, int32_t* out /* 4 entries */);
+ * out[2] waves per SIMD the register allocation targets, out[3] the configuration index
+ * (0 .. HGKS_NUM_LAUNCH_CONFIGS-1), out[4] the block count of a persistent launch (0: one block per
+ * tile, or not launched yet). */
+hgks_status hgks_get_tile(const hgks_t* h, int32_t* out /* 5 entries */);
 
 void hgks_destroy(hgks_t* h);
 const char* hgks_status_str(hgks_status s);

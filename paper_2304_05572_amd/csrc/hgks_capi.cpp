@@ -16,6 +16,8 @@
 
 using namespace hk;
 
+static_assert(kNumConfigs == HGKS_NUM_LAUNCH_CONFIGS, "launch configuration count of the C ABI");
+
 #define HIPOK(x)                                  \
   do {                                            \
     hipError_t e_ = (x);                          \
@@ -28,13 +30,14 @@ using namespace hk;
 static thread_local hipError_t last_hip_error = hipSuccess;
 
 struct hgks {
-  int nprob = 0, dim = 2, fp32 = 0, use_graph = 0, autotune = 0;
-  int tile = 0, tuned = 0;
+  int nprob = 0, dim = 2, fp32 = 0, use_graph = 0, autotune = 0, compensated = 0;
+  int tile = 0, tuned = 0;  // tile: flux launch configuration, 0 .. kNumConfigs-1
+  int pgrid[kNumConfigs];   // persistent grid per configuration (0: not yet queried)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<hgks_problem> hp;
   std::vector<ProbDev> pd;
-  std::vector<size_t> off_W, off_Ws, off_S, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_cnt;
+  std::vector<size_t> off_W, off_Ws, off_S, off_E, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_cnt;
   size_t off_probs = 0, off_ts = 0, off_tab = 0, ws_bytes = 0;
   char* ws = nullptr;
   bool own_ws = false, ready = false;
@@ -80,7 +83,7 @@ static void plan(hgks* h) {
   size_t o = 0;
   const size_t ts = h->fp32 ? sizeof(float) : sizeof(double);
   const int np = h->nprob;
-  h->off_W.resize(np); h->off_Ws.resize(np); h->off_S.resize(np); h->off_flags.resize(np);
+  h->off_W.resize(np); h->off_Ws.resize(np); h->off_S.resize(np); h->off_E.resize(np); h->off_flags.resize(np);
   h->off_Fx.resize(np); h->off_Gx.resize(np); h->off_Fy.resize(np); h->off_Gy.resize(np); h->off_cnt.resize(np);
   for (int p = 0; p < np; ++p) {
     const hgks_problem& q = h->hp[p];
@@ -89,6 +92,11 @@ static void plan(hgks* h) {
     h->off_W[p] = o; o = align256(o + state);
     h->off_Ws[p] = o; o = align256(o + state);
     h->off_S[p] = o; o = align256(o + state);
+    if (h->compensated) {
+      h->off_E[p] = o; o = align256(o + state);
+    } else {
+      h->off_E[p] = 0;
+    }
     h->off_flags[p] = o; o = align256(o + (nx + 4) * (q.dim == 2 ? ny + 4 : 1));
     h->off_Fx[p] = o; o = align256(o + nc * ny * (nx + 1) * ts);
     h->off_Gx[p] = o; o = align256(o + nc * ny * (nx + 1) * ts);
@@ -114,7 +122,9 @@ static void plan(hgks* h) {
     const long cells = (long)q.nx * q.ny;
     const long ext = (long)(q.nx + 4) * (q.dim == 2 ? q.ny + 4 : 1);
     h->tab_cell[p + 1] = h->tab_cell[p] + (int)((cells + 255) / 256);
-    h->tab_ext[p + 1] = h->tab_ext[p] + (int)((ext + 255) / 256);
+    // flag blocks: 16 x 16 tiles of the extended range in 2D, runs of 256 cells in 1D
+    const long fblocks = (q.dim == 2) ? (long)((q.nx + 4 + 15) / 16) * ((q.ny + 4 + 15) / 16) : (ext + 255) / 256;
+    h->tab_ext[p + 1] = h->tab_ext[p] + (int)fblocks;
     for (int t = 0; t < kNumTiles; ++t) h->tab_flux[t][p + 1] = h->tab_flux[t][p] + flux_tiles(q.dim, q.nx, q.ny, t);
   }
 }
@@ -130,16 +140,23 @@ static LaunchCtx ctx(hgks* h) {
   L.ts = reinterpret_cast<TimeDev*>(h->ws + h->off_ts);
   L.off_cell = tab_ptr(h, 0);
   L.off_ext = tab_ptr(h, 1);
-  L.off_flux = tab_ptr(h, 2 + h->tile);
+  const int shape = h->tile % kNumTiles;
+  L.off_flux = tab_ptr(h, 2 + shape);
   L.nprob = h->nprob;
   L.dim = h->dim;
   L.fp32 = h->fp32;
-  L.tile = h->tile;
+  L.tile = shape;
+  L.persistent = h->tile >= kNumTiles;
+  L.persistent_grid = 0;
   L.prfix = 0;
   for (auto& q : h->hp) L.prfix |= (q.eqn == HGKS_NS && q.Pr != 1.0);
   L.cell_blocks = h->tab_cell[h->nprob];
   L.ext_blocks = h->tab_ext[h->nprob];
-  L.flux_blocks = h->tab_flux[h->tile][h->nprob];
+  L.flux_blocks = h->tab_flux[shape][h->nprob];
+  if (L.persistent) {
+    if (h->pgrid[h->tile] <= 0) h->pgrid[h->tile] = flux_persistent_grid(L);
+    L.persistent_grid = h->pgrid[h->tile];
+  }
   return L;
 }
 
@@ -173,6 +190,7 @@ static hgks_status materialise(hgks* h) {
     d.W = reinterpret_cast<double*>(h->ws + h->off_W[p]);
     d.Ws = reinterpret_cast<double*>(h->ws + h->off_Ws[p]);
     d.S = reinterpret_cast<double*>(h->ws + h->off_S[p]);
+    d.E = h->compensated ? reinterpret_cast<double*>(h->ws + h->off_E[p]) : nullptr;
     d.flags = reinterpret_cast<uint8_t*>(h->ws + h->off_flags[p]);
     d.Fx = h->ws + h->off_Fx[p];
     d.Gx = h->ws + h->off_Gx[p];
@@ -227,7 +245,7 @@ static hipEvent_t take_event(hgks* h) {
 // Launch `fn` bracketed by events when profiling (kinds: 0 flux, 1 update, 2 flags, 3 scalar).
 template <typename Fn>
 static void timed(hgks* h, int kind, bool capturing, Fn fn) {
-  if (!h->profile || capturing) {
+  if (!h->profile || capturing || (h->profile == 1 && kind != 0)) {
     fn();
     return;
   }
@@ -255,10 +273,10 @@ static void collect_profile(hgks* h) {
 static void enqueue_step(hgks* h, int use_tend, bool capturing = false) {
   const LaunchCtx L = ctx(h);
   timed(h, 3, capturing, [&] { launch_dt_finalize(L, use_tend); });
-  timed(h, 2, capturing, [&] { launch_flags(L, 0, 1); });
+  timed(h, 2, capturing, [&] { launch_flags(L, 0, 1, 0); });
   timed(h, 0, capturing, [&] { launch_flux(L, 1); });
   timed(h, 1, capturing, [&] { launch_update(L, 1); });
-  timed(h, 2, capturing, [&] { launch_flags(L, 1, 0); });
+  timed(h, 2, capturing, [&] { launch_flags(L, 1, 0, 0); });
   timed(h, 0, capturing, [&] { launch_flux(L, 2); });
   timed(h, 1, capturing, [&] { launch_update(L, 2); });
   timed(h, 3, capturing, [&] { launch_commit(L, use_tend); });
@@ -271,6 +289,7 @@ static std::string tune_key(hgks* h) {
   size_t cells = 0;
   for (auto& q : h->hp) cells += (size_t)q.nx * q.ny;
   k += "_c" + std::to_string(cells) + "_x" + std::to_string(h->hp[0].nx) + "_y" + std::to_string(h->hp[0].ny);
+  k += "_r" + std::to_string(h->hp[0].recon) + "_e" + std::to_string(h->hp[0].eqn);
   return k;
 }
 
@@ -283,7 +302,7 @@ static bool tune_cache_lookup(const std::string& key, int& tile) {
   int t;
   bool found = false;
   while (std::fscanf(f, "%255s %d", kbuf, &t) == 2)
-    if (key == kbuf && t >= 0 && t < kNumTiles) { tile = t; found = true; }
+    if (key == kbuf && t >= 0 && t < kNumConfigs) { tile = t; found = true; }
   std::fclose(f);
   return found;
 }
@@ -314,9 +333,9 @@ static hgks_status autotune(hgks* h) {
   int best_t = h->tile;
   {
     LaunchCtx L = ctx(h);
-    launch_flags(L, 0, 0);
+    launch_flags(L, 0, 0, 0);
   }
-  for (int t = 0; t < kNumTiles; ++t) {
+  for (int t = 0; t < kNumConfigs; ++t) {
     h->tile = t;
     LaunchCtx L = ctx(h);
     launch_flux(L, 1);  // warm-up
@@ -349,6 +368,7 @@ static hgks_status build_graph(hgks* h, int use_tend) {
     (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
   }
+  (void)ctx(h);  // queries the persistent grid size (an occupancy call) before the capture starts
   hipGraph_t g;
   HIPOK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   enqueue_step(h, use_tend, true);
@@ -406,7 +426,9 @@ hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opt
   h->use_graph = opts ? opts->use_graph : 0;
   h->autotune = opts ? opts->autotune : 0;
   h->profile = opts ? opts->profile : 0;
-  h->tile = (opts && opts->tile >= 0 && opts->tile < kNumTiles) ? opts->tile : 0;
+  h->tile = (opts && opts->tile >= 0 && opts->tile < kNumConfigs) ? opts->tile : 0;
+  h->compensated = opts ? (opts->compensated != 0) : 0;
+  for (int c = 0; c < kNumConfigs; ++c) h->pgrid[c] = 0;
   if (opts && (opts->precision < 0 || opts->precision > 1)) {
     delete h;
     return HGKS_EINVAL;
@@ -448,6 +470,7 @@ hgks_status hgks_set_ic(hgks_t* h, int32_t prob, const double* W, int32_t on_dev
   const size_t bytes = (size_t)(q.dim + 2) * q.nx * q.ny * sizeof(double);
   HIPOK(hipMemcpyAsync(h->ws + h->off_W[prob], W, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                        h->stream));
+  if (h->compensated) HIPOK(hipMemsetAsync(h->ws + h->off_E[prob], 0, bytes, h->stream));
   std::vector<TimeDev> ts;
   s = read_ts(h, ts);
   if (s) return s;
@@ -548,6 +571,22 @@ hgks_status hgks_get_state(const hgks_t* hc, int32_t prob, double* W, int32_t on
   return status_from(ts);
 }
 
+hgks_status hgks_get_state_lo(const hgks_t* hc, int32_t prob, double* E, int32_t on_device) {
+  hgks* h = const_cast<hgks*>(hc);
+  if (!h || !E || prob < 0 || prob >= h->nprob || !h->ready) return HGKS_EINVAL;
+  const hgks_problem& q = h->hp[prob];
+  const size_t bytes = (size_t)(q.dim + 2) * q.nx * q.ny * sizeof(double);
+  if (h->compensated)
+    HIPOK(hipMemcpyAsync(E, h->ws + h->off_E[prob], bytes,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  else if (on_device)
+    HIPOK(hipMemsetAsync(E, 0, bytes, h->stream));
+  else
+    std::memset(E, 0, bytes);
+  HIPOK(hipStreamSynchronize(h->stream));
+  return HGKS_OK;
+}
+
 hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy) {
   if (!h || !fx || prob < 0 || prob >= h->nprob) return HGKS_EINVAL;
   if (!h->ready || !h->ic_set[prob]) return HGKS_EINVAL;
@@ -558,7 +597,7 @@ hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy) 
   for (int p = 0; p < h->nprob; ++p) ts[p].active = (p == prob);
   s = write_ts(h, ts);
   if (s) return s;
-  launch_flags(ctx(h), 0, 1);
+  launch_flags(ctx(h), 0, 1, 1);
   HIPOK(hipGetLastError());
   const hgks_problem& q = h->hp[prob];
   const size_t ex = q.nx + 4, ey = q.dim == 2 ? q.ny + 4 : 1;
@@ -598,7 +637,7 @@ hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* 
   s = write_ts(h, ts);
   if (s) return s;
   LaunchCtx L = ctx(h);
-  launch_flags(L, 0, 0);
+  launch_flags(L, 0, 0, 0);
   launch_flux(L, 1);
   HIPOK(hipGetLastError());
   const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny;
@@ -656,10 +695,12 @@ hgks_status hgks_get_profile(hgks_t* h, double* out) {
 
 hgks_status hgks_get_tile(const hgks_t* h, int32_t* out) {
   if (!h || !out) return HGKS_EINVAL;
-  out[0] = kTiles[h->tile].tn;
-  out[1] = kTiles[h->tile].tt;
-  out[2] = kTiles[h->tile].wpe;
+  const TileShape& ts = kTiles[h->tile % kNumTiles];
+  out[0] = ts.tn;
+  out[1] = ts.tt;
+  out[2] = ts.wpe;
   out[3] = h->tile;
+  out[4] = h->tile >= kNumTiles ? h->pgrid[h->tile] : 0;
   return HGKS_OK;
 }
 

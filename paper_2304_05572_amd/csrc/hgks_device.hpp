@@ -24,6 +24,8 @@ struct ProbDev {
   double* W;                 // state W^n        [nc][ny][nx]
   double* Ws;                // stage state W*   [nc][ny][nx]
   double* S;                 // partial sum W^n - dt L^n - dt^2/6 L_t^n
+  double* E;                 // compensated mode: rounding error of W^n (between steps) and of S (within a
+                             // step), so that the carried state is W + E; nullptr in plain mode
   uint8_t* flags;            // [(ny+4)][(nx+4)] (2D) / [nx+4] (1D): bit 0 x-flag, bit 1 y-flag
   void* Fx;                  // x-interfaces [4][ny][nx+1]: F (stage 1) / unused (stage 2)
   void* Gx;                  // x-interfaces: dF/dt
@@ -86,7 +88,7 @@ __device__ inline void load_cell(const ProbDev& P, const double* __restrict__ W,
 // xbar = -17 D1 / (10 D2) lies outside [-5/2, 5/2]; Step 3 smooth if it is within 1/4 of the
 // extreme point of the conservative quadratic on the three central cells.
 // ---------------------------------------------------------------------------------------------
-__device__ __attribute__((noinline)) int troubled5(double Qm2, double Qm1, double Q0, double Qp1, double Qp2,
+__device__ inline int troubled5(double Qm2, double Qm1, double Q0, double Qp1, double Qp2,
                                                    double thr) {
 #pragma clang fp contract(off)
   const double D1 = (Qp1 - Qm1) + 2.0 * (Qp2 - Qm2);

@@ -34,7 +34,7 @@ __device__ inline int xcd_swizzle(int b, int nblocks) {
 // CFL quantity of one cell: min(h / (|U| + c), h^2 / (4 mu / rho)) (Sec. 3), FP64, no contraction,
 // the same expression tree as the reference evaluation so the minimum is reproducible bit for bit.
 // ---------------------------------------------------------------------------------------------
-__device__ __attribute__((noinline)) double cfl_quantity(const ProbDev& P, double rho, double mu_, double mv,
+__device__ inline double cfl_quantity(const ProbDev& P, double rho, double mu_, double mv,
                                                          double E) {
 #pragma clang fp contract(off)
   const double U = mu_ / rho;
@@ -95,6 +95,8 @@ __global__ void k_dt_finalize(const ProbDev* __restrict__ probs, TimeDev* __rest
   const ProbDev& P = probs[p];
   const double q = __longlong_as_double((long long)s.qmin);
   s.qmin = 0x7ff0000000000000ull;  // +inf for the next reduction
+  P.flag_count[0] = 0;             // troubled cells are counted afresh by the step's first flag pass
+  P.flag_count[1] = 0;
   if (!s.active) {
     s.dt = 0.0;
     return;
@@ -196,6 +198,76 @@ __global__ void __launch_bounds__(256) k_flags(const ProbDev* __restrict__ probs
   }
 }
 
+// 2D form: a block owns a kFT x kFT tile of the extended range and stages the cells it needs in LDS
+// (3 beyond the tile on each side, ghosts synthesised), evaluates the indicator T once per cell and
+// direction for the tile plus one cell on each side, then widens it and writes the flags.
+constexpr int kFT = 16;
+
+__global__ void __launch_bounds__(kFT * kFT) k_flags2d(const ProbDev* __restrict__ probs,
+                                                      const TimeDev* __restrict__ ts,
+                                                      const int* __restrict__ off, int nprob,
+                                                      int use_stage_state, int count) {
+  constexpr int L = kFT + 6;
+  __shared__ double sW[4][L][L];          // cell (i0 - 3 + s, j0 - 3 + r) at [c][r][s]
+  __shared__ uint8_t sTx[kFT][kFT + 2];   // T_x of cell (i0 - 1 + a, j0 + b) at [b][a]
+  __shared__ uint8_t sTy[kFT + 2][kFT];   // T_y of cell (i0 + a, j0 - 1 + b) at [b][a]
+  const int p = find_prob(off, nprob, blockIdx.x);
+  const ProbDev& P = probs[p];
+  if (!ts[p].active) return;
+  const int ex = P.nx + 4, ey = P.ny + 4;
+  const int tiles_x = (ex + kFT - 1) / kFT;
+  const int lt = blockIdx.x - off[p];
+  const int i0 = (lt % tiles_x) * kFT - 2, j0 = (lt / tiles_x) * kFT - 2;  // first cell of the tile
+  const int tid = threadIdx.x;
+  const int a = tid % kFT, b = tid / kFT;
+  const int i = i0 + a, j = j0 + b;
+  const bool inside = (i < P.nx + 2) && (j < P.ny + 2);
+  int fl = 0;
+  if (P.recon == 1) {
+    fl = 3;
+  } else if (P.recon == 0) {
+    const double* W = use_stage_state ? P.Ws : P.W;
+    for (int e = tid; e < L * L; e += kFT * kFT) {
+      const int r = e / L, c = e % L;
+      double q[4];
+      load_cell(P, W, i0 - 3 + c, j0 - 3 + r, q);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sW[k][r][c] = q[k];
+    }
+    __syncthreads();
+    const double tx = (P.zeta1_mode == 0) ? 5.0 * P.dx : 5.0 * P.dx * P.dx * P.dx;
+    const double ty = (P.zeta1_mode == 0) ? 5.0 * P.dy : 5.0 * P.dy * P.dy * P.dy;
+    for (int e = tid; e < kFT * (kFT + 2); e += kFT * kFT) {
+      const int bb = e / (kFT + 2), aa = e % (kFT + 2);  // T_x: row bb, cells aa .. aa+4
+      int t = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        t |= troubled5(sW[k][bb + 3][aa], sW[k][bb + 3][aa + 1], sW[k][bb + 3][aa + 2], sW[k][bb + 3][aa + 3],
+                       sW[k][bb + 3][aa + 4], tx);
+      sTx[bb][aa] = (uint8_t)t;
+      const int ay = e % kFT, by = e / kFT;            // T_y: column ay, rows by .. by+4
+      t = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        t |= troubled5(sW[k][by][ay + 3], sW[k][by + 1][ay + 3], sW[k][by + 2][ay + 3], sW[k][by + 3][ay + 3],
+                       sW[k][by + 4][ay + 3], ty);
+      sTy[by][ay] = (uint8_t)t;
+    }
+    __syncthreads();
+    fl = (sTx[b][a] | sTx[b][a + 1] | sTx[b][a + 2]) | ((sTy[b][a] | sTy[b + 1][a] | sTy[b + 2][a]) << 1);
+  }
+  if (inside) P.flags[(size_t)(j + 2) * ex + (i + 2)] = (uint8_t)fl;
+  if (count) {
+    const bool interior = inside && i >= 0 && i < P.nx && j >= 0 && j < P.ny;
+    const unsigned long long bx = __ballot(interior && (fl & 1));
+    const unsigned long long by = __ballot(interior && (fl & 2));
+    if ((tid & 63) == 0) {
+      if (bx) atomicAdd(&P.flag_count[0], __popcll(bx));
+      if (by) atomicAdd(&P.flag_count[1], __popcll(by));
+    }
+  }
+}
+
 __global__ void k_clear_counts(const ProbDev* __restrict__ probs, int nprob) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < nprob) {
@@ -254,10 +326,9 @@ __device__ inline void tangential_side(const T (*sNR)[TN][16], int tt, int k, in
 // points, the equilibrium state and the flux (Sec. 2.3.3 Steps 1-3, Sec. 2.1-2.2).
 // Frame: slot 1 holds the normal momentum, slot 2 the tangential one (y-interfaces swap U and V).
 // ---------------------------------------------------------------------------------------------
-template <typename T, int TN, int TT, int DIM, bool PRFIX, int WPE>
-__global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WPE))) k_flux(const ProbDev* __restrict__ probs,
-                                                  const TimeDev* __restrict__ ts,
-                                                  const int* __restrict__ off, int nprob, int stage) {
+template <typename T, int TN, int TT, int DIM, bool PRFIX>
+__device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
+                                 const int* __restrict__ off, int nprob, int stage, int b) {
   constexpr int R = (DIM == 2) ? TT + 4 : 1;  // rows with halo
   constexpr int RO = (DIM == 2) ? 2 : 0;      // halo rows below
   constexpr int C = TN + 5;                   // cells along the normal: -3 .. TN+1
@@ -266,8 +337,6 @@ __global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WP
   __shared__ uint8_t sF[R][TN + 1];
   __shared__ T sNR[R][TN][16];
 
-  const int nblocks = gridDim.x;
-  const int b = xcd_swizzle(blockIdx.x, nblocks);
   const int p = find_prob(off, nprob, b);
   const ProbDev& P = probs[p];
   const TimeDev& tsp = ts[p];
@@ -424,6 +493,32 @@ __global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WP
   }
 }
 
+// One block per tile; tiles are renumbered so that each XCD works on a contiguous range.
+template <typename T, int TN, int TT, int DIM, bool PRFIX, int WPE>
+__global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_flux(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts, const int* __restrict__ off, int nprob,
+       int stage) {
+  flux_tile<T, TN, TT, DIM, PRFIX>(probs, ts, off, nprob, stage, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
+// Persistent form: a grid of co-resident blocks (a multiple of 8) walks the tile list of every problem
+// in the batch. Blocks are dealt to the XCDs round-robin, so block b serves XCD b % 8; each XCD takes the
+// same contiguous tile range as above and deals it to its blocks cyclically, which spreads the costlier
+// tiles along a shock over many blocks. Every block leaves the loop after at most ceil(range / blocks)
+// tiles.
+template <typename T, int TN, int TT, int DIM, bool PRFIX, int WPE>
+__global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_flux_persistent(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts, const int* __restrict__ off,
+                  int nprob, int stage, int ntiles) {
+  const int x = blockIdx.x & 7, li = blockIdx.x >> 3, nloc = gridDim.x >> 3;
+  const int q = ntiles >> 3, r = ntiles & 7;
+  const int begin = x * q + (x < r ? x : r), end = begin + q + (x < r ? 1 : 0);
+  for (int b = begin + li; b < end; b += nloc) {
+    flux_tile<T, TN, TT, DIM, PRFIX>(probs, ts, off, nprob, stage, b);
+    __syncthreads();  // the tile's LDS is dead before the next tile is staged
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // S2O4 stage updates (Sec. 2.2), FP64 state:
 //   stage 1: W* = W^n - sum_dir [F(dt/2)_{+} - F(dt/2)_{-}]/h,  F(dt/2) = dt/2 F + dt^2/8 dF/dt
@@ -431,6 +526,18 @@ __global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WP
 //   stage 2: W^{n+1} = S - dt^2/3 sum_dir [dF*/dt_{+} - dF*/dt_{-}]/h, then the CFL quantity of
 //            W^{n+1} for the next step.
 // ---------------------------------------------------------------------------------------------
+// Compensated accumulation: (a + e) + b with a's carried rounding error e, as a rounded value `hi`
+// and the new error, which is returned (error-free two-sum, then a fast renormalisation). Contraction
+// stays off so that the rounding errors are recovered exactly.
+__device__ inline double comp_add(double a, double b, double e, double& hi) {
+#pragma clang fp contract(off)
+  const double s = a + b;
+  const double bb = s - a;
+  const double err = ((a - (s - bb)) + (b - bb)) + e;
+  hi = s + err;
+  return err - (hi - s);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
                                                 const int* __restrict__ off, int nprob, int stage) {
@@ -461,13 +568,25 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
       if (stage == 1) {
         const double fx = (double(Fx[c * px + ox + 1]) - double(Fx[c * px + ox])) * idx;
         const double fy = (P.dim == 2) ? (double(Fy[c * py + oy + P.nx]) - double(Fy[c * py + oy])) * idy : 0.0;
-        const double ws = w - (dt * (0.5 * fx + 0.125 * dt * gx) + dt * (0.5 * fy + 0.125 * dt * gy));
-        const double s = w - (dt * (fx + dt / 6.0 * gx) + dt * (fy + dt / 6.0 * gy));
+        const double d1 = dt * (0.5 * fx + 0.125 * dt * gx) + dt * (0.5 * fy + 0.125 * dt * gy);
+        const double d2 = dt * (fx + dt / 6.0 * gx) + dt * (fy + dt / 6.0 * gy);
+        double ws, s;
+        if (P.E) {
+          const double e = P.E[c * ncell + cell];
+          ws = w - (d1 - e);
+          P.E[c * ncell + cell] = comp_add(w, -d2, e, s);
+        } else {
+          ws = w - d1;
+          s = w - d2;
+        }
         P.Ws[c * ncell + cell] = ws;
         P.S[c * ncell + cell] = s;
         wn[c == nc - 1 ? 3 : c] = ws;
       } else {
-        const double wnew = P.S[c * ncell + cell] - dt * dt / 3.0 * (gx + gy);
+        const double d3 = dt * dt / 3.0 * (gx + gy);
+        double wnew;
+        if (P.E) P.E[c * ncell + cell] = comp_add(P.S[c * ncell + cell], -d3, P.E[c * ncell + cell], wnew);
+        else wnew = P.S[c * ncell + cell] - d3;
         P.W[c * ncell + cell] = wnew;
         wn[c == nc - 1 ? 3 : c] = wnew;
       }
@@ -501,27 +620,58 @@ void launch_commit(const LaunchCtx& L, int use_tend) {
   hipLaunchKernelGGL(k_commit, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.ts, L.nprob, use_tend);
 }
 
-void launch_flags(const LaunchCtx& L, int stage_state, int count) {
-  if (count) hipLaunchKernelGGL(k_clear_counts, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.probs, L.nprob);
-  hipLaunchKernelGGL(k_flags, dim3(L.ext_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_ext, L.nprob,
-                     stage_state, count);
+void launch_flags(const LaunchCtx& L, int stage_state, int count, int clear) {
+  if (clear) hipLaunchKernelGGL(k_clear_counts, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.probs, L.nprob);
+  if (L.dim == 2)
+    hipLaunchKernelGGL(k_flags2d, dim3(L.ext_blocks), dim3(kFT * kFT), 0, L.stream, L.probs, L.ts, L.off_ext,
+                       L.nprob, stage_state, count);
+  else
+    hipLaunchKernelGGL(k_flags, dim3(L.ext_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_ext, L.nprob,
+                       stage_state, count);
+}
+
+// Blocks of a persistent launch: what the occupancy calculator says fits on every CU at once, rounded
+// down to a multiple of 8 (one share per XCD), and never more than the tiles.
+static int resident_grid(const void* fn, int threads, int ntiles) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 8;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, 0) != hipSuccess || per < 1) per = 1;
+  int g = cus * per;
+  const int cap = (ntiles + 7) & ~7;
+  if (g > cap) g = cap;
+  g &= ~7;
+  return g < 8 ? 8 : g;
+}
+
+// stage 0 asks for the persistent grid size of the variant instead of launching (written to *grid)
+template <typename T, int TN, int TT, int DIM, bool PR, int WPE>
+static void flux_launch(const LaunchCtx& L, int stage, int* grid) {
+  constexpr int TNd = (DIM == 1) ? TN * TT : TN, TTd = (DIM == 1) ? 1 : TT;
+  if (stage == 0) {
+    *grid = resident_grid(reinterpret_cast<const void*>(k_flux_persistent<T, TNd, TTd, DIM, PR, WPE>), TN * TT,
+                          L.flux_blocks);
+    return;
+  }
+  if (!L.persistent)
+    hipLaunchKernelGGL((k_flux<T, TNd, TTd, DIM, PR, WPE>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream,
+                       L.probs, L.ts, L.off_flux, L.nprob, stage);
+  else
+    hipLaunchKernelGGL((k_flux_persistent<T, TNd, TTd, DIM, PR, WPE>), dim3(L.persistent_grid), dim3(TN * TT), 0,
+                       L.stream, L.probs, L.ts, L.off_flux, L.nprob, stage, L.flux_blocks);
 }
 
 template <typename T, int TN, int TT, bool PR, int WPE>
-static void flux_variant_pr(const LaunchCtx& L, int stage) {
-  if (L.dim == 1)
-    hipLaunchKernelGGL((k_flux<T, TN * TT, 1, 1, PR, WPE>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream,
-                       L.probs, L.ts, L.off_flux, L.nprob, stage);
-  else
-    hipLaunchKernelGGL((k_flux<T, TN, TT, 2, PR, WPE>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream, L.probs,
-                       L.ts, L.off_flux, L.nprob, stage);
+static void flux_variant_pr(const LaunchCtx& L, int stage, int* grid) {
+  if (L.dim == 1) flux_launch<T, TN, TT, 1, PR, WPE>(L, stage, grid);
+  else flux_launch<T, TN, TT, 2, PR, WPE>(L, stage, grid);
 }
 
 // the Prandtl-number correction is compiled in only for launches that need it (NS with Pr != 1)
 template <typename T, int TN, int TT, int WPE>
-static void flux_variant(const LaunchCtx& L, int stage) {
-  if (L.prfix) flux_variant_pr<T, TN, TT, true, WPE>(L, stage);
-  else flux_variant_pr<T, TN, TT, false, WPE>(L, stage);
+static void flux_variant(const LaunchCtx& L, int stage, int* grid) {
+  if (L.prfix) flux_variant_pr<T, TN, TT, true, WPE>(L, stage, grid);
+  else flux_variant_pr<T, TN, TT, false, WPE>(L, stage, grid);
 }
 
 // launch configurations: tile shape and the waves-per-SIMD target the register allocator works to
@@ -529,20 +679,27 @@ static void flux_variant(const LaunchCtx& L, int stage) {
 const TileShape kTiles[kNumTiles] = {{8, 8, 1}, {8, 8, 2}, {16, 8, 1}, {16, 8, 2}, {16, 16, 2}, {8, 8, 3}};
 
 template <typename T>
-static void launch_flux_t(const LaunchCtx& L, int stage) {
+static void launch_flux_t(const LaunchCtx& L, int stage, int* grid) {
   switch (L.tile) {
-    case 0: flux_variant<T, 8, 8, 1>(L, stage); break;
-    case 1: flux_variant<T, 8, 8, 2>(L, stage); break;
-    case 2: flux_variant<T, 16, 8, 1>(L, stage); break;
-    case 3: flux_variant<T, 16, 8, 2>(L, stage); break;
-    case 4: flux_variant<T, 16, 16, 2>(L, stage); break;
-    default: flux_variant<T, 8, 8, 3>(L, stage); break;
+    case 0: flux_variant<T, 8, 8, 1>(L, stage, grid); break;
+    case 1: flux_variant<T, 8, 8, 2>(L, stage, grid); break;
+    case 2: flux_variant<T, 16, 8, 1>(L, stage, grid); break;
+    case 3: flux_variant<T, 16, 8, 2>(L, stage, grid); break;
+    case 4: flux_variant<T, 16, 16, 2>(L, stage, grid); break;
+    default: flux_variant<T, 8, 8, 3>(L, stage, grid); break;
   }
 }
 
 void launch_flux(const LaunchCtx& L, int stage) {
-  if (L.fp32) launch_flux_t<float>(L, stage);
-  else launch_flux_t<double>(L, stage);
+  if (L.fp32) launch_flux_t<float>(L, stage, nullptr);
+  else launch_flux_t<double>(L, stage, nullptr);
+}
+
+int flux_persistent_grid(const LaunchCtx& L) {
+  int g = 8;
+  if (L.fp32) launch_flux_t<float>(L, 0, &g);
+  else launch_flux_t<double>(L, 0, &g);
+  return g;
 }
 
 void launch_update(const LaunchCtx& L, int stage) {

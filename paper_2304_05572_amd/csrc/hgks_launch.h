@@ -12,17 +12,23 @@ struct TileShape {
 };
 constexpr int kNumTiles = 6;
 extern const TileShape kTiles[kNumTiles];
+// launch configurations of the flux kernel: tile shape c % kNumTiles, one block per tile (c < kNumTiles)
+// or a persistent grid of co-resident blocks walking the tiles (c >= kNumTiles)
+constexpr int kNumConfigs = 2 * kNumTiles;
 
 struct LaunchCtx {
   hipStream_t stream;
   const ProbDev* probs;  // device array [nprob]
   TimeDev* ts;           // device array [nprob]
   const int* off_cell;   // prefix sums of 256-cell blocks per problem
-  const int* off_ext;    // prefix sums of 256-cell blocks of the extended (flag) range
+  const int* off_ext;    // prefix sums of flag blocks over the extended range: 16 x 16 tiles (2D) or
+                         // 256-cell runs (1D)
   const int* off_flux;   // prefix sums of flux tiles (x then y) for the current tile shape
   int nprob, dim, fp32, tile;
+  int persistent;        // 1: persistent flux launch of persistent_grid blocks
+  int persistent_grid;
   int prfix;             // 1 if any problem is Navier-Stokes with Pr != 1
-  int cell_blocks, ext_blocks, flux_blocks;
+  int cell_blocks, ext_blocks, flux_blocks;  // flux_blocks: tiles of all problems
 };
 
 // number of flux tiles of one problem for tile shape `tile`
@@ -35,8 +41,11 @@ inline int flux_tiles(int dim, int nx, int ny, int tile) {
 void launch_cfl(const LaunchCtx& L);
 void launch_dt_finalize(const LaunchCtx& L, int use_tend);
 void launch_commit(const LaunchCtx& L, int use_tend);
-void launch_flags(const LaunchCtx& L, int stage_state, int count);
+// troubled-cell flags of the current (stage_state 0) or stage (1) state; count: tally the interior
+// troubled cells; clear: zero the tallies first (the step's dt finalisation already does)
+void launch_flags(const LaunchCtx& L, int stage_state, int count, int clear);
 void launch_flux(const LaunchCtx& L, int stage);
+int flux_persistent_grid(const LaunchCtx& L);  // blocks of the persistent flux launch for L's variant
 void launch_update(const LaunchCtx& L, int stage);
 
 }  // namespace hk

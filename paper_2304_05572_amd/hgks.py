@@ -25,10 +25,11 @@ EULER, NS = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_NOSLIP = 0, 1, 2, 3
 RECON_HYBRID, RECON_WENOAO, RECON_LINEAR = 0, 1, 2
 FP64, FP32_BULK = 0, 1
+NUM_LAUNCH_CONFIGS = 12  # flux launch configurations: 6 tile shapes x (one block per tile, persistent)
 
 ENTRY_POINTS = ("hgks_create", "hgks_workspace_bytes", "hgks_bind_workspace", "hgks_set_ic", "hgks_step",
-                "hgks_run", "hgks_get_state", "hgks_debug_flags", "hgks_debug_stage_fluxes", "hgks_get_stats",
-                "hgks_get_tile", "hgks_get_profile", "hgks_destroy", "hgks_status_str")
+                "hgks_run", "hgks_get_state", "hgks_get_state_lo", "hgks_debug_flags", "hgks_debug_stage_fluxes",
+                "hgks_get_stats", "hgks_get_tile", "hgks_get_profile", "hgks_destroy", "hgks_status_str")
 
 
 class HgksLibraryMissing(ImportError):
@@ -55,7 +56,8 @@ class hgks_problem(C.Structure):
 
 class hgks_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("autotune", C.c_int32), ("use_graph", C.c_int32),
-                ("tile", C.c_int32), ("profile", C.c_int32), ("hip_stream", C.c_void_p)]
+                ("tile", C.c_int32), ("profile", C.c_int32), ("compensated", C.c_int32),
+                ("hip_stream", C.c_void_p)]
 
 
 @dataclasses.dataclass
@@ -133,6 +135,7 @@ def lib():
             "hgks_step": (i32, [vp, vp]),
             "hgks_run": (i32, [vp, vp, i64, vp]),
             "hgks_get_state": (i32, [vp, i32, vp, i32, vp]),
+            "hgks_get_state_lo": (i32, [vp, i32, vp, i32]),
             "hgks_debug_flags": (i32, [vp, i32, vp, vp]),
             "hgks_debug_stage_fluxes": (i32, [vp, i32, d, vp, vp, vp, vp]),
             "hgks_get_stats": (i32, [vp, i32, vp]),
@@ -167,9 +170,9 @@ def hgks_status_str(code: int) -> str:
 
 
 def hgks_create(problems: Sequence[Problem], precision=FP64, autotune=0, use_graph=0, tile=-1, hip_stream=None,
-                profile=0):
+                profile=0, compensated=0):
     arr = (hgks_problem * len(problems))(*[p.c_struct() for p in problems])
-    opts = hgks_opts(int(precision), int(autotune), int(use_graph), int(tile), int(profile),
+    opts = hgks_opts(int(precision), int(autotune), int(use_graph), int(tile), int(profile), int(compensated),
                      C.c_void_p(hip_stream) if hip_stream else None)
     h = C.c_void_p()
     _check(lib().hgks_create(arr, len(problems), C.byref(opts), C.byref(h)), "hgks_create")
@@ -213,6 +216,11 @@ def hgks_get_state(h, prob: int, out):
     return t.value
 
 
+def hgks_get_state_lo(h, prob: int, out):
+    ptr, dev = _addr(out)
+    _check(lib().hgks_get_state_lo(h, int(prob), ptr, dev), "hgks_get_state_lo")
+
+
 def hgks_debug_flags(h, prob: int, fx: np.ndarray, fy: np.ndarray | None):
     _check(lib().hgks_debug_flags(h, int(prob), fx.ctypes.data_as(C.c_void_p),
                                   fy.ctypes.data_as(C.c_void_p) if fy is not None else None), "hgks_debug_flags")
@@ -230,8 +238,9 @@ def hgks_get_stats(h, prob: int):
 
 
 def hgks_get_tile(h):
-    """(interfaces along the normal, rows along the tangential direction, waves-per-SIMD target, index)."""
-    out = np.zeros(4, np.int32)
+    """(interfaces along the normal, rows along the tangential direction, waves-per-SIMD target,
+    configuration index, persistent grid blocks or 0)."""
+    out = np.zeros(5, np.int32)
     _check(lib().hgks_get_tile(h, out.ctypes.data_as(C.c_void_p)), "hgks_get_tile")
     return tuple(int(x) for x in out)
 
@@ -251,14 +260,15 @@ class Solver:
     """Owns one library handle for a list of problems advanced together."""
 
     def __init__(self, problems: Sequence[Problem] | Problem, precision=FP64, autotune=False, use_graph=False,
-                 tile=-1, stream=None, workspace=None, profile=False):
+                 tile=-1, stream=None, workspace=None, profile=False, compensated=False):
         if isinstance(problems, Problem):
             problems = [problems]
         self.problems = list(problems)
         sp = None
         if stream is not None:
             sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        self.h = hgks_create(self.problems, precision, int(autotune), int(use_graph), tile, sp, int(profile))
+        self.h = hgks_create(self.problems, precision, int(autotune), int(use_graph), tile, sp, int(profile),
+                             int(compensated))
         self.workspace = None
         if workspace is not None:
             self.bind_workspace(workspace)
@@ -292,6 +302,13 @@ class Solver:
         t = hgks_get_state(self.h, prob, out)
         return out, t
 
+    def get_state_lo(self, prob: int = 0, out=None):
+        """Low-order part E of the carried state W + E (zeros unless compensated)."""
+        if out is None:
+            out = np.zeros(self.problems[prob].shape)
+        hgks_get_state_lo(self.h, prob, out)
+        return out
+
     def flags(self, prob: int = 0):
         P = self.problems[prob]
         shp = (P.nx,) if P.dim == 1 else (P.ny, P.nx)
@@ -320,7 +337,8 @@ class Solver:
         return hgks_get_tile(self.h)
 
     def profile(self):
-        """Per kernel group: (total ms, launches) for flux, update, flags, scalar kernels."""
+        """Per kernel group: (total ms, launches) for flux, update, flags, scalar kernels (profile=1 times
+        the flux launches only, profile=2 every launch)."""
         o = hgks_get_profile(self.h)
         names = ("flux", "update", "flags", "scalar")
         return {n: (o[2 * k], int(o[2 * k + 1])) for k, n in enumerate(names)}
