@@ -7,11 +7,19 @@ CFL 0.5, c1 = 0.01, c2 = 1, outflow boundaries. One step = one full two-stage fo
 cell (flags, fused reconstruction + gas-kinetic flux, stage update, for both stages, plus the CFL
 reduction), inputs resident in device memory.
 
-`value` is the plain FP64 path in Mcell-updates/s. The same line carries the FP32-bulk path on the same
-workload, the batched path (64 uneven problems in one set of launches), their L1 distance to the CPU
-oracle on a sampled window after one step, the roofline position of the dominant kernel (fused flux,
-VALU-bound, FP64 flops from HIP-event timing of its launches in the timed region) and the oracle's own
-CPU throughput on a bounded sample.
+`value` is the plain FP64 path in Mcell-updates/s, timed over K steps issued eagerly with HIP events
+around the flux launches only. The same line carries: the FP32-bulk path on the same workload; forced
+WENO5-AO (every cell troubled) against the hybrid scheme; FP32-bulk with compensated state; the batched
+path (64 uneven problems in one set of launches); per-kernel-group times and graph-replay step times from
+short side windows; the rate with host transfers included; the L1/Linf distance of the first step of each
+precision to the CPU oracle over the full grid; the roofline position of the dominant kernel (fused
+reconstruction + flux, VALU-bound: algorithmic FP64 flops per Gauss point x Gauss points per launch over
+the HIP-event mean launch time in the timed region; HBM bytes per launch from committed FETCH_SIZE /
+WRITE_SIZE counts when they match the sources and the launch configuration); and the oracle's own CPU
+throughput on a bounded sample.
+
+Other modes: --tile-sweep times every flux launch configuration; --copy-calibration runs a plain copy for
+scaling the HBM byte counters.
 """
 import argparse
 import hashlib
@@ -29,9 +37,12 @@ METRIC = "Mcell-updates/s, 2D Euler 1024^2: FP64 plain vs FP32 vs batched, L1 er
 PEAK_FP64_VALU = 78.6  # TFLOP/s, MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (packed)
 PEAK_HBM = 8000.0  # GB/s
-# FP64 operations per Gauss-point flux evaluation of the fused kernel on unflagged data (FMA = 2),
-# counted with the VALU instruction counters; see profiles/k_flux_counters_rp1024.txt
-FLOPS_PER_GP = {"fp64": None, "fp32": None}
+# Algorithmic FP64 operations (FMA = 2) per Gauss-point evaluation of the fused reconstruction + flux
+# kernel on this workload (seed 0, about 2% of the cells troubled): normal and tangential reconstruction,
+# equilibrium state and gas-kinetic flux, without the tile's recomputation of halo rows. From the
+# SQ_INSTS_VALU_FLOPS_FP64 counter at two tile shapes, extrapolated to no recomputation
+# (profiles/k_flux_rp1024_counters.txt).
+FLOPS_PER_GP_FP64 = 2616.9
 
 
 def log(*a):
@@ -119,6 +130,28 @@ def side_windows(H, problems, states, precision, tile, compensated=False, steps=
     return out
 
 
+def host_io(H, problems, states, precision, tile, steps):
+    """The same steps with the state handed over in host memory: upload (hgks_set_ic from a host array),
+    the steps, download (hgks_get_state into a host array); returns ms of each part."""
+    import torch
+    s = H.Solver(problems, precision=precision, tile=tile)
+    s.set_ic(0, states[0])
+    s.run(np.inf, 1)  # first-launch costs out of the way
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, W in enumerate(states):
+        s.set_ic(p, W)
+    t1 = time.perf_counter()
+    s.run(np.inf, steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for p in range(len(states)):
+        s.get_state(p)
+    t3 = time.perf_counter()
+    s.close()
+    return {"upload_ms": (t1 - t0) * 1e3, "steps_ms": (t2 - t1) * 1e3, "download_ms": (t3 - t2) * 1e3}
+
+
 def gpu_first_step(H, W0, n, precision):
     """State after one S2O4 step from the initial data, and the step's dt."""
     s = H.Solver(rp_problem(H, n), precision=precision)
@@ -142,6 +175,29 @@ def oracle_leg(W0, n):
            "sample": f"one S2O4 step of the full {n}x{n} Riemann problem from its initial data, FP64 C oracle, "
                      f"{nth} OpenMP threads, {el:.1f} s wall"}
     return W, dt, rec
+
+
+def tile_sweep(args):
+    """Mean flux-launch time of every launch configuration on the benchmark workload, one JSON line each;
+    with --variants restricting the precisions."""
+    import torch
+    from paper_2304_05572_amd import hgks as H
+    from paper_2304_05572_amd import workloads as wl
+    W0, _ = wl.riemann_2d(args.n, seed=args.seed)
+    for name, prec in (("fp64", H.FP64), ("fp32", H.FP32_BULK)):
+        if name not in args.variants.split(","):
+            continue
+        for c in range(H.NUM_LAUNCH_CONFIGS):
+            s = H.Solver(rp_problem(H, args.n), precision=prec, tile=c, profile=1)
+            s.set_ic(0, W0)
+            s.run(np.inf, 1)
+            p0 = s.profile()["flux"]
+            s.run(np.inf, 3)
+            p1 = s.profile()["flux"]
+            torch.cuda.synchronize()
+            print(json.dumps({"precision": name, "config": c, "tile": s.tile(),
+                              "flux_ms_per_launch": (p1[0] - p0[0]) / max(p1[1] - p0[1], 1)}), flush=True)
+            s.close()
 
 
 def copy_calibration(mib=512, reps=5):
@@ -169,6 +225,8 @@ def main():
                          "fp32c (FP32-bulk with compensated state)")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle leg (CPU baseline and parity)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a plain copy (counter scaling)")
+    ap.add_argument("--tile-sweep", action="store_true",
+                    help="only time every flux launch configuration (FP64 and FP32-bulk, 3 steps each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (each box has one GPU); "
@@ -177,6 +235,9 @@ def main():
     variants = set(x for x in args.variants.split(",") if x)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.tile_sweep:
+        tile_sweep(args)
         return
 
     import torch  # device memory and streams; the compute is the HIP library
@@ -203,6 +264,11 @@ def main():
                          mcells=cells * args.steps / el / 1e6, ms_per_step=el / args.steps * 1e3)
         if name in ("fp64", "fp32", "fp32c"):
             res[name].update(side_windows(H, [rp_problem(H, n, recon)], [W0], prec, tile[3], comp))
+        if name == "fp64":
+            io = host_io(H, [rp_problem(H, n, recon)], [W0], prec, tile[3], args.steps)
+            io["mcells_incl_host_io"] = cells * args.steps / ((io["upload_ms"] + io["steps_ms"] + io["download_ms"])
+                                                             * 1e-3) / 1e6
+            res[name]["host_io"] = io
         log(f"[bench] {name}: {res[name]['mcells']:.1f} Mcell-updates/s, {res[name]['ms_per_step']:.3f} ms/step, "
             f"flux kernel {flux_ms:.3f} ms/launch, tile {tile}, flagged x {stats[0]['flagged_x']:.4f}")
 
@@ -238,17 +304,21 @@ def main():
     r = res["fp64"]
     gps = 2 * ((n + 1) * n * 2)  # two Gauss points on every x- and y-interface
     roof = None
-    fl = FLOPS_PER_GP.get("fp64")
+    fl = FLOPS_PER_GP_FP64
     traffic = read_profile_table("k_flux_traffic_rp1024_fp64.txt")
-    if fl:
+    if n == 1024 and r["flux_ms"] > 0:
         achieved = fl * gps / (r["flux_ms"] * 1e-3) / 1e12
-        tr = None
-        if traffic.get("kernel_hash") == kernel_hash() and "bytes_per_launch" in traffic:
-            tr = float(traffic["bytes_per_launch"])
+        tr = None  # counted HBM bytes, only for the sources and launch configuration they were taken on
+        key = "bytes_per_launch_%d" % r["tile"][3]
+        if traffic.get("kernel_hash") == kernel_hash() and key in traffic:
+            tr = float(traffic[key])
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_VALU, "traffic": tr,
-                "kernel": "k_flux (fused reconstruction + GKS flux, FP64)", "ms_per_launch": r["flux_ms"],
-                "flops_per_launch": fl * gps}
+                "kernel": ("k_flux_persistent" if r["tile"][4] else "k_flux") + "<double, %d, %d, 2, false, %d>"
+                          % (r["tile"][0], r["tile"][1], r["tile"][2]) + " (fused reconstruction + GKS flux)",
+                "ms_per_launch": r["flux_ms"],
+                "flops_per_launch": fl * gps, "flops_per_gauss_point": fl, "gauss_points_per_launch": gps,
+                "traffic_unit": "bytes per launch"}
     out = {
         "metric": METRIC,
         "value": r["mcells"],
@@ -271,6 +341,7 @@ def main():
         "variants": {
             "fp64": {"value": r["mcells"], "ms_per_step": r["ms_per_step"], "flux_ms_per_launch": r["flux_ms"],
                      "kernel_ms_per_step": r["kernel_ms_per_step"], "graph_ms_per_step": r["graph_ms_per_step"],
+                     "host_io": r["host_io"],
                      "l1_rel_vs_oracle": parity.get("fp64", (None,) * 3)[0],
                      "linf_rel_vs_oracle": parity.get("fp64", (None,) * 3)[1],
                      "dt_bit_exact_vs_oracle": parity.get("fp64", (None,) * 3)[2]},

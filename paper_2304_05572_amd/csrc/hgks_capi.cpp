@@ -316,8 +316,10 @@ static void tune_cache_store(const std::string& key, int tile) {
   std::fclose(f);
 }
 
-// Time the first-stage flux kernel of every tile shape on the current state (dt already set by the
-// step's finalize launch) and keep the fastest.
+// Time the first-stage flux kernel of every launch configuration on the current state (dt already set
+// by the step's finalize launch) and keep the fastest: two interleaved rounds of three timed launches per
+// configuration after one untimed launch, the better round counting, so that clock ramps and noise
+// affect all candidates alike.
 static hgks_status autotune(hgks* h) {
   h->tuned = 1;
   const std::string key = tune_key(h);
@@ -329,24 +331,28 @@ static hgks_status autotune(hgks* h) {
   hipEvent_t e0, e1;
   HIPOK(hipEventCreate(&e0));
   HIPOK(hipEventCreate(&e1));
-  float best = 1e30f;
-  int best_t = h->tile;
+  std::vector<float> best(kNumConfigs, 1e30f);
   {
     LaunchCtx L = ctx(h);
     launch_flags(L, 0, 0, 0);
   }
-  for (int t = 0; t < kNumConfigs; ++t) {
-    h->tile = t;
-    LaunchCtx L = ctx(h);
-    launch_flux(L, 1);  // warm-up
-    HIPOK(hipEventRecord(e0, h->stream));
-    for (int r = 0; r < 3; ++r) launch_flux(L, 1);
-    HIPOK(hipEventRecord(e1, h->stream));
-    HIPOK(hipEventSynchronize(e1));
-    float ms = 0;
-    HIPOK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) { best = ms; best_t = t; }
+  for (int round = 0; round < 2; ++round) {
+    for (int t = 0; t < kNumConfigs; ++t) {
+      h->tile = t;
+      LaunchCtx L = ctx(h);
+      launch_flux(L, 1);  // warm-up
+      HIPOK(hipEventRecord(e0, h->stream));
+      for (int r = 0; r < 3; ++r) launch_flux(L, 1);
+      HIPOK(hipEventRecord(e1, h->stream));
+      HIPOK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPOK(hipEventElapsedTime(&ms, e0, e1));
+      best[t] = std::min(best[t], ms);
+    }
   }
+  int best_t = 0;
+  for (int t = 1; t < kNumConfigs; ++t)
+    if (best[t] < best[best_t]) best_t = t;
   h->tile = best_t;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
