@@ -185,6 +185,11 @@ static hgks_status materialise(hgks* h) {
     // model with V = 0, which has the same u-moments as the 1D model with K + 1 = 2/(gamma-1)
     d.K = (4.0 - 2.0 * q.gamma) / (q.gamma - 1.0);
     d.mu = q.mu; d.Pr = q.Pr; d.c1 = q.c1; d.c2 = q.c2;
+    d.Kp2 = d.K + 2.0;
+    d.iKp2 = 1.0 / d.Kp2;
+    d.kpr = 1.0 / q.Pr - 1.0;
+    d.ihx = 1.0 / d.dx;
+    d.ihy = 1.0 / d.dy;
     d.cfl = q.cfl; d.fixed_dt = q.fixed_dt;
     d.ghi = q.gamma_hi; d.glo = q.gamma_lo; d.eps = q.weno_eps;
     d.W = reinterpret_cast<double*>(h->ws + h->off_W[p]);
@@ -486,7 +491,7 @@ hgks_status hgks_set_ic(hgks_t* h, int32_t prob, const double* W, int32_t on_dev
   ts[prob].active = 1;
   ts[prob].status = 0;
   ts[prob].steps = 0;
-  ts[prob].dt = 0.0;
+  set_time_step(ts[prob], 0.0);
   s = write_ts(h, ts);
   if (s) return s;
   h->ic_set[prob] = 1;
@@ -638,7 +643,7 @@ hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* 
   saved = ts;
   for (int p = 0; p < h->nprob; ++p) {
     ts[p].active = (p == prob);
-    ts[p].dt = dt;
+    set_time_step(ts[p], dt);
   }
   s = write_ts(h, ts);
   if (s) return s;

@@ -19,6 +19,8 @@ struct ProbDev {
   int recon, zeta1_mode;
   double dx, dy, h;          // cell sizes; h = min(dx, dy) for the CFL step
   double gamma, K, mu, Pr, c1, c2;  // K: internal dof of the 2D model (1D problems embed into it)
+  double Kp2, iKp2, kpr;     // K + 2, 1 / (K + 2), 1 / Pr - 1 (uniform values kept out of the lanes)
+  double ihx, ihy;           // 1 / dx, 1 / dy
   double cfl, fixed_dt;
   double ghi, glo, eps;
   double* W;                 // state W^n        [nc][ny][nx]
@@ -36,11 +38,20 @@ struct ProbDev {
 
 struct TimeDev {
   double dt, t, t_new, t_end;
+  double dth, idt, idt2;     // dt / 2, 1 / dt, 4 / dt^2 of the current step
   unsigned long long qmin;   // bit pattern of the positive FP64 minimum of the CFL quantity
   int active;                // 1 while t < t_end
   int status;                // sticky: 1 when a non-physical state appeared
   long long steps;
 };
+
+// Derived time-step quantities of the step (set wherever dt is set).
+__host__ __device__ inline void set_time_step(TimeDev& s, double dt) {
+  s.dt = dt;
+  s.dth = 0.5 * dt;
+  s.idt = dt > 0.0 ? 1.0 / dt : 0.0;
+  s.idt2 = 4.0 * s.idt * s.idt;
+}
 
 // ---------------------------------------------------------------------------------------------
 // Boundary conditions: index of the interior cell a (ghost) index reads, and velocity sign flips
@@ -365,11 +376,11 @@ __device__ inline void mom_psi(const Maxw<T>& g, T out[4]) {
 
 // Microscopic slope a with <a psi> = b (closed-form inverse of the 4x4 moment matrix of g).
 template <typename T>
-__device__ inline void solve_slope(const Maxw<T>& g, T Kp2, const T b[4], T a[4]) {
+__device__ inline void solve_slope(const Maxw<T>& g, T Kp2, T iKp2, const T b[4], T a[4]) {
   const T U = g.U, V = g.V, l = g.lam;
   const T q2 = U * U + V * V;
   const T ni = Kp2 * T(0.5) * drcp(l);  // (K+2)/(2 lam)
-  a[3] = T(4) * l * l * drcp(Kp2) * (T(2) * b[3] - T(2) * U * b[1] - T(2) * V * b[2] + (q2 - ni) * b[0]);
+  a[3] = T(4) * l * l * iKp2 * (T(2) * b[3] - T(2) * U * b[1] - T(2) * V * b[2] + (q2 - ni) * b[0]);
   a[2] = T(2) * l * (b[2] - V * b[0]) - V * a[3];
   a[1] = T(2) * l * (b[1] - U * b[0]) - U * a[3];
   a[0] = b[0] - U * a[1] - V * a[2] - T(0.5) * a[3] * (q2 + ni);
@@ -377,8 +388,9 @@ __device__ inline void solve_slope(const Maxw<T>& g, T Kp2, const T b[4], T a[4]
 
 // Time integrals over [0, delta] of the five coefficient functions of Eq. (equ10) (FP64):
 // 1 - e, (t+tau) e - tau, t - tau + tau e, e, (t+tau) e with e = exp(-t/tau); for delta/tau < 1 the
-// Taylor series of the same integrals (the closed forms cancel there).
-__device__ inline void time_integrals(double d, double tau, double C[5]) {
+// Taylor series of the same integrals (the closed forms cancel there). `e` is exp(-delta/tau), needed
+// only when delta/tau >= 1.
+__device__ inline void time_integrals(double d, double tau, double e, double C[5]) {
   if (tau == 0.0) {
     C[0] = d; C[1] = 0.0; C[2] = 0.5 * d * d; C[3] = 0.0; C[4] = 0.0;
     return;
@@ -396,7 +408,6 @@ __device__ inline void time_integrals(double d, double tau, double C[5]) {
     C[0] = tau * s1; C[1] = tau * tau * s2; C[2] = tau * tau * s3; C[3] = tau * s4; C[4] = tau * tau * (x + s2);
     return;
   }
-  const double e = exp(-x);
   C[0] = d - tau * (1.0 - e);
   C[1] = 2.0 * tau * tau - tau * d - tau * (d + 2.0 * tau) * e;
   C[2] = 0.5 * d * d - tau * d + tau * tau * (1.0 - e);
@@ -404,8 +415,21 @@ __device__ inline void time_integrals(double d, double tau, double C[5]) {
   C[4] = 2.0 * tau * tau - tau * (2.0 * tau + d) * e;
 }
 
+// Both step lengths of the S2O4 flux (dt and dt/2) from one exponential: exp(-dt/tau) is the square of
+// exp(-dt/(2 tau)).
+__device__ inline void time_integrals_pair(double dt, double dth, double tau, double Cd[5], double Ch[5]) {
+  double eh = 0.0, ed = 0.0;
+  if (tau > 0.0 && dt >= tau) {
+    eh = exp(-(dth / tau));
+    ed = eh * eh;
+  }
+  time_integrals(dt, tau, ed, Cd);
+  time_integrals(dth, tau, eh, Ch);
+}
+
 struct FluxParams {
   double gamma, K, mu, Pr, c1, c2, dt;
+  double Kp2, iKp2, kpr, dth, idt, idt2;  // K + 2, 1/(K + 2), 1/Pr - 1, dt/2, 1/dt, 4/dt^2
   int ns;
   int want_F;  // 0: only dF/dt (second stage)
 };
@@ -424,19 +448,12 @@ struct FluxAcc {
   T p_side[2];
 };
 
-template <typename T>
-__device__ inline void flux_acc_init(FluxAcc<T>& a) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    a.Wc[c] = 0; a.Wxc[c] = 0; a.Wyc[c] = 0; a.M4a[c] = 0; a.M4b[c] = 0; a.M5[c] = 0; a.N4b[c] = 0; a.N5[c] = 0;
-  }
-}
-
-// side S = 0: g_l integrated over u > 0; S = 1: g_r over u < 0
+// side S = 0: g_l integrated over u > 0 (the first side: its moments initialise the accumulators);
+// S = 1: g_r over u < 0 (added)
 template <int S, bool PRFIX, typename T>
-__device__ inline void flux_side(const T W[4], const T Wx[4], const T Wy[4], T gamma, T K, FluxAcc<T>& acc) {
+__device__ inline void flux_side(const T W[4], const T Wx[4], const T Wy[4], T gamma, T K, T Kp2, T iKp2,
+                                 FluxAcc<T>& acc) {
   constexpr int s = S;
-  const T Kp2 = K + T(2);
   Maxw<T> g;
   maxw_prims(W, gamma, g);
   acc.p_side[s] = T(0.5) * g.rho * drcp(g.lam);
@@ -446,45 +463,45 @@ __device__ inline void flux_side(const T W[4], const T Wx[4], const T Wy[4], T g
   maxw_moments(g, K, 0);
 #pragma unroll
   for (int c = 0; c < 4; ++c) b[c] = Wx[c] * ir;
-  solve_slope(g, Kp2, b, ax);
+  solve_slope(g, Kp2, iKp2, b, ax);
 #pragma unroll
   for (int c = 0; c < 4; ++c) b[c] = Wy[c] * ir;
-  solve_slope(g, Kp2, b, ay);
+  solve_slope(g, Kp2, iKp2, b, ay);
   mom_a<1, 0>(g, ax, t1);
   mom_a<0, 1>(g, ay, t2);
 #pragma unroll
   for (int c = 0; c < 4; ++c) b[c] = -(t1[c] + t2[c]);
-  solve_slope(g, Kp2, b, A);
+  solve_slope(g, Kp2, iKp2, b, A);
   // half-line moments
   maxw_moments(g, K, s ? -1 : 1);
   const T rho = g.rho;
+  auto put = [&](T (&dst)[4], const T x[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c] = (S == 0) ? rho * x[c] : dst[c] + rho * x[c];
+  };
   mom_psi<0, 0>(g, t1);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc.Wc[c] += rho * t1[c];
+  put(acc.Wc, t1);
   mom_a<0, 0>(g, ax, t1);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc.Wxc[c] += rho * t1[c];
+  put(acc.Wxc, t1);
   mom_a<0, 0>(g, ay, t1);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc.Wyc[c] += rho * t1[c];
+  put(acc.Wyc, t1);
   mom_psi<1, 0>(g, t1);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc.M4a[c] += rho * t1[c];
+  put(acc.M4a, t1);
   mom_a<1, 0>(g, A, t1);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc.M4b[c] += rho * t1[c];
+  put(acc.M4b, t1);
   mom_a<2, 0>(g, ax, t1);
   mom_a<1, 1>(g, ay, t2);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) acc.M5[c] += rho * (t1[c] + t2[c]);
+  for (int c = 0; c < 4; ++c) t1[c] += t2[c];
+  put(acc.M5, t1);
   if (PRFIX) {
     mom_a<0, 0>(g, A, t1);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc.N4b[c] += rho * t1[c];
+    put(acc.N4b, t1);
     mom_a<1, 0>(g, ax, t1);
     mom_a<0, 1>(g, ay, t2);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc.N5[c] += rho * (t1[c] + t2[c]);
+    for (int c = 0; c < 4; ++c) t1[c] += t2[c];
+    put(acc.N5, t1);
   }
 }
 
@@ -496,7 +513,7 @@ struct TermCoef {
 
 template <bool PRFIX, typename T>
 __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt, T F[4], T dF[4]) {
-  const T gamma = T(fp.gamma), K = T(fp.K), Kp2 = K + T(2);
+  const T gamma = T(fp.gamma), K = T(fp.K), Kp2 = T(fp.Kp2), iKp2 = T(fp.iKp2);
   // equilibrium g0 at the interface
   Maxw<T> g0;
   maxw_prims(acc.Wc, gamma, g0);
@@ -515,9 +532,8 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
       tau = fp.c1 * fp.dt + fp.c2 * jump * fp.dt;
     }
     double Cd[5], Ch[5];
-    time_integrals(fp.dt, tau, Cd);
-    time_integrals(0.5 * fp.dt, tau, Ch);
-    const double idt = 1.0 / fp.dt, idt2 = 4.0 * idt * idt;
+    time_integrals_pair(fp.dt, fp.dth, tau, Cd, Ch);
+    const double idt = fp.idt, idt2 = fp.idt2;
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
       tc.f[m] = fp.want_F ? wgt * T((4.0 * Ch[m] - Cd[m]) * idt) : T(0);
@@ -530,7 +546,7 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
   // (u psi) M and conserved moments (psi) N; the energy flux of the term gains (1/Pr - 1) q
   const T U0 = g0.U, V0 = g0.V;
   const T cA = T(1.5) * U0 * U0 + T(0.5) * V0 * V0, cB = T(0.5) * U0 * (U0 * U0 + V0 * V0);
-  const T kpr = T(1.0 / fp.Pr - 1.0);
+  const T kpr = T(fp.kpr);
   auto heat = [&](const T M[4], const T N[4]) -> T {
     return M[3] - U0 * M[1] - V0 * M[2] + cA * M[0] + U0 * V0 * N[2] - U0 * N[3] - cB * N[0];
   };
@@ -571,12 +587,12 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) b[c] = acc.Wxc[c] * ir0;
-  solve_slope(g0, Kp2, b, a0);
+  solve_slope(g0, Kp2, iKp2, b, a0);
   mom_a<1, 0>(g0, a0, rhs);
   mom_a<2, 0>(g0, a0, t2);
 #pragma unroll
   for (int c = 0; c < 4; ++c) b[c] = acc.Wyc[c] * ir0;
-  solve_slope(g0, Kp2, b, a0);  // a0 now holds the y-slope b0
+  solve_slope(g0, Kp2, iKp2, b, a0);  // a0 now holds the y-slope b0
   mom_a<0, 1>(g0, a0, t1);
 #pragma unroll
   for (int c = 0; c < 4; ++c) rhs[c] = -(rhs[c] + t1[c]);  // <A0 psi> = -<(a0 u + b0 v) psi>
@@ -593,7 +609,7 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
     }
     fold(M, tc.f[1], tc.d[1]);
   }
-  solve_slope(g0, Kp2, rhs, a0);  // a0 now holds A0
+  solve_slope(g0, Kp2, iKp2, rhs, a0);  // a0 now holds A0
   {
     T M[4];
     mom_a<1, 0>(g0, a0, M);
@@ -615,9 +631,9 @@ template <bool PRFIX, typename T>
 __device__ inline void gks_flux_gp(const T Wl[4], const T Wxl[4], const T Wyl[4], const T Wr[4], const T Wxr[4],
                                    const T Wyr[4], const FluxParams& fp, T wgt, T F[4], T dF[4]) {
   FluxAcc<T> acc;
-  flux_acc_init(acc);
-  flux_side<0, PRFIX>(Wl, Wxl, Wyl, T(fp.gamma), T(fp.K), acc);
-  flux_side<1, PRFIX>(Wr, Wxr, Wyr, T(fp.gamma), T(fp.K), acc);
+  const T gam = T(fp.gamma), K = T(fp.K), Kp2 = T(fp.Kp2), iKp2 = T(fp.iKp2);
+  flux_side<0, PRFIX>(Wl, Wxl, Wyl, gam, K, Kp2, iKp2, acc);
+  flux_side<1, PRFIX>(Wr, Wxr, Wyr, gam, K, Kp2, iKp2, acc);
   flux_finish<PRFIX>(acc, fp, wgt, F, dF);
 }
 

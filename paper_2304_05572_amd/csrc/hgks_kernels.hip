@@ -98,14 +98,14 @@ __global__ void k_dt_finalize(const ProbDev* __restrict__ probs, TimeDev* __rest
   P.flag_count[0] = 0;             // troubled cells are counted afresh by the step's first flag pass
   P.flag_count[1] = 0;
   if (!s.active) {
-    s.dt = 0.0;
+    set_time_step(s, 0.0);
     return;
   }
   double dt = (P.fixed_dt > 0.0) ? P.fixed_dt : P.cfl * q;
   if (!(dt > 0.0) || !(dt < __builtin_inf())) {
     s.status |= 2;
     s.active = 0;
-    s.dt = 0.0;
+    set_time_step(s, 0.0);
     return;
   }
   if (use_tend && s.t + dt >= s.t_end) {
@@ -114,7 +114,7 @@ __global__ void k_dt_finalize(const ProbDev* __restrict__ probs, TimeDev* __rest
   } else {
     s.t_new = s.t + dt;
   }
-  s.dt = dt;
+  set_time_step(s, dt);
 }
 
 __global__ void k_commit(TimeDev* __restrict__ ts, int nprob, int use_tend) {
@@ -333,9 +333,13 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   constexpr int RO = (DIM == 2) ? 2 : 0;      // halo rows below
   constexpr int C = TN + 5;                   // cells along the normal: -3 .. TN+1
   constexpr int NT = TN * TT;
-  __shared__ T sW[4][R][C];
+  // the cell tile is dead once the normal reconstruction is done; phase 3 then parks the first Gauss
+  // point's F and dF/dt there (8 values per thread) while the second Gauss point is evaluated
+  constexpr int NRAW = (4 * R * C > 8 * NT) ? 4 * R * C : 8 * NT;
+  __shared__ T sRaw[NRAW];
   __shared__ uint8_t sF[R][TN + 1];
   __shared__ T sNR[R][TN][16];
+  T(*const sW)[R][C] = reinterpret_cast<T(*)[R][C]>(sRaw);
 
   const int p = find_prob(off, nprob, b);
   const ProbDev& P = probs[p];
@@ -351,7 +355,6 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   const int nn = dir ? P.ny : P.nx, nt = dir ? P.nx : P.ny;
   const int tilesn = (nn + 1 + TN - 1) / TN;
   const int n0 = (lt % tilesn) * TN, t0 = (lt / tilesn) * TT;
-  const double hn = dir ? P.dy : P.dx, ht = dir ? P.dx : P.dy;
 
   // ---- phase 1: load cells (with ghost synthesis) and flags
   const double* __restrict__ Wsrc = (stage == 1) ? P.W : P.Ws;
@@ -387,7 +390,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   __syncthreads();
 
   // ---- phase 2: normal reconstruction of every row (Sec. 2.3.1; line averages in 2D)
-  const T ihn = T(1.0 / hn);
+  const T ihn = T(dir ? P.ihy : P.ihx);
   const T gam = T(P.gamma), ghi = T(P.ghi), glo = T(P.glo), eps = T(P.eps);
   for (int e = tid; e < R * TN; e += NT) {
     const int r = e / TN, k = e % TN;
@@ -440,7 +443,9 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
 
   FluxParams fp;
   fp.gamma = P.gamma; fp.K = P.K; fp.mu = P.mu; fp.Pr = P.Pr; fp.c1 = P.c1; fp.c2 = P.c2;
-  fp.dt = tsp.dt; fp.ns = P.ns; fp.want_F = (stage == 1);
+  fp.Kp2 = P.Kp2; fp.iKp2 = P.iKp2; fp.kpr = P.kpr;
+  fp.dt = tsp.dt; fp.dth = tsp.dth; fp.idt = tsp.idt; fp.idt2 = tsp.idt2;
+  fp.ns = P.ns; fp.want_F = (stage == 1);
   T F[4] = {0, 0, 0, 0}, dF[4] = {0, 0, 0, 0};
   if (DIM == 1) {
     T Wl[4], Wxl[4], Wr[4], Wxr[4];
@@ -452,22 +457,33 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
     }
     gks_flux_gp<PRFIX>(Wl, Wxl, z, Wr, Wxr, z, fp, T(1), F, dF);
   } else {
-    const T iht = T(1.0 / ht);
+    const T iht = T(dir ? P.ihx : P.ihy);
+    const T K = T(P.K), Kp2 = T(P.Kp2), iKp2 = T(P.iKp2);
+    T* park = sRaw + tid;  // 8 values at stride NT
 #pragma unroll 1
     for (int gp = 0; gp < 2; ++gp) {
       FluxAcc<T> acc;
-      flux_acc_init(acc);
       T Ws[4], Wxs[4], Wys[4];
       // tangential reconstruction of one side at this Gauss point, then its share of the flux
       tangential_side<T, TN, R>(sNR, tt, k, 0, (sF[tt + 2][k] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
       __builtin_amdgcn_sched_barrier(0);
-      flux_side<0, PRFIX>(Ws, Wxs, Wys, gam, T(P.K), acc);
+      flux_side<0, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
       __builtin_amdgcn_sched_barrier(0);
       tangential_side<T, TN, R>(sNR, tt, k, 1, (sF[tt + 2][k + 1] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
       __builtin_amdgcn_sched_barrier(0);
-      flux_side<1, PRFIX>(Ws, Wxs, Wys, gam, T(P.K), acc);
+      flux_side<1, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
       __builtin_amdgcn_sched_barrier(0);
-      flux_finish<PRFIX>(acc, fp, T(0.5), F, dF);
+      T Fg[4] = {0, 0, 0, 0}, dFg[4] = {0, 0, 0, 0};
+      flux_finish<PRFIX>(acc, fp, T(0.5), Fg, dFg);
+      if (gp == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { park[v * NT] = Fg[v]; park[(4 + v) * NT] = dFg[v]; }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { F[v] = park[v * NT] + Fg[v]; dF[v] = park[(4 + v) * NT] + dFg[v]; }
+      }
+      // the parked values leave the registers: no value is carried across the loop in a register
+      __asm__ volatile("" ::: "memory");
     }
   }
 
