@@ -276,12 +276,15 @@ __global__ void k_clear_counts(const ProbDev* __restrict__ probs, int nprob) {
   }
 }
 
+// Stride (in values) of one interface entry of the normal-reconstruction rows in LDS.
+constexpr int kNRS = 17;
+
 // Tangential reconstruction (Sec. 2.3.3, Step 2) of side s of interface column k at Gauss point gp from
 // the line averages of rows tt..tt+4 (value line W^s and normal-slope line W^s_x): values at the Gauss
 // point, tangential slope of W^s, value of W^s_x. Linear quartic per component, or WENO-AO in the
 // tangential characteristic variables about the side's own centre-segment state when flagged.
 template <typename T, int TN, int R>
-__device__ inline void tangential_side(const T (*sNR)[TN][16], int tt, int k, int s, int ft, int gp, T gam, T ghi,
+__device__ inline void tangential_side(const T (*sNR)[TN][kNRS], int tt, int k, int s, int ft, int gp, T gam, T ghi,
                                        T glo, T eps, T iht, T Ws[4], T Wxs[4], T Wys[4]) {
   const int ov = 8 * s, od = 8 * s + 4;
   if (ft) {
@@ -321,7 +324,9 @@ __device__ inline void tangential_side(const T (*sNR)[TN][16], int tt, int k, in
 // TT rows (2D) and stages in LDS:
 //   sW  : cell averages, normal -3..TN+1 around the interfaces, rows -2..TT+1 (ghosts synthesised)
 //   sF  : flags of the cells adjacent to each interface (bit 0 normal, bit 1 tangential)
-//   sNR : normal reconstruction of every row: W^l, W^l_x, W^r, W^r_x (16 values per interface)
+//   sNR : normal reconstruction of every row: W^l, W^l_x, W^r, W^r_x (16 values per interface, padded
+//         to 17 so that the lanes of a wavefront spread over the LDS banks: neighbouring interfaces and
+//         rows would otherwise sit a multiple of 128 bytes apart and hit the same banks)
 // then each thread takes one interface through the tangential reconstruction at the two Gauss
 // points, the equilibrium state and the flux (Sec. 2.3.3 Steps 1-3, Sec. 2.1-2.2).
 // Frame: slot 1 holds the normal momentum, slot 2 the tangential one (y-interfaces swap U and V).
@@ -338,7 +343,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   constexpr int NRAW = (4 * R * C > 8 * NT) ? 4 * R * C : 8 * NT;
   __shared__ T sRaw[NRAW];
   __shared__ uint8_t sF[R][TN + 1];
-  __shared__ T sNR[R][TN][16];
+  __shared__ T sNR[R][TN][kNRS];
   T(*const sW)[R][C] = reinterpret_cast<T(*)[R][C]>(sRaw);
 
   const int p = find_prob(off, nprob, b);
