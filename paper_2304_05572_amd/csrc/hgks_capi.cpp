@@ -38,7 +38,7 @@ struct hgks {
   std::vector<hgks_problem> hp;
   std::vector<ProbDev> pd;
   std::vector<size_t> off_W, off_Ws, off_S, off_E, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_cnt;
-  size_t off_probs = 0, off_ts = 0, off_tab = 0, ws_bytes = 0;
+  size_t off_probs = 0, off_ts = 0, off_tab = 0, off_qpart = 0, ws_bytes = 0;
   char* ws = nullptr;
   bool own_ws = false, ready = false;
   std::vector<int> tab_cell, tab_ext, tab_flux[kNumTiles];
@@ -112,6 +112,9 @@ static void plan(hgks* h) {
   h->off_ts = o; o = align256(o + np * sizeof(TimeDev));
   // tables: cell, ext, and one flux table per tile shape, each nprob+1 ints
   h->off_tab = o; o = align256(o + (size_t)(2 + kNumTiles) * (np + 1) * sizeof(int));
+  long cell_blocks = 0;
+  for (int p = 0; p < np; ++p) cell_blocks += ((long)h->hp[p].nx * h->hp[p].ny + 255) / 256;
+  h->off_qpart = o; o = align256(o + (size_t)cell_blocks * sizeof(double));
   h->ws_bytes = o;
   // prefix sums
   h->tab_cell.assign(np + 1, 0);
@@ -139,6 +142,7 @@ static LaunchCtx ctx(hgks* h) {
   L.probs = reinterpret_cast<const ProbDev*>(h->ws + h->off_probs);
   L.ts = reinterpret_cast<TimeDev*>(h->ws + h->off_ts);
   L.off_cell = tab_ptr(h, 0);
+  L.qpart = reinterpret_cast<double*>(h->ws + h->off_qpart);
   L.off_ext = tab_ptr(h, 1);
   const int shape = h->tile % kNumTiles;
   L.off_flux = tab_ptr(h, 2 + shape);
@@ -209,7 +213,6 @@ static hgks_status materialise(hgks* h) {
   for (auto& s : ts) {
     std::memset(&s, 0, sizeof s);
     s.t_end = INFINITY;
-    s.qmin = 0x7ff0000000000000ull;
   }
   HIPOK(hipMemcpyAsync(h->ws + h->off_ts, ts.data(), h->nprob * sizeof(TimeDev), hipMemcpyHostToDevice, h->stream));
   std::vector<int> tabs((size_t)(2 + kNumTiles) * (h->nprob + 1));

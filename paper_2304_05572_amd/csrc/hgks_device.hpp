@@ -39,7 +39,6 @@ struct ProbDev {
 struct TimeDev {
   double dt, t, t_new, t_end;
   double dth, idt, idt2;     // dt / 2, 1 / dt, 4 / dt^2 of the current step
-  unsigned long long qmin;   // bit pattern of the positive FP64 minimum of the CFL quantity
   int active;                // 1 while t < t_end
   int status;                // sticky: 1 when a non-physical state appeared
   long long steps;

@@ -56,24 +56,26 @@ __device__ inline double wave_min(double v) {
   return v;
 }
 
-// Block-wide minimum, then one atomic per block on the problem's bit pattern (positive doubles order
-// like their bit patterns).
-__device__ inline void block_min_atomic(double q, unsigned long long* dst) {
+// Block-wide minimum (wavefront shuffles, then the waves' minima through LDS); thread 0 returns it.
+__device__ inline double block_min(double q) {
   __shared__ double red[16];
   q = wave_min(q);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) red[w] = q;
   __syncthreads();
+  double m = red[0];
   if (threadIdx.x == 0) {
-    double m = red[0];
     const int nw = (blockDim.x + 63) >> 6;
     for (int k = 1; k < nw; ++k) m = fmin(m, red[k]);
-    if (m < __builtin_inf()) atomicMin(dst, (unsigned long long)__double_as_longlong(m));
   }
+  return m;
 }
 
-__global__ void __launch_bounds__(256) k_cfl(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
-                                             const int* __restrict__ off, int nprob) {
+// The CFL minimum is reduced in two levels: every block of the cell-wise kernels (this one and the
+// second-stage update) stores its minimum in qpart[block], and the next dt finalisation reduces the
+// blocks of each problem. Minima are order-independent, so the time step is reproducible bit for bit.
+__global__ void __launch_bounds__(256) k_cfl(const ProbDev* __restrict__ probs, const int* __restrict__ off,
+                                             int nprob, double* __restrict__ qpart) {
   const int p = find_prob(off, nprob, blockIdx.x);
   const ProbDev& P = probs[p];
   const size_t ncell = (size_t)P.nx * P.ny;
@@ -84,17 +86,21 @@ __global__ void __launch_bounds__(256) k_cfl(const ProbDev* __restrict__ probs, 
     const double mv = (P.dim == 2) ? W[2 * ncell + cell] : 0.0;
     q = cfl_quantity(P, W[cell], W[ncell + cell], mv, W[(P.dim + 1) * ncell + cell]);
   }
-  block_min_atomic(q, &ts[p].qmin);
+  q = block_min(q);
+  if (threadIdx.x == 0) qpart[blockIdx.x] = q;
 }
 
-__global__ void k_dt_finalize(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts, int nprob,
-                              int use_tend) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprob) return;
+// One block per problem: the minimum over the problem's block minima, then dt (Sec. 3) by thread 0.
+__global__ void __launch_bounds__(256) k_dt_finalize(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
+                                                     const int* __restrict__ off, const double* __restrict__ qpart,
+                                                     int use_tend) {
+  const int p = blockIdx.x;
+  double q = __builtin_inf();
+  for (int b = off[p] + threadIdx.x; b < off[p + 1]; b += blockDim.x) q = fmin(q, qpart[b]);
+  q = block_min(q);
+  if (threadIdx.x != 0) return;
   TimeDev& s = ts[p];
   const ProbDev& P = probs[p];
-  const double q = __longlong_as_double((long long)s.qmin);
-  s.qmin = 0x7ff0000000000000ull;  // +inf for the next reduction
   P.flag_count[0] = 0;             // troubled cells are counted afresh by the step's first flag pass
   P.flag_count[1] = 0;
   if (!s.active) {
@@ -125,11 +131,6 @@ __global__ void k_commit(TimeDev* __restrict__ ts, int nprob, int use_tend) {
   s.t = s.t_new;
   s.steps += 1;
   if (use_tend && s.t >= s.t_end) s.active = 0;
-}
-
-__global__ void k_reset_qmin(TimeDev* __restrict__ ts, int nprob) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < nprob) ts[p].qmin = 0x7ff0000000000000ull;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -561,7 +562,8 @@ __device__ inline double comp_add(double a, double b, double e, double& hi) {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
-                                                const int* __restrict__ off, int nprob, int stage) {
+                                                const int* __restrict__ off, int nprob, int stage,
+                                                double* __restrict__ qpart) {
   const int p = find_prob(off, nprob, blockIdx.x);
   const ProbDev& P = probs[p];
   TimeDev& tsp = ts[p];
@@ -619,7 +621,10 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
     if (bad) atomicOr(&tsp.status, 1);
     if (stage == 2) q = cfl_quantity(P, wn[0], wn[1], wn[2], wn[3]);
   }
-  if (stage == 2) block_min_atomic(q, &tsp.qmin);
+  if (stage == 2) {
+    q = block_min(q);
+    if (threadIdx.x == 0) qpart[blockIdx.x] = q;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -628,12 +633,11 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
 static inline unsigned nblk(int n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_cfl(const LaunchCtx& L) {
-  hipLaunchKernelGGL(k_reset_qmin, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.ts, L.nprob);
-  hipLaunchKernelGGL(k_cfl, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell, L.nprob);
+  hipLaunchKernelGGL(k_cfl, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.off_cell, L.nprob, L.qpart);
 }
 
 void launch_dt_finalize(const LaunchCtx& L, int use_tend) {
-  hipLaunchKernelGGL(k_dt_finalize, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.probs, L.ts, L.nprob,
+  hipLaunchKernelGGL(k_dt_finalize, dim3(L.nprob), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell, L.qpart,
                      use_tend);
 }
 
@@ -726,10 +730,10 @@ int flux_persistent_grid(const LaunchCtx& L) {
 void launch_update(const LaunchCtx& L, int stage) {
   if (L.fp32)
     hipLaunchKernelGGL(k_update<float>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
-                       L.nprob, stage);
+                       L.nprob, stage, L.qpart);
   else
     hipLaunchKernelGGL(k_update<double>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
-                       L.nprob, stage);
+                       L.nprob, stage, L.qpart);
 }
 
 }  // namespace hk
