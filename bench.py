@@ -42,7 +42,7 @@ PEAK_HBM = 8000.0  # GB/s
 # equilibrium state and gas-kinetic flux, without the tile's recomputation of halo rows. From the
 # SQ_INSTS_VALU_FLOPS_FP64 counter at two tile shapes, extrapolated to no recomputation
 # (profiles/k_flux_rp1024_counters.txt).
-FLOPS_PER_GP_FP64 = 2616.9
+FLOPS_PER_GP_FP64 = 2558.6
 
 
 def log(*a):
