@@ -280,6 +280,9 @@ __global__ void k_clear_counts(const ProbDev* __restrict__ probs, int nprob) {
 // Stride (in values) of one interface entry of the normal-reconstruction rows in LDS.
 constexpr int kNRS = 17;
 
+// Threads of a flux block: one per Gauss point in 2D (two per interface), one per interface in 1D.
+constexpr int flux_threads(int tn, int tt, int dim) { return (dim == 2 ? 2 : 1) * tn * tt; }
+
 // Tangential reconstruction (Sec. 2.3.3, Step 2) of side s of interface column k at Gauss point gp from
 // the line averages of rows tt..tt+4 (value line W^s and normal-slope line W^s_x): values at the Gauss
 // point, tangential slope of W^s, value of W^s_x. Linear quartic per component, or WENO-AO in the
@@ -338,14 +341,10 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   constexpr int R = (DIM == 2) ? TT + 4 : 1;  // rows with halo
   constexpr int RO = (DIM == 2) ? 2 : 0;      // halo rows below
   constexpr int C = TN + 5;                   // cells along the normal: -3 .. TN+1
-  constexpr int NT = TN * TT;
-  // the cell tile is dead once the normal reconstruction is done; phase 3 then parks the first Gauss
-  // point's F and dF/dt there (8 values per thread) while the second Gauss point is evaluated
-  constexpr int NRAW = (4 * R * C > 8 * NT) ? 4 * R * C : 8 * NT;
-  __shared__ T sRaw[NRAW];
+  constexpr int NTH = flux_threads(TN, TT, DIM);  // 2D: two threads (Gauss points) per interface
+  __shared__ T sW[4][R][C];
   __shared__ uint8_t sF[R][TN + 1];
   __shared__ T sNR[R][TN][kNRS];
-  T(*const sW)[R][C] = reinterpret_cast<T(*)[R][C]>(sRaw);
 
   const int p = find_prob(off, nprob, b);
   const ProbDev& P = probs[p];
@@ -364,7 +363,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
 
   // ---- phase 1: load cells (with ghost synthesis) and flags
   const double* __restrict__ Wsrc = (stage == 1) ? P.W : P.Ws;
-  for (int e = tid; e < R * C; e += NT) {
+  for (int e = tid; e < R * C; e += NTH) {
     int r, c;
     if (dir == 0) { r = e / C; c = e % C; }  // consecutive threads along x
     else { c = e / R; r = e % R; }          // consecutive threads along x (= tangential)
@@ -382,7 +381,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
     for (int k = 0; k < 4; ++k) sW[k][r][c] = T(q[k]);
   }
   const int ex = P.nx + 4;
-  for (int e = tid; e < R * (TN + 1); e += NT) {
+  for (int e = tid; e < R * (TN + 1); e += NTH) {
     const int r = e / (TN + 1), c = e % (TN + 1);
     const int n = n0 - 1 + c, t = (DIM == 2) ? t0 - RO + r : 0;
     const int gi = dir ? t : n, gj = dir ? n : t;
@@ -398,7 +397,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   // ---- phase 2: normal reconstruction of every row (Sec. 2.3.1; line averages in 2D)
   const T ihn = T(dir ? P.ihy : P.ihx);
   const T gam = T(P.gamma), ghi = T(P.ghi), glo = T(P.glo), eps = T(P.eps);
-  for (int e = tid; e < R * TN; e += NT) {
+  for (int e = tid; e < R * TN; e += NTH) {
     const int r = e / TN, k = e % TN;
     T q6[6][4];
 #pragma unroll
@@ -440,10 +439,14 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   }
   __syncthreads();
 
-  // ---- phase 3: tangential reconstruction at the Gauss points, equilibrium state and GKS flux
+  // ---- phase 3: tangential reconstruction at the Gauss points, equilibrium state and GKS flux. In 2D
+  // lanes 2m and 2m+1 take the two Gauss points of interface m (they read the same LDS rows, which the
+  // hardware broadcasts) and add their halves of F and dF/dt with one lane exchange; both lanes of a
+  // pair are live or retired together.
+  const int m = (DIM == 2) ? (tid >> 1) : tid, gp = (DIM == 2) ? (tid & 1) : 0;
   int k, tt;
-  if (dir == 0) { k = tid % TN; tt = tid / TN; }
-  else { tt = tid % TT; k = tid / TT; }
+  if (dir == 0) { k = m % TN; tt = m / TN; }
+  else { tt = m % TT; k = m / TT; }
   const int n = n0 + k, t = t0 + tt;
   if (n > nn || (DIM == 2 && t >= nt)) return;
 
@@ -465,31 +468,22 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   } else {
     const T iht = T(dir ? P.ihx : P.ihy);
     const T K = T(P.K), Kp2 = T(P.Kp2), iKp2 = T(P.iKp2);
-    T* park = sRaw + tid;  // 8 values at stride NT
-#pragma unroll 1
-    for (int gp = 0; gp < 2; ++gp) {
-      FluxAcc<T> acc;
-      T Ws[4], Wxs[4], Wys[4];
-      // tangential reconstruction of one side at this Gauss point, then its share of the flux
-      tangential_side<T, TN, R>(sNR, tt, k, 0, (sF[tt + 2][k] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
-      __builtin_amdgcn_sched_barrier(0);
-      flux_side<0, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
-      __builtin_amdgcn_sched_barrier(0);
-      tangential_side<T, TN, R>(sNR, tt, k, 1, (sF[tt + 2][k + 1] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
-      __builtin_amdgcn_sched_barrier(0);
-      flux_side<1, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
-      __builtin_amdgcn_sched_barrier(0);
-      T Fg[4] = {0, 0, 0, 0}, dFg[4] = {0, 0, 0, 0};
-      flux_finish<PRFIX>(acc, fp, T(0.5), Fg, dFg);
-      if (gp == 0) {
+    FluxAcc<T> acc;
+    T Ws[4], Wxs[4], Wys[4];
+    // tangential reconstruction of one side at this Gauss point, then its share of the flux
+    tangential_side<T, TN, R>(sNR, tt, k, 0, (sF[tt + 2][k] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
+    __builtin_amdgcn_sched_barrier(0);
+    flux_side<0, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    tangential_side<T, TN, R>(sNR, tt, k, 1, (sF[tt + 2][k + 1] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
+    __builtin_amdgcn_sched_barrier(0);
+    flux_side<1, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    flux_finish<PRFIX>(acc, fp, T(0.5), F, dF);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) { park[v * NT] = Fg[v]; park[(4 + v) * NT] = dFg[v]; }
-      } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) { F[v] = park[v * NT] + Fg[v]; dF[v] = park[(4 + v) * NT] + dFg[v]; }
-      }
-      // the parked values leave the registers: no value is carried across the loop in a register
-      __asm__ volatile("" ::: "memory");
+    for (int v = 0; v < 4; ++v) {
+      F[v] += __shfl_xor(F[v], 1, 64);
+      dF[v] += __shfl_xor(dF[v], 1, 64);
     }
   }
 
@@ -510,14 +504,14 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
       if (v == 3) gc = 2;
     }
     if (gc >= nc) continue;
-    if (stage == 1) Fo[gc * plane + o] = F[v];
-    Go[gc * plane + o] = dF[v];
+    if (stage == 1 && gp == 0) Fo[gc * plane + o] = F[v];
+    if (DIM == 1 || gp == 1) Go[gc * plane + o] = dF[v];
   }
 }
 
 // One block per tile; tiles are renumbered so that each XCD works on a contiguous range.
 template <typename T, int TN, int TT, int DIM, bool PRFIX, int WPE>
-__global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WPE)))
+__global__ void __launch_bounds__(flux_threads(TN, TT, DIM)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_flux(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts, const int* __restrict__ off, int nprob,
        int stage) {
   flux_tile<T, TN, TT, DIM, PRFIX>(probs, ts, off, nprob, stage, xcd_swizzle(blockIdx.x, gridDim.x));
@@ -529,7 +523,7 @@ k_flux(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts, const 
 // tiles along a shock over many blocks. Every block leaves the loop after at most ceil(range / blocks)
 // tiles.
 template <typename T, int TN, int TT, int DIM, bool PRFIX, int WPE>
-__global__ void __launch_bounds__(TN * TT) __attribute__((amdgpu_waves_per_eu(WPE)))
+__global__ void __launch_bounds__(flux_threads(TN, TT, DIM)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_flux_persistent(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts, const int* __restrict__ off,
                   int nprob, int stage, int ntiles) {
   const int x = blockIdx.x & 7, li = blockIdx.x >> 3, nloc = gridDim.x >> 3;
@@ -673,16 +667,17 @@ static int resident_grid(const void* fn, int threads, int ntiles) {
 template <typename T, int TN, int TT, int DIM, bool PR, int WPE>
 static void flux_launch(const LaunchCtx& L, int stage, int* grid) {
   constexpr int TNd = (DIM == 1) ? TN * TT : TN, TTd = (DIM == 1) ? 1 : TT;
+  constexpr int NTH = flux_threads(TNd, TTd, DIM);
   if (stage == 0) {
-    *grid = resident_grid(reinterpret_cast<const void*>(k_flux_persistent<T, TNd, TTd, DIM, PR, WPE>), TN * TT,
+    *grid = resident_grid(reinterpret_cast<const void*>(k_flux_persistent<T, TNd, TTd, DIM, PR, WPE>), NTH,
                           L.flux_blocks);
     return;
   }
   if (!L.persistent)
-    hipLaunchKernelGGL((k_flux<T, TNd, TTd, DIM, PR, WPE>), dim3(L.flux_blocks), dim3(TN * TT), 0, L.stream,
+    hipLaunchKernelGGL((k_flux<T, TNd, TTd, DIM, PR, WPE>), dim3(L.flux_blocks), dim3(NTH), 0, L.stream,
                        L.probs, L.ts, L.off_flux, L.nprob, stage);
   else
-    hipLaunchKernelGGL((k_flux_persistent<T, TNd, TTd, DIM, PR, WPE>), dim3(L.persistent_grid), dim3(TN * TT), 0,
+    hipLaunchKernelGGL((k_flux_persistent<T, TNd, TTd, DIM, PR, WPE>), dim3(L.persistent_grid), dim3(NTH), 0,
                        L.stream, L.probs, L.ts, L.off_flux, L.nprob, stage, L.flux_blocks);
 }
 
