@@ -37,12 +37,11 @@ METRIC = "Mcell-updates/s, 2D Euler 1024^2: FP64 plain vs FP32 vs batched, L1 er
 PEAK_FP64_VALU = 78.6  # TFLOP/s, MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (packed)
 PEAK_HBM = 8000.0  # GB/s
-# Algorithmic FP64 operations (FMA = 2) per Gauss-point evaluation of the fused reconstruction + flux
-# kernel on this workload (seed 0, about 2% of the cells troubled): normal and tangential reconstruction,
-# equilibrium state and gas-kinetic flux, without the tile's recomputation of halo rows. From the
-# SQ_INSTS_VALU_FLOPS_FP64 counter at two tile shapes, extrapolated to no recomputation
-# (profiles/k_flux_rp1024_counters.txt).
-FLOPS_PER_GP_FP64 = 2558.6
+# FP64 operations (FMA = 2) per Gauss-point evaluation of the fused reconstruction + flux kernel on this
+# workload (seed 0, about 2% of the cells troubled): normal and tangential reconstruction, equilibrium
+# state and gas-kinetic flux, from the SQ_INSTS_VALU_FLOPS_FP64 counter (the tile's recomputation of halo
+# rows is below 0.5%; profiles/k_flux_rp1024_counters.txt).
+FLOPS_PER_GP_FP64 = 2552.5
 
 
 def log(*a):
