@@ -125,8 +125,8 @@ static void plan(hgks* h) {
     const long cells = (long)q.nx * q.ny;
     const long ext = (long)(q.nx + 4) * (q.dim == 2 ? q.ny + 4 : 1);
     h->tab_cell[p + 1] = h->tab_cell[p] + (int)((cells + 255) / 256);
-    // flag blocks: 16 x 16 tiles of the extended range in 2D, runs of 256 cells in 1D
-    const long fblocks = (q.dim == 2) ? (long)((q.nx + 4 + 15) / 16) * ((q.ny + 4 + 15) / 16) : (ext + 255) / 256;
+    // flag blocks: 32 x 16 tiles of the extended range in 2D, runs of 256 cells in 1D
+    const long fblocks = (q.dim == 2) ? (long)((q.nx + 4 + 31) / 32) * ((q.ny + 4 + 15) / 16) : (ext + 255) / 256;
     h->tab_ext[p + 1] = h->tab_ext[p] + (int)fblocks;
     for (int t = 0; t < kNumTiles; ++t) h->tab_flux[t][p + 1] = h->tab_flux[t][p] + flux_tiles(q.dim, q.nx, q.ny, t);
   }

@@ -415,10 +415,11 @@ __device__ inline void time_integrals(double d, double tau, double e, double C[5
 }
 
 // Both step lengths of the S2O4 flux (dt and dt/2) from one exponential: exp(-dt/tau) is the square of
-// exp(-dt/(2 tau)).
+// exp(-dt/(2 tau)). For dt/(2 tau) > 45 the exponential (< 3e-20) and its products with the other terms
+// (at most dt/tau times larger) stay below half an ulp of every coefficient, so it is taken as 0.
 __device__ inline void time_integrals_pair(double dt, double dth, double tau, double Cd[5], double Ch[5]) {
   double eh = 0.0, ed = 0.0;
-  if (tau > 0.0 && dt >= tau) {
+  if (tau > 0.0 && dt >= tau && dth < 45.0 * tau) {
     eh = exp(-(dth / tau));
     ed = eh * eh;
   }
@@ -549,10 +550,11 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
   auto heat = [&](const T M[4], const T N[4]) -> T {
     return M[3] - U0 * M[1] - V0 * M[2] + cA * M[0] + U0 * V0 * N[2] - U0 * N[3] - cB * N[0];
   };
+  const bool want_F = fp.want_F;  // the second stage needs dF/dt only (uniform per launch)
   auto fold = [&](const T M[4], T cf, T cd) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      F[c] += cf * M[c];
+      if (want_F) F[c] += cf * M[c];
       dF[c] += cd * M[c];
     }
   };

@@ -199,55 +199,69 @@ __global__ void __launch_bounds__(256) k_flags(const ProbDev* __restrict__ probs
   }
 }
 
-// 2D form: a block owns a kFT x kFT tile of the extended range and stages the cells it needs in LDS
+// 2D form: a block owns a kFX x kFY tile of the extended range and stages the cells it needs in LDS
 // (3 beyond the tile on each side, ghosts synthesised), evaluates the indicator T once per cell and
-// direction for the tile plus one cell on each side, then widens it and writes the flags.
-constexpr int kFT = 16;
+// direction for the tile plus one cell on each side, then widens it and writes the flags (two rows per
+// thread).
+constexpr int kFX = 32, kFY = 16, kFThreads = 256;
 
-__global__ void __launch_bounds__(kFT * kFT) k_flags2d(const ProbDev* __restrict__ probs,
+__global__ void __launch_bounds__(kFThreads) k_flags2d(const ProbDev* __restrict__ probs,
                                                       const TimeDev* __restrict__ ts,
                                                       const int* __restrict__ off, int nprob,
                                                       int use_stage_state, int count) {
-  constexpr int L = kFT + 6;
-  __shared__ double sW[4][L][L];          // cell (i0 - 3 + s, j0 - 3 + r) at [c][r][s]
-  __shared__ uint8_t sTx[kFT][kFT + 2];   // T_x of cell (i0 - 1 + a, j0 + b) at [b][a]
-  __shared__ uint8_t sTy[kFT + 2][kFT];   // T_y of cell (i0 + a, j0 - 1 + b) at [b][a]
+  constexpr int LX = kFX + 6, LY = kFY + 6;
+  constexpr int RPT = kFX * kFY / kFThreads;  // output rows per thread
+  __shared__ double sW[4][LY][LX];          // cell (i0 - 3 + s, j0 - 3 + r) at [c][r][s]
+  __shared__ uint8_t sTx[kFY][kFX + 2];     // T_x of cell (i0 - 1 + a, j0 + b) at [b][a]
+  __shared__ uint8_t sTy[kFY + 2][kFX];     // T_y of cell (i0 + a, j0 - 1 + b) at [b][a]
   const int p = find_prob(off, nprob, blockIdx.x);
   const ProbDev& P = probs[p];
   if (!ts[p].active) return;
-  const int ex = P.nx + 4, ey = P.ny + 4;
-  const int tiles_x = (ex + kFT - 1) / kFT;
+  const int ex = P.nx + 4;
+  const int tiles_x = (ex + kFX - 1) / kFX;
   const int lt = blockIdx.x - off[p];
-  const int i0 = (lt % tiles_x) * kFT - 2, j0 = (lt / tiles_x) * kFT - 2;  // first cell of the tile
+  const int i0 = (lt % tiles_x) * kFX - 2, j0 = (lt / tiles_x) * kFY - 2;  // first cell of the tile
   const int tid = threadIdx.x;
-  const int a = tid % kFT, b = tid / kFT;
-  const int i = i0 + a, j = j0 + b;
-  const bool inside = (i < P.nx + 2) && (j < P.ny + 2);
-  int fl = 0;
+  const int a = tid % kFX, b0 = tid / kFX;  // rows b0, b0 + kFY / RPT, ...
+  int fl[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) fl[q] = 0;
   if (P.recon == 1) {
-    fl = 3;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) fl[q] = 3;
   } else if (P.recon == 0) {
     const double* W = use_stage_state ? P.Ws : P.W;
-    for (int e = tid; e < L * L; e += kFT * kFT) {
-      const int r = e / L, c = e % L;
-      double q[4];
-      load_cell(P, W, i0 - 3 + c, j0 - 3 + r, q);
+    // all of a thread's loads are issued before the first LDS store (unrolled, fixed trip count)
+    constexpr int NL = (LX * LY + kFThreads - 1) / kFThreads;
+    double q4[NL][4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) sW[k][r][c] = q[k];
+    for (int u = 0; u < NL; ++u) {
+      const int e = tid + u * kFThreads;
+      if (e < LX * LY) load_cell(P, W, i0 - 3 + e % LX, j0 - 3 + e / LX, q4[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = tid + u * kFThreads;
+      if (e < LX * LY) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sW[k][e / LX][e % LX] = q4[u][k];
+      }
     }
     __syncthreads();
     const double tx = (P.zeta1_mode == 0) ? 5.0 * P.dx : 5.0 * P.dx * P.dx * P.dx;
     const double ty = (P.zeta1_mode == 0) ? 5.0 * P.dy : 5.0 * P.dy * P.dy * P.dy;
-    for (int e = tid; e < kFT * (kFT + 2); e += kFT * kFT) {
-      const int bb = e / (kFT + 2), aa = e % (kFT + 2);  // T_x: row bb, cells aa .. aa+4
+    for (int e = tid; e < kFY * (kFX + 2); e += kFThreads) {  // T_x: row bb, cells aa .. aa+4
+      const int bb = e / (kFX + 2), aa = e % (kFX + 2);
       int t = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         t |= troubled5(sW[k][bb + 3][aa], sW[k][bb + 3][aa + 1], sW[k][bb + 3][aa + 2], sW[k][bb + 3][aa + 3],
                        sW[k][bb + 3][aa + 4], tx);
       sTx[bb][aa] = (uint8_t)t;
-      const int ay = e % kFT, by = e / kFT;            // T_y: column ay, rows by .. by+4
-      t = 0;
+    }
+    for (int e = tid; e < (kFY + 2) * kFX; e += kFThreads) {  // T_y: column ay, rows by .. by+4
+      const int ay = e % kFX, by = e / kFX;
+      int t = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         t |= troubled5(sW[k][by][ay + 3], sW[k][by + 1][ay + 3], sW[k][by + 2][ay + 3], sW[k][by + 3][ay + 3],
@@ -255,17 +269,27 @@ __global__ void __launch_bounds__(kFT * kFT) k_flags2d(const ProbDev* __restrict
       sTy[by][ay] = (uint8_t)t;
     }
     __syncthreads();
-    fl = (sTx[b][a] | sTx[b][a + 1] | sTx[b][a + 2]) | ((sTy[b][a] | sTy[b + 1][a] | sTy[b + 2][a]) << 1);
-  }
-  if (inside) P.flags[(size_t)(j + 2) * ex + (i + 2)] = (uint8_t)fl;
-  if (count) {
-    const bool interior = inside && i >= 0 && i < P.nx && j >= 0 && j < P.ny;
-    const unsigned long long bx = __ballot(interior && (fl & 1));
-    const unsigned long long by = __ballot(interior && (fl & 2));
-    if ((tid & 63) == 0) {
-      if (bx) atomicAdd(&P.flag_count[0], __popcll(bx));
-      if (by) atomicAdd(&P.flag_count[1], __popcll(by));
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int b = b0 + q * (kFY / RPT);
+      fl[q] = (sTx[b][a] | sTx[b][a + 1] | sTx[b][a + 2]) | ((sTy[b][a] | sTy[b + 1][a] | sTy[b + 2][a]) << 1);
     }
+  }
+  int cx = 0, cy = 0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = i0 + a, j = j0 + b0 + q * (kFY / RPT);
+    const bool inside = (i < P.nx + 2) && (j < P.ny + 2);
+    if (inside) P.flags[(size_t)(j + 2) * ex + (i + 2)] = (uint8_t)fl[q];
+    if (count) {
+      const bool interior = inside && i >= 0 && i < P.nx && j >= 0 && j < P.ny;
+      cx += __popcll(__ballot(interior && (fl[q] & 1)));
+      cy += __popcll(__ballot(interior && (fl[q] & 2)));
+    }
+  }
+  if (count && (tid & 63) == 0) {
+    if (cx) atomicAdd(&P.flag_count[0], cx);
+    if (cy) atomicAdd(&P.flag_count[1], cy);
   }
 }
 
@@ -363,22 +387,37 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
 
   // ---- phase 1: load cells (with ghost synthesis) and flags
   const double* __restrict__ Wsrc = (stage == 1) ? P.W : P.Ws;
-  for (int e = tid; e < R * C; e += NTH) {
-    int r, c;
-    if (dir == 0) { r = e / C; c = e % C; }  // consecutive threads along x
-    else { c = e / R; r = e % R; }          // consecutive threads along x (= tangential)
-    const int n = n0 - 3 + c, t = (DIM == 2) ? t0 - RO + r : 0;
-    double q[4];
-    const bool ok = n >= -4 && n <= nn + 3 && (DIM == 1 || (t >= -4 && t <= nt + 3));
-    if (ok) {
-      if (dir == 0) load_cell(P, Wsrc, n, t, q);
-      else load_cell(P, Wsrc, t, n, q);
-      if (dir) { const double s = q[1]; q[1] = q[2]; q[2] = s; }
-    } else {
-      q[0] = 1.0; q[1] = 0.0; q[2] = 0.0; q[3] = 2.5;
-    }
+  // all of a thread's cell loads are issued before the first LDS store (unrolled, fixed trip count)
+  constexpr int NL = (R * C + NTH - 1) / NTH;
+  double q[NL][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sW[k][r][c] = T(q[k]);
+  for (int u = 0; u < NL; ++u) {
+    const int e = tid + u * NTH;
+    if (e < R * C) {
+      int r, c;
+      if (dir == 0) { r = e / C; c = e % C; }  // consecutive threads along x
+      else { c = e / R; r = e % R; }          // consecutive threads along x (= tangential)
+      const int n = n0 - 3 + c, t = (DIM == 2) ? t0 - RO + r : 0;
+      const bool ok = n >= -4 && n <= nn + 3 && (DIM == 1 || (t >= -4 && t <= nt + 3));
+      if (ok) {
+        if (dir == 0) load_cell(P, Wsrc, n, t, q[u]);
+        else load_cell(P, Wsrc, t, n, q[u]);
+      } else {
+        q[u][0] = 1.0; q[u][1] = 0.0; q[u][2] = 0.0; q[u][3] = 2.5;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int e = tid + u * NTH;
+    if (e < R * C) {
+      int r, c;
+      if (dir == 0) { r = e / C; c = e % C; }
+      else { c = e / R; r = e % R; }
+      if (dir) { const double sw = q[u][1]; q[u][1] = q[u][2]; q[u][2] = sw; }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sW[k][r][c] = T(q[u][k]);
+    }
   }
   const int ex = P.nx + 4;
   for (int e = tid; e < R * (TN + 1); e += NTH) {
@@ -578,7 +617,9 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
     const size_t ox = (size_t)j * (P.nx + 1) + i, oy = (size_t)j * P.nx + i;
     double wn[4] = {0, 0, 0, 0};
     bool bad = false;
-    for (int c = 0; c < nc; ++c) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {  // fixed trip count: the components' loads are all in flight together
+      if (c >= nc) break;
       const double gx = (double(Gx[c * px + ox + 1]) - double(Gx[c * px + ox])) * idx;
       const double gy = (P.dim == 2) ? (double(Gy[c * py + oy + P.nx]) - double(Gy[c * py + oy])) * idy : 0.0;
       const double w = P.W[c * ncell + cell];
@@ -642,7 +683,7 @@ void launch_commit(const LaunchCtx& L, int use_tend) {
 void launch_flags(const LaunchCtx& L, int stage_state, int count, int clear) {
   if (clear) hipLaunchKernelGGL(k_clear_counts, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.probs, L.nprob);
   if (L.dim == 2)
-    hipLaunchKernelGGL(k_flags2d, dim3(L.ext_blocks), dim3(kFT * kFT), 0, L.stream, L.probs, L.ts, L.off_ext,
+    hipLaunchKernelGGL(k_flags2d, dim3(L.ext_blocks), dim3(kFThreads), 0, L.stream, L.probs, L.ts, L.off_ext,
                        L.nprob, stage_state, count);
   else
     hipLaunchKernelGGL(k_flags, dim3(L.ext_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_ext, L.nprob,

@@ -22,7 +22,7 @@ struct LaunchCtx {
   TimeDev* ts;           // device array [nprob]
   const int* off_cell;   // prefix sums of 256-cell blocks per problem
   double* qpart;         // CFL minimum of every 256-cell block (cell_blocks entries)
-  const int* off_ext;    // prefix sums of flag blocks over the extended range: 16 x 16 tiles (2D) or
+  const int* off_ext;    // prefix sums of flag blocks over the extended range: 32 x 16 tiles (2D) or
                          // 256-cell runs (1D)
   const int* off_flux;   // prefix sums of flux tiles (x then y) for the current tile shape
   int nprob, dim, fp32, tile;
