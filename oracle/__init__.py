@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_NOSLIP = 0, 1, 2, 3
 RECON_HYBRID, RECON_WENOAO, RECON_LINEAR = 0, 1, 2
 EULER, NS = 0, 1
+OK, EINVAL, ENONPHYS, EDT = 0, -1, -4, -5  # status codes of the C oracle
 
 
 class _Problem(C.Structure):

@@ -77,6 +77,26 @@ def sod_1d(n: int, gamma=GAMMA):
     return prim_to_cons(rho, np.zeros(n), None, p, gamma, dim=1)
 
 
+def shu_osher_1d(n: int = 400, gamma=GAMMA):
+    """Shu-Osher shock / entropy-wave interaction (Sec. 3.2(b)) on [0, 10]: (3.857134, 2.629369, 10.33333)
+    for x < 1, (1 + 0.2 sin(5 x), 0, 1) beyond, as values at the cell centres (x = 1 is a face for n
+    divisible by 10)."""
+    xc = (np.arange(n) + 0.5) * (10.0 / n)
+    left = xc < 1.0
+    rho = np.where(left, 3.857134, 1.0 + 0.2 * np.sin(5.0 * xc))
+    u = np.where(left, 2.629369, 0.0)
+    p = np.where(left, 10.33333, 1.0)
+    return prim_to_cons(rho, u, None, p, gamma, dim=1)
+
+
+def blast_wave_1d(n: int = 400, gamma=GAMMA):
+    """Woodward-Colella interacting blast waves (Sec. 3.2(c)) on [0, 1]: rho = 1, U = 0 and p = 1000 for
+    x < 0.1, 0.01 between, 100 for x > 0.9 (both jumps on faces for n divisible by 10)."""
+    xc = (np.arange(n) + 0.5) / n
+    p = np.where(xc < 0.1, 1000.0, np.where(xc < 0.9, 0.01, 100.0))
+    return prim_to_cons(np.ones(n), np.zeros(n), None, p, gamma, dim=1)
+
+
 def viscous_shock_tube(nx: int, ny: int, gamma=GAMMA):
     """(120, 0, 0, 120/gamma) for x < 0.5 and (1.2, 0, 0, 1.2/gamma) for x > 0.5 on [0,1]x[0,0.5]."""
     xc = (np.arange(nx) + 0.5) / nx

@@ -1,0 +1,133 @@
+"""Long runs against the CPU oracle: whole runs to the end time where the oracle finishes in seconds
+(Shu-Osher, a 256^2 four-quadrant Riemann problem), windows of the 100th step of the viscous shock tube,
+and the blast wave's failure reported the same way by both. After many steps the two states differ by
+rounding order, so the bars are looser than one step's; troubled-cell flags stay bit-exact on an
+identical state."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_05572_amd import hgks as H
+from paper_2304_05572_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def l1(a, b):
+    return float(np.abs(a - b).mean() / np.abs(b).mean())
+
+
+def linf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+SHU = dict(dim=1, nx=400, ny=1, x0=0.0, x1=10.0, bc=(1, 1, 0, 0), cfl=0.5)
+
+
+@pytest.fixture(scope="module")
+def shu_oracle():
+    W, t, n, _ = O.run(O.Problem(**SHU), wl.shu_osher_1d(400), 1.8, nthreads=NT)
+    return W, n
+
+
+@pytest.mark.parametrize("precision,tol1,tolinf", [(H.FP64, 1e-9, 1e-6), (H.FP32_BULK, 1e-4, 1e-2)])
+def test_shu_osher_to_end_time(shu_oracle, precision, tol1, tolinf):
+    """Sec. 3.2(b), 400 cells to t = 1.8 (689 steps), the whole run on the GPU against the oracle's."""
+    Wo, no = shu_oracle
+    say("shu-osher", precision)
+    s = H.Solver(H.Problem(**SHU), precision=precision, use_graph=True)
+    s.set_ic(0, wl.shu_osher_1d(400))
+    steps = s.run(1.8)[0]
+    Wg, t = s.get_state(0)
+    say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+    assert t == 1.8 and abs(int(steps) - no) <= 1
+    assert l1(Wg, Wo) < tol1 and linf(Wg, Wo) < tolinf
+    fx, _ = s.flags(0)
+    ox, _ = O.flags(O.Problem(**SHU), Wg)
+    assert np.array_equal(fx, ox)
+
+
+def test_blast_wave_reported_nonphysical_like_the_oracle():
+    """Sec. 3.2(c) read as stated has no positivity treatment: the first step drives a cell's pressure
+    negative next to the 1e5 pressure jump. Both paths report it as a non-physical state."""
+    kw = dict(dim=1, nx=400, ny=1, bc=(2, 2, 0, 0), cfl=0.5)
+    W0 = wl.blast_wave_1d(400)
+    with pytest.raises(O.OracleError) as eo:
+        O.step(O.Problem(**kw), W0, 0.0)
+    assert eo.value.code == O.ENONPHYS
+    say("blast wave")
+    s = H.Solver(H.Problem(**kw))
+    s.set_ic(0, W0)
+    with pytest.raises(H.HgksError) as eg:
+        s.step()
+    assert eg.value.code == H.ENONPHYS
+
+
+def test_riemann_256_to_end_time():
+    """The seed-0 four-quadrant problem at 256^2 to t = 0.25 in FP64, GPU against oracle over the whole run
+    (about 300 steps, each with its own bit-exact CFL step while the states agree to rounding)."""
+    n = 256
+    kw = dict(dim=2, nx=n, ny=n, bc=(1, 1, 1, 1), cfl=0.5, c1=0.01, c2=1.0)
+    W0, _ = wl.riemann_2d(n, seed=0)
+    say("rp256 to t_end: oracle")
+    Wo, to, no, _ = O.run(O.Problem(**kw), W0, 0.25, nthreads=NT)
+    say("rp256 to t_end: gpu")
+    s = H.Solver(H.Problem(**kw), use_graph=True, autotune=True)
+    s.set_ic(0, W0)
+    steps = s.run(0.25)[0]
+    Wg, t = s.get_state(0)
+    say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+    assert t == 0.25 and steps == no
+    assert l1(Wg, Wo) < 1e-9 and linf(Wg, Wo) < 1e-6
+    fx, fy = s.flags(0)
+    ox, oy = O.flags(O.Problem(**kw), Wg)
+    assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
+
+
+def test_viscous_shock_tube_hundredth_step():
+    """Navier-Stokes, 1000 x 500, Re = 200, Pr = 0.73: the 100th FP64 step on windows over the shock, the
+    contact, the wall corners and the symmetry line against the oracle (each window one oracle step with
+    the GPU's dt, margins beyond the dependency radius); FP32-bulk after 100 steps against FP64."""
+    nx, ny = 1000, 500
+    kw = dict(dim=2, nx=nx, ny=ny, y1=0.5, bc=(3, 3, 3, 2), eqn=1, mu=1 / 200, Pr=0.73, cfl=0.3, c1=0.01, c2=1.0)
+    W0 = wl.viscous_shock_tube(nx, ny)
+    say("vst 100 steps fp64")
+    s = H.Solver(H.Problem(**kw), autotune=True, use_graph=True)
+    s.set_ic(0, W0)
+    s.run(np.inf, 99)
+    W99, t99 = s.get_state(0)
+    dt = s.step()[0]
+    W100, _ = s.get_state(0)
+    h = 1.0 / nx
+    worst = 0.0
+    for (ci, cj) in [(500, 250), (520, 30), (560, 480), (30, 20), (970, 490), (700, 300)]:
+        half, margin = 24, 10
+        i0, i1 = max(ci - half - margin, 0), min(ci + half + margin, nx)
+        j0, j1 = max(cj - half - margin, 0), min(cj + half + margin, ny)
+        sub = np.ascontiguousarray(W99[:, j0:j1, i0:i1])
+        wbc = (3 if i0 == 0 else 1, 3 if i1 == nx else 1, 3 if j0 == 0 else 1, 2 if j1 == ny else 1)
+        P = O.Problem(dim=2, nx=i1 - i0, ny=j1 - j0, x0=i0 * h, x1=i1 * h, y0=j0 * h, y1=j1 * h, bc=wbc, eqn=1,
+                      mu=1 / 200, Pr=0.73, fixed_dt=dt, c1=0.01, c2=1.0)
+        Wo, _, _ = O.step(P, sub, t99, nthreads=NT)
+        a0 = 0 if i0 == 0 else margin
+        a1 = (i1 - i0) if i1 == nx else (i1 - i0 - margin)
+        b0 = 0 if j0 == 0 else margin
+        b1 = (j1 - j0) if j1 == ny else (j1 - j0 - margin)
+        worst = max(worst, linf(W100[:, j0 + b0:j0 + b1, i0 + a0:i0 + a1], Wo[:, b0:b1, a0:a1]))
+    say("vst window Linf", worst)
+    assert worst < 1e-12
+    say("vst 100 steps fp32-bulk")
+    s32 = H.Solver(H.Problem(**kw), precision=H.FP32_BULK, autotune=True, use_graph=True)
+    s32.set_ic(0, W0)
+    s32.run(np.inf, 100)
+    W32, _ = s32.get_state(0)
+    say("fp32 vs fp64 after 100 steps L1", l1(W32, W100), "Linf", linf(W32, W100))
+    assert l1(W32, W100) < 1e-6

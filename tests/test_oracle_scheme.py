@@ -135,6 +135,36 @@ def test_sod_hybrid_close_to_weno_ao():
     assert np.abs(out[0][0] - out[1][0]).mean() < 2e-3
 
 
+def test_shu_osher_shock_front():
+    """Sec. 3.2(b): the Mach-3 shock of the Shu-Osher problem (pressure ratio 10.33 gives M = 3 by the
+    Rankine-Hugoniot relations) moves at 3 c_R into the entropy wave, c_R = sqrt(1.4 / rho_R) with rho_R in
+    [0.8, 1.2]: at t = 1.8 its front lies between x = 1 + 3.24 t and 1 + 3.97 t, i.e. in [6.8, 8.2], and
+    near 7.4 for the mean density; the state right behind it has the Mach-3 pressure ratio. Positivity
+    holds throughout. (The paper holds the analytic wave profile fixed beyond x = 10; with zero-gradient
+    ghosts instead, a weak rarefaction enters from the right boundary, away from the pinned front.)"""
+    n = 400
+    P = O.Problem(dim=1, nx=n, ny=1, x0=0.0, x1=10.0, bc=(O.BC_OUTFLOW, O.BC_OUTFLOW, 0, 0), cfl=0.5)
+    W0 = wl.shu_osher_1d(n)
+    W, t, ns, _ = O.run(P, W0, 1.8, nthreads=NT)
+    assert t == 1.8
+    rho, u, _, p = wl.cons_to_prim(W)
+    assert rho.min() > 0 and p.min() > 0
+    x = (np.arange(n) + 0.5) * (10.0 / n)
+    i = np.nonzero(p > 2.0)[0].max()  # last cell behind the shock (p jumps from 1 to ~10)
+    assert 6.8 < x[i] < 8.2 and abs(x[i] - 7.4) < 0.25
+    assert 8.5 < p[i - 2] < 12.5 and abs(p[i + 3] - 1.0) < 0.01
+
+
+def test_blast_wave_fails_at_first_step_as_read():
+    """Sec. 3.2(c), read as stated (no positivity treatment is given): at the 1e5 pressure jump the
+    second-stage dF/dt term of the first step drives a cell's pressure negative, which the oracle reports
+    as a non-physical state rather than producing NaNs."""
+    P = O.Problem(dim=1, nx=400, ny=1, bc=(O.BC_REFLECT, O.BC_REFLECT, 0, 0), cfl=0.5)
+    with pytest.raises(O.OracleError) as e:
+        O.step(P, wl.blast_wave_1d(400), 0.0)
+    assert e.value.code == O.ENONPHYS
+
+
 def test_conservation_periodic():
     rng = np.random.default_rng(2)
     n, m = 24, 20
