@@ -95,9 +95,19 @@ __global__ void __launch_bounds__(256) k_dt_finalize(const ProbDev* __restrict__
                                                      const int* __restrict__ off, const double* __restrict__ qpart,
                                                      int use_tend) {
   const int p = blockIdx.x;
-  double q = __builtin_inf();
-  for (int b = off[p] + threadIdx.x; b < off[p + 1]; b += blockDim.x) q = fmin(q, qpart[b]);
-  q = block_min(q);
+  // four independent loads in flight per thread, then the tree
+  double q0 = __builtin_inf(), q1 = q0, q2 = q0, q3 = q0;
+  const int b1 = off[p + 1];
+  const int stride = blockDim.x;
+  int b = off[p] + threadIdx.x;
+  for (; b + 3 * stride < b1; b += 4 * stride) {
+    q0 = fmin(q0, qpart[b]);
+    q1 = fmin(q1, qpart[b + stride]);
+    q2 = fmin(q2, qpart[b + 2 * stride]);
+    q3 = fmin(q3, qpart[b + 3 * stride]);
+  }
+  for (; b < b1; b += stride) q0 = fmin(q0, qpart[b]);
+  double q = block_min(fmin(fmin(q0, q1), fmin(q2, q3)));
   if (threadIdx.x != 0) return;
   TimeDev& s = ts[p];
   const ProbDev& P = probs[p];
@@ -214,12 +224,14 @@ __global__ void __launch_bounds__(kFThreads) k_flags2d(const ProbDev* __restrict
   __shared__ double sW[4][LY][LX];          // cell (i0 - 3 + s, j0 - 3 + r) at [c][r][s]
   __shared__ uint8_t sTx[kFY][kFX + 2];     // T_x of cell (i0 - 1 + a, j0 + b) at [b][a]
   __shared__ uint8_t sTy[kFY + 2][kFX];     // T_y of cell (i0 + a, j0 - 1 + b) at [b][a]
-  const int p = find_prob(off, nprob, blockIdx.x);
+  // neighbouring tiles share their halos: keep them on one XCD (and its L2)
+  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int p = find_prob(off, nprob, blk);
   const ProbDev& P = probs[p];
   if (!ts[p].active) return;
   const int ex = P.nx + 4;
   const int tiles_x = (ex + kFX - 1) / kFX;
-  const int lt = blockIdx.x - off[p];
+  const int lt = blk - off[p];
   const int i0 = (lt % tiles_x) * kFX - 2, j0 = (lt / tiles_x) * kFY - 2;  // first cell of the tile
   const int tid = threadIdx.x;
   const int a = tid % kFX, b0 = tid / kFX;  // rows b0, b0 + kFY / RPT, ...
