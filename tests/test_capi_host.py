@@ -66,3 +66,48 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(H, "LIB_PATH", str(tmp_path / "libhgks.so"))
     with pytest.raises(H.HgksLibraryMissing):
         H.lib()
+
+
+C_EXAMPLE = r"""
+#include <stdint.h>
+#include "hgks.h"
+/* the usage example of the README: the header is plain C and the documented calls type-check */
+int run_example(const double* W0, double* W) {
+  hgks_problem p = {.dim = 2, .nx = 1024, .ny = 1024, .x1 = 1, .y1 = 1, .eqn = HGKS_EULER, .gamma = 1.4,
+                    .Pr = 1, .cfl = 0.5, .c1 = 0.01, .c2 = 1, .bc = {1, 1, 1, 1}, .recon = HGKS_RECON_HYBRID,
+                    .gamma_hi = 0.85, .gamma_lo = 0.85, .weno_eps = 1e-8};
+  hgks_opts o = {.precision = HGKS_FP64, .autotune = 1, .use_graph = 1, .tile = -1};
+  hgks_t* h;
+  double t = 0.0, t_end = 0.25;
+  int32_t tile[5];
+  double prof[8];
+  if (hgks_create(&p, 1, &o, &h) != HGKS_OK) return 1;
+  hgks_set_ic(h, 0, W0, 0, 0.0);
+  hgks_run(h, &t_end, INT64_MAX, NULL);
+  hgks_get_state(h, 0, W, 0, &t);
+  hgks_get_state_lo(h, 0, W, 0);
+  hgks_get_tile(h, tile);
+  hgks_get_profile(h, prof);
+  hgks_destroy(h);
+  return (int)hgks_status_str(HGKS_OK)[0] + HGKS_NUM_LAUNCH_CONFIGS;
+}
+"""
+
+
+def test_header_is_plain_c_and_the_readme_example_compiles(tmp_path):
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "example.c"
+    src.write_text(C_EXAMPLE)
+    r = subprocess.run([cc, "-std=c11", "-Wall", "-Werror", "-pedantic", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_launch_config_count_matches_binding():
+    src = open(HEADER).read()
+    m = re.search(r"#define HGKS_NUM_LAUNCH_CONFIGS (\d+)", src)
+    assert m and int(m.group(1)) == H.NUM_LAUNCH_CONFIGS
