@@ -208,3 +208,20 @@ def test_workspace_bound_from_torch_matches_library_allocation():
     out = torch.empty(W0.shape, dtype=torch.float64, device="cuda")
     a.get_state(0, out)
     assert np.array_equal(out.cpu().numpy(), b.get_state(0)[0])
+
+
+def test_largest_grid_64bit_offsets():
+    """8192^2 cells (state arrays of 2.1 GB, flux arrays beyond 2^31 bytes): one FP64 step, windows at the
+    origin, the centre and the far corner (whose byte offsets need 64 bits) against the oracle."""
+    n = 8192
+    W0, _ = wl.riemann_2d(n, seed=4)
+    say("8192^2 one step")
+    s = H.Solver(H.Problem(**rp(n)), precision=H.FP64)
+    s.set_ic(0, W0)
+    dt = s.step()[0]
+    W1, _ = s.get_state(0)
+    worst = _window_check(W0, W1, dt, n, [(20, 20), (4096, 4096), (8170, 8175), (4096, 8180)], cfl=0.5, c1=0.01,
+                          c2=1.0)
+    say("worst window Linf", worst)
+    assert worst < 1e-12
+    del W1
