@@ -22,7 +22,13 @@
  *     hgks_bind_workspace, which it borrows until hgks_destroy and never frees.
  *   - Every call returns an hgks_status. Device-side failures (a non-physical state) are sticky:
  *     they are reported by the next hgks_step / hgks_run / hgks_get_state of that handle.
- *   - A handle is not thread-safe; calls on one handle must not overlap.
+ *   - A handle is not thread-safe; calls on one handle must not overlap. It lives on the HIP device
+ *     current at hgks_create; every later call must be made with that device current.
+ *   - Streams: all work of a handle is issued on one stream (opts.hip_stream, or a non-blocking stream
+ *     the library creates). Device buffers passed in must be ready on that stream: either the caller
+ *     produced them on the same stream, or it synchronised its own stream before the call (the
+ *     library's own stream does not wait for other streams). Calls that return data synchronise the
+ *     stream before returning, so device buffers filled by the library are ready on return.
  */
 #ifndef HGKS_H
 #define HGKS_H
@@ -116,7 +122,9 @@ size_t hgks_workspace_bytes(const hgks_t* h);
  * Must precede the first hgks_set_ic. */
 hgks_status hgks_bind_workspace(hgks_t* h, void* dev_ptr, size_t bytes);
 
-/* Upload the cell averages of problem `prob` and set its time to t0. */
+/* Upload the cell averages of problem `prob` ([nc][ny][nx] FP64, host or device as `on_device`
+ * says) and set its time to t0; recomputes the CFL minimum of the handle's problems. Synchronises the
+ * stream. */
 hgks_status hgks_set_ic(hgks_t* h, int32_t prob, const double* W, int32_t on_device, double t0);
 
 /* Advance every problem by one S2O4 step of its own CFL (or fixed) time step, with no end time.

@@ -191,6 +191,10 @@ def hgks_bind_workspace(h, buf, nbytes: int):
 def hgks_set_ic(h, prob: int, W, t0: float = 0.0):
     if not hasattr(W, "data_ptr"):
         W = np.ascontiguousarray(W, dtype=np.float64)
+    elif W.is_cuda:
+        # the library's stream does not wait for torch's: make the tensor's producer finish first
+        import torch
+        torch.cuda.current_stream(W.device).synchronize()
     ptr, dev = _addr(W)
     _check(lib().hgks_set_ic(h, int(prob), ptr, dev, float(t0)), "hgks_set_ic")
 
