@@ -184,6 +184,10 @@ def hgks_workspace_bytes(h) -> int:
 
 
 def hgks_bind_workspace(h, buf, nbytes: int):
+    if hasattr(buf, "is_cuda") and buf.is_cuda:
+        # torch's allocator may hand out memory that earlier work on torch's stream still uses
+        import torch
+        torch.cuda.current_stream(buf.device).synchronize()
     ptr, _ = _addr(buf)
     _check(lib().hgks_bind_workspace(h, ptr, int(nbytes)), "hgks_bind_workspace")
 
