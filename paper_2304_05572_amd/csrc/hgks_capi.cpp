@@ -239,6 +239,21 @@ static hgks_status write_ts(hgks* h, const std::vector<TimeDev>& ts) {
   return HGKS_OK;
 }
 
+// Restores a saved device time state when a debug entry point returns, on every path (the debug calls
+// temporarily change the active flags and dt of the handle's problems).
+struct TimeStateRestore {
+  hgks* h;
+  const std::vector<TimeDev>& saved;
+  bool done = false;
+  hgks_status restore() {
+    done = true;
+    return write_ts(h, saved);
+  }
+  ~TimeStateRestore() {
+    if (!done) (void)write_ts(h, saved);
+  }
+};
+
 static hipEvent_t take_event(hgks* h) {
   if (!h->spare.empty()) {
     hipEvent_t e = h->spare.back();
@@ -608,6 +623,7 @@ hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy) 
   hgks_status s = read_ts(h, ts);
   if (s) return s;
   saved = ts;
+  TimeStateRestore guard{h, saved};
   for (int p = 0; p < h->nprob; ++p) ts[p].active = (p == prob);
   s = write_ts(h, ts);
   if (s) return s;
@@ -619,7 +635,7 @@ hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy) 
   HIPOK(hipMemcpyAsync(buf.data(), h->ws + h->off_flags[prob], buf.size(), hipMemcpyDeviceToHost, h->stream));
   int cnt[2];
   HIPOK(hipMemcpyAsync(cnt, h->ws + h->off_cnt[prob], sizeof cnt, hipMemcpyDeviceToHost, h->stream));
-  s = write_ts(h, saved);
+  s = guard.restore();  // synchronises the stream: buf and cnt are complete
   if (s) return s;
   const int jo = q.dim == 2 ? 2 : 0;
   for (int j = 0; j < q.ny; ++j)
@@ -644,6 +660,7 @@ hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* 
   hgks_status s = read_ts(h, ts);
   if (s) return s;
   saved = ts;
+  TimeStateRestore guard{h, saved};
   for (int p = 0; p < h->nprob; ++p) {
     ts[p].active = (p == prob);
     set_time_step(ts[p], dt);
@@ -674,7 +691,7 @@ hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* 
     if ((s = fetch(h->off_Fy[prob], nyf, Fy))) return s;
     if ((s = fetch(h->off_Gy[prob], nyf, Gy))) return s;
   }
-  return write_ts(h, saved);
+  return guard.restore();
 }
 
 hgks_status hgks_get_stats(const hgks_t* hc, int32_t prob, double* out) {
