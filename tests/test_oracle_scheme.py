@@ -125,6 +125,27 @@ def test_sod_converges_to_exact_solution():
     assert errs[1] < 0.65 * errs[0]
 
 
+def test_riemann_2d_edges_follow_exact_1d_solutions():
+    """Far from the centre each edge of a four-quadrant problem is a 1D Riemann problem until the corner
+    interaction arrives (at t = 0.1 the waves from the centre have not reached y = 0.9 or x = 0.9): the
+    row y = 0.9 follows the exact solution between the upper-left and upper-right states in (rho, U, p),
+    the column x = 0.9 the one between the lower-right and upper-right states in (rho, V, p), within the
+    L1 bound the 1D Sod test allows at a comparable cell count (the discontinuities limit the accuracy
+    to first order)."""
+    n = 128
+    W0, st = wl.riemann_2d(n, seed=0)
+    P = O.Problem(dim=2, nx=n, ny=n, bc=(1, 1, 1, 1), cfl=0.5, c1=0.01, c2=1.0)
+    W, t, ns, _ = O.run(P, W0, 0.1, nthreads=NT)
+    rho, u, v, p = wl.cons_to_prim(W)
+    assert rho.min() > 0 and p.min() > 0
+    k = int(0.9 * n)
+    row = ER.cell_averages((st[1][0], st[1][1], st[1][3]), (st[0][0], st[0][1], st[0][3]), n, 0.1)
+    col = ER.cell_averages((st[3][0], st[3][2], st[3][3]), (st[0][0], st[0][2], st[0][3]), n, 0.1)
+    errs = [np.abs(rho[k] - row[0]).mean(), np.abs(u[k] - row[1]).mean(), np.abs(p[k] - row[2]).mean(),
+            np.abs(rho[:, k] - col[0]).mean(), np.abs(v[:, k] - col[1]).mean(), np.abs(p[:, k] - col[2]).mean()]
+    assert max(errs) < 4e-3, errs
+
+
 def test_sod_hybrid_close_to_weno_ao():
     """Sec. 3.2(a): the hybrid and the WENO-AO solutions are almost identical."""
     n = 200
