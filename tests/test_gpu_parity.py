@@ -253,3 +253,30 @@ def test_fp32_bulk_close_to_oracle():
     l1 = np.abs(Wg - Wo).mean() / np.abs(Wo).mean()
     say("fp32 L1_rel", l1, "Linf_rel", rel(Wg, Wo))
     assert l1 < 1e-5 and rel(Wg, Wo) < 1e-3
+
+
+def test_batch_1d_uneven_with_minimum_size():
+    """1D problems of uneven sizes down to the minimum of 5 cells in one handle: each advances exactly as
+    when run alone (own dt) and matches the oracle."""
+    specs = [(dict(dim=1, nx=200, ny=1, bc=(2, 2, 0, 0)), wl.sod_1d(200)),
+             (dict(dim=1, nx=400, ny=1, x0=0.0, x1=10.0, bc=(1, 1, 0, 0)), wl.shu_osher_1d(400)),
+             (dict(dim=1, nx=5, ny=1, x1=2.0, bc=(0, 0, 0, 0)), wl.advection_1d(5)),
+             (dict(dim=1, nx=37, ny=1, bc=(3, 1, 0, 0)), wl.sod_1d(37))]
+    say("batch 1d")
+    sb = H.Solver([H.Problem(**kw) for kw, _ in specs])
+    for p, (_, W) in enumerate(specs):
+        sb.set_ic(p, W)
+    for _ in range(4):
+        dts = sb.step()
+    for p, (kw, W) in enumerate(specs):
+        s1 = H.Solver(H.Problem(**kw))
+        s1.set_ic(0, W)
+        for _ in range(4):
+            dt1 = s1.step()[0]
+        assert dt1 == dts[p]
+        a, _ = sb.get_state(p)
+        assert np.array_equal(a, s1.get_state(0)[0])
+        Wo, t = W.copy(), 0.0
+        for _ in range(4):
+            Wo, t, _ = O.step(O.Problem(**kw), Wo, t, nthreads=NT)
+        assert rel(a, Wo) < 1e-11
