@@ -225,3 +225,52 @@ def test_largest_grid_64bit_offsets():
     say("worst window Linf", worst)
     assert worst < 1e-12
     del W1
+
+
+def dyadic_cells(shape, nc, seed, block=64):
+    """Cell averages on small dyadic alphabets (k/4 and 3k/8 for k = 0..3, k/2 for k = 1..16) with a cell
+    size of 1, so that the indicator's sums are exact and many decisions fall exactly on a threshold
+    (|D2| = 5 dx, |xbar| = 5/2, |xbar - xhat| = 1/4): there only a correctly rounded FP64 division in the
+    canonical operation order gives the oracle's answer. Each block of cells draws one component from one
+    alphabet (the other components stay constant, hence smooth), so that the OR over components and the
+    widening mask few decisions in the blocks of the first two alphabets, whose flagged fraction is low."""
+    table = np.concatenate([np.tile(np.arange(4) / 4, 4), np.tile(np.arange(4) * 3 / 8, 4),
+                            np.arange(1, 17) / 2])
+    rng = np.random.default_rng(seed)
+    code = rng.integers(0, 16, shape, dtype=np.int16)
+    axes = [(np.arange(m) // block).reshape([-1 if a == d else 1 for a in range(len(shape))])
+            for d, m in enumerate(shape)]
+    b = sum(ax * (1 + 6 * d) for d, ax in enumerate(reversed(axes)))
+    comp, alph = b % nc, (b // nc) % 3
+    code += (alph * 16).astype(np.int16)
+    q = table[code]
+    del code
+    W = np.empty((nc,) + tuple(shape))
+    for c, const in enumerate([1.0] + [0.0] * (nc - 2) + [2.5]):
+        W[c] = np.where(comp == c, q, const)
+    return W
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_flags_bit_exact_on_1e8_cells_at_exact_thresholds(dim):
+    """The indicator's divisions and comparisons on 10^8 cells built to land exactly on its thresholds:
+    the widened flags of every cell equal the oracle's."""
+    if dim == 1:
+        n = 10 ** 8
+        kw = dict(dim=1, nx=n, ny=1, x0=0.0, x1=float(n), bc=(0, 0, 0, 0))
+        W = dyadic_cells((n,), 3, seed=21, block=500)
+    else:
+        n = 10 ** 4
+        kw = dict(dim=2, nx=n, ny=n, x0=0.0, x1=float(n), y0=0.0, y1=float(n), bc=(0, 0, 0, 0))
+        W = dyadic_cells((n, n), 4, seed=22)
+    say("flags at exact thresholds, dim", dim)
+    s = H.Solver(H.Problem(**kw))
+    s.set_ic(0, W)
+    got = s.flags(0)
+    s.close()
+    ref = O.flags(O.Problem(**kw), W)
+    del W
+    for d in range(dim):
+        say("direction", d, "flagged fraction", float(ref[d].mean()))
+        assert 0.05 < ref[d].mean() < 0.7
+        assert np.array_equal(got[d], ref[d])
