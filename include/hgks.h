@@ -53,13 +53,32 @@ typedef enum { HGKS_EULER = 0, HGKS_NS = 1 } hgks_eqn;
 
 /* Boundary conditions (Sec. 3): periodic; zero-gradient outflow ("non-reflecting"); reflecting
  * slip wall / symmetry plane (normal momentum negated in the ghost cells); no-slip adiabatic wall
- * (both momenta negated in the ghost cells). */
+ * (both momenta negated in the ghost cells); prescribed state (hgks_bc_data), for inflow sides and
+ * the double Mach reflection of Sec. 3.5 (post-shock state on part of the bottom, the exact moving
+ * Mach 10 shock along the top). Ghost cells of the x-sides are synthesised on the interior rows, those
+ * of the y-sides across the full padded width, so a corner cell follows the y-side's rule applied to
+ * the x-ghost beside it. */
 typedef enum {
   HGKS_BC_PERIODIC = 0,
   HGKS_BC_OUTFLOW = 1,
   HGKS_BC_REFLECT = 2,
-  HGKS_BC_NOSLIP_ADIABATIC = 3
+  HGKS_BC_NOSLIP_ADIABATIC = 3,
+  HGKS_BC_PRESCRIBED = 4
 } hgks_bc;
+
+/* Data of a HGKS_BC_PRESCRIBED side. A ghost cell of the side whose centre has tangential coordinate
+ * tau (y on an x-side, 0 in 1D; x on a y-side) and normal coordinate nu takes the conserved state `a`
+ * where tau < s0 + sn * nu + st * t, and beyond that split either the state `b` (rest ==
+ * HGKS_BC_PRESCRIBED) or the ghost of the boundary kind `rest` (outflow, reflect or no-slip). t is the
+ * time of the stage being evaluated: t_n in the first stage, t_n + dt/2 in the second (the
+ * intermediate state of the two-stage step belongs to the half step). States are (rho, rho U, rho V,
+ * rho E) and must be physical; 1D problems use a[0], a[1], a[3]. s0 = +infinity makes the side one
+ * state. The comparison is evaluated in FP64 without contraction, so that its outcome is reproducible. */
+typedef struct {
+  double a[4], b[4];
+  double s0, sn, st;
+  int32_t rest, reserved;
+} hgks_bc_data;
 
 /* Reconstruction: the hybrid scheme, or every cell troubled (the WENO5-AO GKS the paper compares
  * against), or no cell troubled (pure linear upwind). */
@@ -88,6 +107,17 @@ typedef struct {
   double gamma_hi, gamma_lo, weno_eps;  /* WENO-AO linear weights and epsilon (0.85, 0.85, 1e-8) */
   int32_t zeta1_mode;           /* Step-1 threshold: 0 -> 5*h on the normalised quadratic, 1 -> 5*h^3 */
   int32_t tangential_flag_mode; /* 0: tangential step uses the perpendicular-direction cell flag */
+  int32_t positivity;           /* 0: the scheme as the paper states it. 1: two first-order fallbacks.
+                                   A reconstructed state with rho <= 0 or p <= 0 (or not finite) drops to
+                                   first order in space: a normal interface value takes its cell's average
+                                   with zero normal slope, a Gauss-point value the interface's
+                                   centre-segment line values with zero tangential slope. And every face of
+                                   a cell that the S2O4 update leaves non-physical takes the one-stage flux
+                                   F^n + dt/2 dF^n/dt of the first stage (first order lower in time, still
+                                   conservative); a cell still non-physical then is reported. The paper
+                                   gives no positivity treatment; its double Mach reflection and blast wave
+                                   do not run without one. */
+  hgks_bc_data bcd[4];          /* per side, read where bc[side] == HGKS_BC_PRESCRIBED */
 } hgks_problem;
 
 typedef struct {
@@ -142,12 +172,12 @@ hgks_status hgks_get_state(const hgks_t* h, int32_t prob, double* W, int32_t on_
  * was created with opts.compensated == 1; zeros otherwise. Synchronises the stream. */
 hgks_status hgks_get_state_lo(const hgks_t* h, int32_t prob, double* E, int32_t on_device);
 
-/* Widened troubled-cell flags (Steps 1-4) of the current state of problem `prob`, one byte per cell
- * ([ny][nx]); fy is ignored in 1D. */
+/* Widened troubled-cell flags (Steps 1-4) of the current state of problem `prob` at its current time,
+ * one byte per cell ([ny][nx]); fy is ignored in 1D. */
 hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy);
 
-/* Interface flux F and its time derivative dF/dt of the current state for time step dt, as used by
- * the first stage (Sec. 2.2). Host arrays, FP64: Fx, Gx [nc][ny][nx+1]; Fy, Gy [nc][ny+1][nx] (2D). */
+/* Interface flux F and its time derivative dF/dt of the current state at its current time for time
+ * step dt, as used by the first stage (Sec. 2.2). Host arrays, FP64: Fx, Gx [nc][ny][nx+1]; Fy, Gy [nc][ny+1][nx] (2D). */
 hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx,
                                     double* Fy, double* Gy);
 

@@ -17,10 +17,28 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_NOSLIP = 0, 1, 2, 3
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_NOSLIP, BC_PRESCRIBED = 0, 1, 2, 3, 4
 RECON_HYBRID, RECON_WENOAO, RECON_LINEAR = 0, 1, 2
 EULER, NS = 0, 1
 OK, EINVAL, ENONPHYS, EDT = 0, -1, -4, -5  # status codes of the C oracle
+
+
+class _BcData(C.Structure):
+    _fields_ = [("a", C.c_double * 4), ("b", C.c_double * 4), ("s0", C.c_double), ("sn", C.c_double),
+                ("st", C.c_double), ("rest", C.c_int32), ("pad", C.c_int32)]
+
+
+@dataclasses.dataclass
+class BcData:
+    """A prescribed-state side (boundary kind 4): a ghost cell takes the conserved state ``a`` where its
+    tangential coordinate is below s0 + sn * (its normal coordinate) + st * t, else state ``b``
+    (rest = 4) or the ghost of boundary kind ``rest`` (1 outflow, 2 reflect, 3 no-slip)."""
+    a: tuple = (1.0, 0.0, 0.0, 2.5)
+    b: tuple = (1.0, 0.0, 0.0, 2.5)
+    s0: float = float("inf")
+    sn: float = 0.0
+    st: float = 0.0
+    rest: int = BC_PRESCRIBED
 
 
 class _Problem(C.Structure):
@@ -31,7 +49,8 @@ class _Problem(C.Structure):
         ("cfl", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("fixed_dt", C.c_double),
         ("bc", C.c_int32 * 4), ("recon", C.c_int32),
         ("gamma_hi", C.c_double), ("gamma_lo", C.c_double), ("weno_eps", C.c_double),
-        ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32),
+        ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32), ("positivity", C.c_int32),
+        ("bcd", _BcData * 4),
     ]
 
 
@@ -60,6 +79,8 @@ class Problem:
     weno_eps: float = 1e-8
     zeta1_mode: int = 0
     tangential_flag_mode: int = 0
+    positivity: int = 0  # 1: first-order fallback for non-physical reconstructed states
+    bcd: tuple = ()  # BcData per side (x-low, x-high, y-low, y-high), read where bc is BC_PRESCRIBED
 
     @property
     def nc(self) -> int:
@@ -76,6 +97,15 @@ class Problem:
             if f.name == "bc":
                 arr = (C.c_int32 * 4)(*[int(b) for b in (list(v) + [0] * 4)[:4]])
                 s.bc = arr
+            elif f.name == "bcd":
+                for k, d in enumerate(list(v)[:4]):
+                    if d is None:
+                        continue
+                    if isinstance(d, dict):
+                        d = BcData(**d)
+                    s.bcd[k].a = (C.c_double * 4)(*d.a)
+                    s.bcd[k].b = (C.c_double * 4)(*d.b)
+                    s.bcd[k].s0, s.bcd[k].sn, s.bcd[k].st, s.bcd[k].rest = d.s0, d.sn, d.st, int(d.rest)
             else:
                 setattr(s, f.name, v)
         return s
@@ -95,10 +125,10 @@ def lib():
         P = C.POINTER(_Problem)
         dp = C.POINTER(C.c_double)
         sig = {
-            "oracle_flags": (i32, [P, vp, vp, vp]),
+            "oracle_flags": (i32, [P, vp, d, vp, vp]),
             "oracle_cfl_dt": (d, [P, vp]),
             "oracle_step": (i32, [P, vp, dp, d, dp, i32]),
-            "oracle_stage_fluxes": (i32, [P, vp, d, vp, vp, vp, vp, i32]),
+            "oracle_stage_fluxes": (i32, [P, vp, d, d, vp, vp, vp, vp, i32]),
             "oracle_stencil_eval": (None, [i32, vp, d, dp, dp]),
             "oracle_beta": (d, [i32, vp]),
             "oracle_ao_eval": (None, [vp, d, d, d, d, dp, dp]),
@@ -131,14 +161,15 @@ class OracleError(RuntimeError):
 
 
 # ---------------------------------------------------------------- whole scheme
-def flags(prob: Problem, W):
-    """Widened troubled-cell flags (Sec. 2.3.1 Steps 1-4) of every interior cell: (fx, fy)."""
+def flags(prob: Problem, W, t: float = 0.0):
+    """Widened troubled-cell flags (Sec. 2.3.1 Steps 1-4) of every interior cell: (fx, fy); t is the time
+    at which prescribed-state sides are evaluated."""
     W = _f64(W)
     ps = prob.c_struct()
     cells = prob.nx * (prob.ny if prob.dim == 2 else 1)
     fx = np.zeros(cells, np.uint8)
     fy = np.zeros(cells, np.uint8)
-    rc = lib().oracle_flags(C.byref(ps), _ptr(W), _ptr(fx), _ptr(fy))
+    rc = lib().oracle_flags(C.byref(ps), _ptr(W), float(t), _ptr(fx), _ptr(fy))
     if rc:
         raise OracleError(rc)
     shp = (prob.nx,) if prob.dim == 1 else (prob.ny, prob.nx)
@@ -175,8 +206,9 @@ def run(prob: Problem, W, t_end: float, max_steps: int = 10**9, t0: float = 0.0,
     return W, t, len(dts), dts
 
 
-def stage_fluxes(prob: Problem, W, dt: float, nthreads: int = 1):
-    """F and dF/dt at every interface for time step dt (paper eqs. for F and its time derivative)."""
+def stage_fluxes(prob: Problem, W, dt: float, nthreads: int = 1, t: float = 0.0):
+    """F and dF/dt at every interface of state W at time t for time step dt (paper eqs. for F and its
+    time derivative)."""
     W = _f64(W)
     ps = prob.c_struct()
     nc, nx, ny = prob.nc, prob.nx, (prob.ny if prob.dim == 2 else 1)
@@ -184,7 +216,7 @@ def stage_fluxes(prob: Problem, W, dt: float, nthreads: int = 1):
     Gx = np.zeros_like(Fx)
     Fy = np.zeros((nc, ny + 1, nx)) if prob.dim == 2 else np.zeros(1)
     Gy = np.zeros_like(Fy)
-    rc = lib().oracle_stage_fluxes(C.byref(ps), _ptr(W), float(dt), _ptr(Fx), _ptr(Gx), _ptr(Fy),
+    rc = lib().oracle_stage_fluxes(C.byref(ps), _ptr(W), float(t), float(dt), _ptr(Fx), _ptr(Gx), _ptr(Fy),
                                    _ptr(Gy), int(nthreads))
     if rc:
         raise OracleError(rc)

@@ -254,7 +254,7 @@ typedef struct {
   double gamma, K, mu, Pr, c1, c2;
   int ns;
   double ghi, glo, eps;
-  int recon, zeta1_mode;
+  int recon, zeta1_mode, positivity;
 } params;
 
 /* q5[r][c]: the side's five cells (offsets -2..2), xi: evaluation point. Unflagged: component-wise
@@ -650,6 +650,7 @@ static void make_params(const oracle_problem* p, params* pp) {
   pp->eps = p->weno_eps;
   pp->recon = p->recon;
   pp->zeta1_mode = p->zeta1_mode;
+  pp->positivity = p->positivity;
 }
 
 static int check_problem(const oracle_problem* p) {
@@ -657,26 +658,114 @@ static int check_problem(const oracle_problem* p) {
   if (p->nx < 5 || (p->dim == 2 && p->ny < 5) || (p->dim == 1 && p->ny != 1)) return ORACLE_EINVAL;
   if (!(p->gamma > 1.0) || !(p->x1 > p->x0) || (p->dim == 2 && !(p->y1 > p->y0))) return ORACLE_EINVAL;
   if (p->eqn == 1 && !(p->Pr > 0.0 && p->mu >= 0.0)) return ORACLE_EINVAL;
+  if (p->positivity != 0 && p->positivity != 1) return ORACLE_EINVAL;
   int nb = p->dim == 2 ? 4 : 2;
-  for (int s = 0; s < nb; ++s)
-    if (p->bc[s] < 0 || p->bc[s] > 3) return ORACLE_EINVAL;
+  for (int s = 0; s < nb; ++s) {
+    if (p->bc[s] < 0 || p->bc[s] > 4) return ORACLE_EINVAL;
+    if (p->bc[s] == 4) {
+      const oracle_bc_data* d = &p->bcd[s];
+      if (d->rest < 1 || d->rest > 4) return ORACLE_EINVAL;
+      if (isnan(d->s0) || !isfinite(d->sn) || !isfinite(d->st)) return ORACLE_EINVAL;
+      for (int k = 0; k < (d->rest == 4 ? 2 : 1); ++k) {
+        const double* q = k ? d->b : d->a;
+        double mv = (p->dim == 2) ? q[2] : 0.0;
+        double pr = (p->gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + mv * mv) / q[0]);
+        if (!(q[0] > 0.0) || !(pr > 0.0) || !isfinite(q[3]) || !isfinite(q[1]) || !isfinite(mv))
+          return ORACLE_EINVAL;
+      }
+    }
+  }
   for (int s = 0; s < nb; s += 2)
     if ((p->bc[s] == 0) != (p->bc[s + 1] == 0)) return ORACLE_EINVAL;
   return ORACLE_OK;
 }
 
-/* Index of the interior cell that ghost index i (in 0..n-1 or outside) takes its data from,
- * and which velocity components change sign (bit 0: normal, bit 1: tangential). */
-static int bc_map(int i, int n, int bc_lo, int bc_hi, int* flip) {
-  *flip = 0;
-  if (i >= 0 && i < n) return i;
-  int bc = (i < 0) ? bc_lo : bc_hi;
-  switch (bc) {
-    case 0: return ((i % n) + n) % n;          /* periodic */
-    case 1: return (i < 0) ? 0 : n - 1;        /* zero-gradient outflow */
-    case 2: *flip = 1; return (i < 0) ? -1 - i : 2 * n - 1 - i;  /* slip wall / symmetry */
-    default: *flip = 3; return (i < 0) ? -1 - i : 2 * n - 1 - i; /* no-slip adiabatic wall */
-  }
+/* The state with NG ghost layers on every side that exists, filled as the boundary conditions of
+ * Sec. 3 state: first the ghost columns of the interior rows (x-sides), then whole ghost rows across
+ * the padded width (y-sides), so that a corner cell follows the y-side's rule applied to the x-ghost
+ * column beside it. Layout G[c][jp][ip] with jp = j + NG (2D; a single row in 1D), ip = i + NG.
+ *   periodic: the cell one period away; outflow: the nearest interior cell (zero gradient);
+ *   reflect: the mirror cell with the normal momentum negated; no-slip adiabatic: the mirror cell with
+ *   both momenta negated; prescribed: the side's state a or b at the ghost centre and stage time t,
+ *   or beyond the split the ghost of the kind the side names for the rest. */
+typedef struct {
+  int nc, nx, ny, px, py, jo;
+  double* G;
+} padded;
+
+static double* pg(const padded* g, int c, int j, int i) {
+  return g->G + ((size_t)c * g->py + (size_t)(j + g->jo)) * g->px + (size_t)(i + NG);
+}
+
+/* Conserved state of a prescribed side at a ghost centre, or NULL where the rest kind applies;
+ * *kind receives that kind. */
+static const double* prescribed(const oracle_problem* p, int side, double tau, double nu, double t, int* kind) {
+  const oracle_bc_data* d = &p->bcd[side];
+  *kind = d->rest;
+  if (tau < d->s0 + d->sn * nu + d->st * t) return d->a;
+  if (d->rest == 4) return d->b;
+  return NULL;
+}
+
+static void put_state(const padded* g, int j, int i, const double* q) {
+  /* q is (rho, rho U, rho V, rho E); 1D keeps (rho, rho U, rho E) */
+  if (g->nc == 4) for (int c = 0; c < 4; ++c) *pg(g, c, j, i) = q[c];
+  else { *pg(g, 0, j, i) = q[0]; *pg(g, 1, j, i) = q[1]; *pg(g, 2, j, i) = q[3]; }
+}
+
+static void pad_state(const oracle_problem* p, const double* W, double t, padded* g) {
+  int nc = p->dim + 2, nx = p->nx, ny = p->ny;
+  double dx = (p->x1 - p->x0) / nx, dy = (p->dim == 2) ? (p->y1 - p->y0) / ny : 1.0;
+  g->nc = nc; g->nx = nx; g->ny = ny;
+  g->px = nx + 2 * NG;
+  g->jo = (p->dim == 2) ? NG : 0;
+  g->py = ny + 2 * g->jo;
+  g->G = (double*)malloc(sizeof(double) * nc * g->px * g->py);
+  for (int c = 0; c < nc; ++c)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) *pg(g, c, j, i) = W[((size_t)c * ny + j) * nx + i];
+  /* x-sides, interior rows */
+  for (int j = 0; j < ny; ++j)
+    for (int k = 1; k <= NG; ++k)
+      for (int side = 0; side < 2; ++side) {
+        int i = side ? nx - 1 + k : -k;
+        int kind = p->bc[side];
+        if (kind == 4) {
+          double x = p->x0 + (i + 0.5) * dx;
+          double y = (p->dim == 2) ? p->y0 + (j + 0.5) * dy : 0.0;
+          const double* q = prescribed(p, side, y, x, t, &kind);
+          if (q) { put_state(g, j, i, q); continue; }
+        }
+        int src = kind == 0 ? (side ? i - nx : i + nx) : kind == 1 ? (side ? nx - 1 : 0) : (side ? 2 * nx - 1 - i : -1 - i);
+        for (int c = 0; c < nc; ++c) {
+          double v = *pg(g, c, j, src);
+          if ((kind == 2 || kind == 3) && c == 1) v = -v;           /* normal momentum */
+          if (kind == 3 && nc == 4 && c == 2) v = -v;               /* tangential momentum */
+          *pg(g, c, j, i) = v;
+        }
+      }
+  if (p->dim == 1) return;
+  /* y-sides, whole padded rows (ghost columns included); every source row is an interior one */
+  for (int k = 1; k <= NG; ++k)
+    for (int side = 0; side < 2; ++side) {
+      int j = side ? ny - 1 + k : -k;
+      for (int i = -NG; i < nx + NG; ++i) {
+        int kind = p->bc[2 + side];
+        if (kind == 4) {
+          double x = p->x0 + (i + 0.5) * dx;
+          double y = p->y0 + (j + 0.5) * dy;
+          const double* q = prescribed(p, 2 + side, x, y, t, &kind);
+          if (q) { put_state(g, j, i, q); continue; }
+        }
+        int src = kind == 0 ? (side ? j - ny : j + ny) : kind == 1 ? (side ? ny - 1 : 0) : (side ? 2 * ny - 1 - j : -1 - j);
+        for (int c = 0; c < nc; ++c) {
+          double v = *pg(g, c, src, i);
+          if ((kind == 2 || kind == 3) && c == 2) v = -v;           /* normal momentum */
+          if (kind == 3 && c == 1) v = -v;                          /* tangential momentum */
+          *pg(g, c, j, i) = v;
+        }
+      }
+    }
 }
 
 /* A directional view: normal index n (fast), tangential index t, padded by NG on every side that
@@ -692,8 +781,8 @@ static double* fr_at(const frame* f, int c, int jt, int in) {
   return f->P + ((size_t)c * f->pt + (size_t)(jt + f->tp)) * f->pn + (size_t)(in + NG);
 }
 
-/* Build the padded frame for direction dir (0: x, 1: y) from the unpadded state. */
-static void build_frame(const oracle_problem* p, const double* W, int dir, frame* f) {
+/* Build the padded frame for direction dir (0: x, 1: y) from the state padded at stage time t. */
+static void build_frame(const oracle_problem* p, const double* W, double t, int dir, frame* f) {
   int nc = p->dim + 2, nx = p->nx, ny = p->ny;
   f->nc = nc;
   f->dim = p->dim;
@@ -704,22 +793,17 @@ static void build_frame(const oracle_problem* p, const double* W, int dir, frame
   f->pn = f->nn + 2 * NG;
   f->pt = f->nt + 2 * f->tp;
   f->P = (double*)malloc(sizeof(double) * nc * f->pn * f->pt);
+  padded g;
+  pad_state(p, W, t, &g);
   for (int jt = -f->tp; jt < f->nt + f->tp; ++jt)
     for (int in = -NG; in < f->nn + NG; ++in) {
       int i = (dir == 0) ? in : jt, j = (dir == 0) ? jt : in;
-      int fxf, fyf = 0;
-      int ii = bc_map(i, nx, p->bc[0], p->bc[1], &fxf);
-      int jj = (p->dim == 2) ? bc_map(j, ny, p->bc[2], p->bc[3], &fyf) : 0;
       double v[MAXC];
-      for (int c = 0; c < nc; ++c) v[c] = W[((size_t)c * ny + jj) * nx + ii];
-      /* x-walls flip the x velocity (and for no-slip also y); y-walls the reverse */
-      int negu = ((fxf & 1) != 0) ^ ((fyf & 2) != 0);
-      int negv = ((fxf & 2) != 0) ^ ((fyf & 1) != 0);
-      if (negu) v[1] = -v[1];
-      if (p->dim == 2 && negv) v[2] = -v[2];
-      if (dir == 1) { double t = v[1]; v[1] = v[2]; v[2] = t; }
+      for (int c = 0; c < nc; ++c) v[c] = *pg(&g, c, j, i);
+      if (dir == 1) { double tmp = v[1]; v[1] = v[2]; v[2] = tmp; }
       for (int c = 0; c < nc; ++c) *fr_at(f, c, jt, in) = v[c];
     }
+  free(g.G);
 }
 
 /* Widened flags of every padded cell where the 7-cell stencil fits, along the normal (Fn) and
@@ -774,6 +858,14 @@ static void frame_flags(const frame* f, const params* pp, uint8_t* Fn, uint8_t* 
   free(Tt);
 }
 
+/* Whether a reconstructed state (frame components: rho, normal and tangential momentum, energy; no
+ * tangential slot in 1D) has positive density and pressure. */
+static int admissible(const double* w, int nc, double gamma) {
+  double mt = (nc == 4) ? w[2] : 0.0;
+  double pr = (gamma - 1.0) * (w[nc - 1] - 0.5 * (w[1] * w[1] + mt * mt) / w[0]);
+  return w[0] > 0.0 && pr > 0.0 && isfinite(pr);
+}
+
 /* Time-integrated fluxes F(dt), F(dt/2) at every interface of the frame (normal-direction
  * interfaces k = 0..nn of rows 0..nt-1), averaged over the Gauss points of each segment.
  * Output layout: [nc][nt][nn+1], components in the frame's (rotated) order. */
@@ -805,6 +897,11 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
         for (int r = 0; r < 5; ++r)
           for (int c = 0; c < nc; ++c) q5[r][c] = *fr_at(f, c, row, cell - 2 + r);
         recon_side(pp, q5, s == 0 ? 0.5 : -0.5, s == 0 ? fl : fr, R, L, val, der);
+        if (pp->positivity && !admissible(val, nc, pp->gamma))
+          for (int c = 0; c < nc; ++c) { /* first order: the cell's own average, no slope */
+            val[c] = q5[2][c];
+            der[c] = 0.0;
+          }
         for (int c = 0; c < nc; ++c) {
           LVAT(2 * s, c, row, k) = val[c];
           LVAT(2 * s + 1, c, row, k) = der[c] / f->hn;
@@ -848,14 +945,16 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
             for (int r = 0; r < 5; ++r)
               for (int c = 0; c < nc; ++c) q5[r][c] = LVAT(2 * s, c, j - 2 + r, k);
             recon_side(pp, q5, xi, ftf[s], R[s], L[s], val, der);
+            /* first order along the interface: the centre segment's line values, no tangential slope */
+            int low = pp->positivity && !admissible(val, nc, pp->gamma);
             for (int c = 0; c < nc; ++c) {
-              Ws[s][c] = val[c];
-              Wys[s][c] = der[c] / f->ht;
+              Ws[s][c] = low ? q5[2][c] : val[c];
+              Wys[s][c] = low ? 0.0 : der[c] / f->ht;
             }
             for (int r = 0; r < 5; ++r)
               for (int c = 0; c < nc; ++c) q5[r][c] = LVAT(2 * s + 1, c, j - 2 + r, k);
             recon_side(pp, q5, xi, ftf[s], R[s], L[s], val, der);
-            for (int c = 0; c < nc; ++c) Wxs[s][c] = val[c];
+            for (int c = 0; c < nc; ++c) Wxs[s][c] = low ? q5[2][c] : val[c];
           }
           gp_flux(pp, Ws[0], Wxs[0], Wys[0], Ws[1], Wxs[1], Wys[1], dt, Fdg, Fhg, NULL);
           for (int c = 0; c < nc; ++c) {
@@ -878,10 +977,10 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
 
 /* Time-integrated fluxes of both directions in the grid's own component order:
  * x: [nc][ny][nx+1], y: [nc][ny+1][nx]. */
-static void all_fluxes(const oracle_problem* p, const params* pp, const double* W, double dt,
+static void all_fluxes(const oracle_problem* p, const params* pp, const double* W, double t, double dt,
                        double* Fxd, double* Fxh, double* Fyd, double* Fyh, int nthreads) {
   frame f;
-  build_frame(p, W, 0, &f);
+  build_frame(p, W, t, 0, &f);
   frame_fluxes(&f, pp, dt, Fxd, Fxh, nthreads);
   free(f.P);
   if (p->dim == 2) {
@@ -889,7 +988,7 @@ static void all_fluxes(const oracle_problem* p, const params* pp, const double* 
     size_t n = (size_t)nc * nx * (ny + 1);
     double* td = (double*)malloc(sizeof(double) * n);
     double* th = (double*)malloc(sizeof(double) * n);
-    build_frame(p, W, 1, &f);
+    build_frame(p, W, t, 1, &f);
     frame_fluxes(&f, pp, dt, td, th, nthreads); /* [nc'][nx][ny+1] */
     free(f.P);
     for (int c = 0; c < nc; ++c) {
@@ -905,16 +1004,37 @@ static void all_fluxes(const oracle_problem* p, const params* pp, const double* 
   }
 }
 
-static int nonphysical(const oracle_problem* p, const double* W) {
+static int admissible_cell(const oracle_problem* p, const double* W, size_t s) {
   int nc = p->dim + 2;
   size_t ncell = (size_t)p->nx * p->ny;
-  for (size_t s = 0; s < ncell; ++s) {
-    double rho = W[s], mx = W[ncell + s], my = (p->dim == 2) ? W[2 * ncell + s] : 0.0;
-    double E = W[(size_t)(nc - 1) * ncell + s];
-    double pr = (p->gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / rho);
-    if (!(rho > 0.0) || !(pr > 0.0) || !isfinite(E)) return 1;
-  }
+  double rho = W[s], mx = W[ncell + s], my = (p->dim == 2) ? W[2 * ncell + s] : 0.0;
+  double E = W[(size_t)(nc - 1) * ncell + s];
+  double pr = (p->gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / rho);
+  return rho > 0.0 && pr > 0.0 && isfinite(E);
+}
+
+static int nonphysical(const oracle_problem* p, const double* W) {
+  size_t ncell = (size_t)p->nx * p->ny;
+  for (size_t s = 0; s < ncell; ++s)
+    if (!admissible_cell(p, W, s)) return 1;
   return 0;
+}
+
+/* W_new = W - dt (dFx/dx + dFy/dy) with face fluxes Fx [nc][ny][nx+1], Fy [nc][ny+1][nx]. */
+static void update_cells(const oracle_problem* p, const double* W, const double* Fx, const double* Fy, double dt,
+                         double* Wn) {
+  int nc = p->dim + 2, nx = p->nx, ny = p->ny;
+  double dx = (p->x1 - p->x0) / nx, dy = p->dim == 2 ? (p->y1 - p->y0) / ny : 1.0;
+  size_t ncell = (size_t)nx * ny;
+  for (int c = 0; c < nc; ++c)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double a = (Fx[((size_t)c * ny + j) * (nx + 1) + i + 1] - Fx[((size_t)c * ny + j) * (nx + 1) + i]) / dx;
+        double b = 0.0;
+        if (p->dim == 2) b = (Fy[((size_t)c * (ny + 1) + j + 1) * nx + i] - Fy[((size_t)c * (ny + 1) + j) * nx + i]) / dy;
+        size_t o = (size_t)c * ncell + (size_t)j * nx + i;
+        Wn[o] = W[o] - dt * (a + b);
+      }
 }
 
 double oracle_cfl_dt(const oracle_problem* p, const double* W) {
@@ -945,7 +1065,7 @@ double oracle_cfl_dt(const oracle_problem* p, const double* W) {
   return p->cfl * qmin;
 }
 
-int oracle_stage_fluxes(const oracle_problem* p, const double* W, double dt, double* Fx, double* Gx,
+int oracle_stage_fluxes(const oracle_problem* p, const double* W, double t, double dt, double* Fx, double* Gx,
                         double* Fy, double* Gy, int nthreads) {
   oracle_init();
   int rc = check_problem(p);
@@ -958,7 +1078,7 @@ int oracle_stage_fluxes(const oracle_problem* p, const double* W, double dt, dou
   double* Fxh = (double*)malloc(sizeof(double) * nxf);
   double* Fyd = p->dim == 2 ? (double*)malloc(sizeof(double) * nyf) : NULL;
   double* Fyh = p->dim == 2 ? (double*)malloc(sizeof(double) * nyf) : NULL;
-  all_fluxes(p, &pp, W, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
+  all_fluxes(p, &pp, W, t, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
   /* F = (4 F(dt/2) - F(dt))/dt, dF/dt = 4 (F(dt) - 2 F(dt/2))/dt^2 */
   for (size_t s = 0; s < nxf; ++s) {
     Fx[s] = (4.0 * Fxh[s] - Fxd[s]) / dt;
@@ -1010,7 +1130,7 @@ int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, dou
   double* Ws = (double*)malloc(sizeof(double) * nc * ncell);
 
   /* stage 1 at t_n */
-  all_fluxes(p, &pp, W, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
+  all_fluxes(p, &pp, W, *t, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
   for (size_t s = 0; s < nxf; ++s) {
     Fx[s] = (4.0 * Fxh[s] - Fxd[s]) / dt;
     Gxn[s] = 4.0 * (Fxd[s] - 2.0 * Fxh[s]) / (dt * dt);
@@ -1020,6 +1140,11 @@ int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, dou
       Fy[s] = (4.0 * Fyh[s] - Fyd[s]) / dt;
       Gyn[s] = 4.0 * (Fyd[s] - 2.0 * Fyh[s]) / (dt * dt);
     }
+  /* F^n kept for the time-order fallback */
+  double* Fxn = (double*)malloc(sizeof(double) * nxf);
+  double* Fyn = (double*)malloc(sizeof(double) * nyf);
+  memcpy(Fxn, Fx, sizeof(double) * nxf);
+  if (dim == 2) memcpy(Fyn, Fy, sizeof(double) * nyf);
   /* W* = W^n - [F(dt/2)_{i+1/2} - F(dt/2)_{i-1/2}]/dx - [G(dt/2)_{j+1/2} - G(dt/2)_{j-1/2}]/dy */
   for (int c = 0; c < nc; ++c)
     for (int j = 0; j < ny; ++j)
@@ -1033,7 +1158,7 @@ int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, dou
   if (nonphysical(p, Ws)) rc = ORACLE_ENONPHYS;
   if (!rc) {
     /* stage 2 at t* = t_n + dt/2: only the time derivative of the flux is needed */
-    all_fluxes(p, &pp, Ws, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
+    all_fluxes(p, &pp, Ws, *t + 0.5 * dt, dt, Fxd, Fxh, Fyd, Fyh, nthreads);
     for (size_t s = 0; s < nxf; ++s) {
       double Gs = 4.0 * (Fxd[s] - 2.0 * Fxh[s]) / (dt * dt);
       Fx[s] = Fx[s] + dt / 6.0 * (Gxn[s] + 2.0 * Gs);
@@ -1043,15 +1168,31 @@ int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, dou
         double Gs = 4.0 * (Fyd[s] - 2.0 * Fyh[s]) / (dt * dt);
         Fy[s] = Fy[s] + dt / 6.0 * (Gyn[s] + 2.0 * Gs);
       }
-    for (int c = 0; c < nc; ++c)
+    update_cells(p, W, Fx, Fy, dt, Ws);
+    if (pp.positivity && nonphysical(p, Ws)) {
+      /* time-order fallback: every face of a cell that this update leaves non-physical takes the
+       * one-stage flux of the first stage's linear-in-time expansion, F^n + dt/2 dF^n/dt (the flux
+       * integrated over the whole step, divided by dt), for both of its cells; then update again */
+      uint8_t* bad = (uint8_t*)calloc(ncell, 1);
+      for (size_t s = 0; s < ncell; ++s) bad[s] = !admissible_cell(p, Ws, s);
       for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-          double a = (Fx[((size_t)c * ny + j) * (nx + 1) + i + 1] - Fx[((size_t)c * ny + j) * (nx + 1) + i]) / dx;
-          double b = 0.0;
-          if (dim == 2) b = (Fy[((size_t)c * (ny + 1) + j + 1) * nx + i] - Fy[((size_t)c * (ny + 1) + j) * nx + i]) / dy;
-          size_t o = (size_t)c * ncell + (size_t)j * nx + i;
-          Ws[o] = W[o] - dt * (a + b);
+          if (!bad[(size_t)j * nx + i]) continue;
+          for (int c = 0; c < nc; ++c) {
+            for (int f = 0; f < 2; ++f) {
+              size_t s = ((size_t)c * ny + j) * (nx + 1) + i + f;
+              Fx[s] = Fxn[s] + 0.5 * dt * Gxn[s];
+            }
+            if (dim == 2)
+              for (int f = 0; f < 2; ++f) {
+                size_t s = ((size_t)c * (ny + 1) + j + f) * nx + i;
+                Fy[s] = Fyn[s] + 0.5 * dt * Gyn[s];
+              }
+          }
         }
+      free(bad);
+      update_cells(p, W, Fx, Fy, dt, Ws);
+    }
     if (nonphysical(p, Ws)) rc = ORACLE_ENONPHYS;
     if (!rc) {
       memcpy(W, Ws, sizeof(double) * nc * ncell);
@@ -1060,11 +1201,11 @@ int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, dou
     }
   }
   free(Fxd); free(Fxh); free(Fyd); free(Fyh);
-  free(Fx); free(Fy); free(Gxn); free(Gyn); free(Ws);
+  free(Fx); free(Fy); free(Gxn); free(Gyn); free(Ws); free(Fxn); free(Fyn);
   return rc;
 }
 
-int oracle_flags(const oracle_problem* p, const double* W, uint8_t* fx, uint8_t* fy) {
+int oracle_flags(const oracle_problem* p, const double* W, double t, uint8_t* fx, uint8_t* fy) {
   oracle_init();
   int rc = check_problem(p);
   if (rc) return rc;
@@ -1072,7 +1213,7 @@ int oracle_flags(const oracle_problem* p, const double* W, uint8_t* fx, uint8_t*
   make_params(p, &pp);
   for (int dir = 0; dir < p->dim; ++dir) {
     frame f;
-    build_frame(p, W, dir, &f);
+    build_frame(p, W, t, dir, &f);
     uint8_t* Fn = (uint8_t*)malloc((size_t)f.pn * f.pt);
     frame_flags(&f, &pp, Fn, NULL);
     uint8_t* out = (dir == 0) ? fx : fy;

@@ -19,6 +19,18 @@
 extern "C" {
 #endif
 
+/* Data of a prescribed-state side (boundary kind 4), as the double Mach reflection of Sec. 3.5
+ * needs: a ghost cell whose centre has tangential coordinate tau (y on an x-side, 0 in 1D; x on a
+ * y-side) and normal coordinate nu takes the conserved state a when
+ *   tau < s0 + sn * nu + st * t      (t: the stage time: t_n in stage 1, t_n + dt/2 in stage 2)
+ * and otherwise the state b (rest == 4) or the ghost of boundary kind rest (1, 2 or 3). States are
+ * (rho, rho U, rho V, rho E); 1D problems use a[0], a[1], a[3]. */
+typedef struct {
+  double a[4], b[4];
+  double s0, sn, st;
+  int32_t rest, pad;
+} oracle_bc_data;
+
 /* Problem statement (Sec. 2 and Sec. 3 of the paper). Field meanings follow the
  * HIP library's hgks_problem, but this is a separate declaration. */
 typedef struct {
@@ -28,26 +40,34 @@ typedef struct {
   double gamma, mu, Pr;         /* ratio of specific heats, dynamic viscosity, Prandtl number */
   double cfl, c1, c2;           /* CFL number and collision-time constants (Sec. 3) */
   double fixed_dt;              /* > 0: use this time step instead of the CFL one */
-  int32_t bc[4];                /* x-low, x-high, y-low, y-high: 0 periodic, 1 outflow, 2 reflect, 3 no-slip adiabatic */
+  int32_t bc[4];                /* x-low, x-high, y-low, y-high: 0 periodic, 1 outflow, 2 reflect, 3 no-slip
+                                   adiabatic, 4 prescribed state (bcd[side]) */
   int32_t recon;                /* 0 hybrid, 1 always WENO5-AO, 2 always linear */
   double gamma_hi, gamma_lo, weno_eps;  /* WENO-AO linear-weight parameters and epsilon */
   int32_t zeta1_mode;           /* 0: Step-1 threshold 5*h on the normalised quadratic, 1: 5*h^3 */
   int32_t tangential_flag_mode; /* only 0 (perpendicular cell flag) is implemented */
+  int32_t positivity;           /* 0: the scheme as the paper states it. 1: first-order fallbacks: a
+                                   reconstructed interface or Gauss-point state with rho <= 0 or p <= 0 is
+                                   replaced by the state of the cell (or centre segment) it belongs to, with
+                                   zero slopes; and the faces of a cell that the S2O4 update leaves
+                                   non-physical take the one-stage flux F^n + dt/2 dF^n/dt */
+  oracle_bc_data bcd[4];        /* per side, read where bc[side] == 4 */
 } oracle_problem;
 
 enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_ENONPHYS = -4, ORACLE_EDT = -5 };
 
 /* --- whole-scheme entry points ------------------------------------------ */
-/* Widened troubled-cell flags of every interior cell: fx (x direction), fy (y direction, 2D only). */
-int oracle_flags(const oracle_problem* p, const double* W, uint8_t* fx, uint8_t* fy);
+/* Widened troubled-cell flags of every interior cell of state W at time t (the time enters through
+ * prescribed-state sides): fx (x direction), fy (y direction, 2D only). */
+int oracle_flags(const oracle_problem* p, const double* W, double t, uint8_t* fx, uint8_t* fy);
 /* CFL time step of state W (before clipping to t_end). */
 double oracle_cfl_dt(const oracle_problem* p, const double* W);
 /* One S2O4 step in place. The step is the CFL one (or fixed_dt), clipped so that t never passes
  * t_end; *t is advanced. Returns ORACLE_ENONPHYS if a non-physical state appears. */
 int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken, int nthreads);
-/* Stage fluxes of state W for time step dt: Fn, dtFn at every interface.
+/* Stage fluxes of state W at time t for time step dt: Fn, dtFn at every interface.
  * Fx, Gx: [nc][ny][nx+1]; Fy, Gy: [nc][ny+1][nx] (2D only). */
-int oracle_stage_fluxes(const oracle_problem* p, const double* W, double dt,
+int oracle_stage_fluxes(const oracle_problem* p, const double* W, double t, double dt,
                         double* Fx, double* Gx, double* Fy, double* Gy, int nthreads);
 
 /* --- unit-level entry points (for tests) --------------------------------- */

@@ -68,11 +68,25 @@ static hgks_status validate(const hgks_problem& p) {
   if (p.eqn != HGKS_EULER && p.eqn != HGKS_NS) return HGKS_EINVAL;
   if (p.eqn == HGKS_NS && !(p.Pr > 0.0 && p.mu >= 0.0)) return HGKS_EINVAL;
   if (p.c1 < 0.0 || p.c2 < 0.0 || p.recon < 0 || p.recon > 2 || p.tangential_flag_mode != 0) return HGKS_EINVAL;
+  if (p.positivity != 0 && p.positivity != 1) return HGKS_EINVAL;
   if (!(p.gamma_hi > 0.0 && p.gamma_hi < 1.0) || !(p.gamma_lo > 0.0 && p.gamma_lo < 1.0) || !(p.weno_eps > 0.0))
     return HGKS_EINVAL;
   const int nb = p.dim == 2 ? 4 : 2;
-  for (int s = 0; s < nb; ++s)
-    if (p.bc[s] < 0 || p.bc[s] > 3) return HGKS_EINVAL;
+  for (int s = 0; s < nb; ++s) {
+    if (p.bc[s] < 0 || p.bc[s] > HGKS_BC_PRESCRIBED) return HGKS_EINVAL;
+    if (p.bc[s] != HGKS_BC_PRESCRIBED) continue;
+    const hgks_bc_data& d = p.bcd[s];
+    if (d.rest < HGKS_BC_OUTFLOW || d.rest > HGKS_BC_PRESCRIBED) return HGKS_EINVAL;
+    if (std::isnan(d.s0) || !std::isfinite(d.sn) || !std::isfinite(d.st)) return HGKS_EINVAL;
+    for (int k = 0; k < (d.rest == HGKS_BC_PRESCRIBED ? 2 : 1); ++k) {
+      const double* w = k ? d.b : d.a;
+      const double mv = p.dim == 2 ? w[2] : 0.0;
+      if (!std::isfinite(w[0]) || !std::isfinite(w[1]) || !std::isfinite(mv) || !std::isfinite(w[3]))
+        return HGKS_EINVAL;
+      if (!(w[0] > 0.0) || !((p.gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + mv * mv) / w[0]) > 0.0))
+        return HGKS_EINVAL;
+    }
+  }
   for (int s = 0; s < nb; s += 2)
     if ((p.bc[s] == HGKS_BC_PERIODIC) != (p.bc[s + 1] == HGKS_BC_PERIODIC)) return HGKS_EINVAL;
   if ((size_t)p.nx * p.ny > (size_t)1 << 30) return HGKS_EINVAL;
@@ -154,6 +168,8 @@ static LaunchCtx ctx(hgks* h) {
   L.persistent_grid = 0;
   L.prfix = 0;
   for (auto& q : h->hp) L.prfix |= (q.eqn == HGKS_NS && q.Pr != 1.0);
+  L.positivity = 0;
+  for (auto& q : h->hp) L.positivity |= q.positivity;
   L.cell_blocks = h->tab_cell[h->nprob];
   L.ext_blocks = h->tab_ext[h->nprob];
   L.flux_blocks = h->tab_flux[shape][h->nprob];
@@ -179,8 +195,21 @@ static hgks_status materialise(hgks* h) {
     ProbDev& d = h->pd[p];
     std::memset(&d, 0, sizeof d);
     d.dim = q.dim; d.nx = q.nx; d.ny = q.ny; d.ns = (q.eqn == HGKS_NS);
-    for (int s = 0; s < 4; ++s) d.bc[s] = q.bc[s];
-    d.recon = q.recon; d.zeta1_mode = q.zeta1_mode;
+    for (int s = 0; s < 4; ++s) {
+      d.bc[s] = q.bc[s];
+      if (q.bc[s] != HGKS_BC_PRESCRIBED || (q.dim == 1 && s >= 2)) continue;
+      d.prescribed = 1;
+      BcDev& B = d.bcd[s];
+      for (int c = 0; c < 4; ++c) {
+        B.a[c] = q.bcd[s].a[c];
+        B.b[c] = q.bcd[s].b[c];
+      }
+      if (q.dim == 1) B.a[2] = B.b[2] = 0.0;
+      B.s0 = q.bcd[s].s0; B.sn = q.bcd[s].sn; B.st = q.bcd[s].st;
+      B.rest = q.bcd[s].rest;
+    }
+    d.recon = q.recon; d.zeta1_mode = q.zeta1_mode; d.positivity = q.positivity;
+    d.x0 = q.x0; d.y0 = q.dim == 2 ? q.y0 : 0.0;
     d.dx = (q.x1 - q.x0) / q.nx;
     d.dy = q.dim == 2 ? (q.y1 - q.y0) / q.ny : 1.0;
     d.h = q.dim == 2 ? std::min(d.dx, d.dy) : d.dx;
@@ -302,6 +331,7 @@ static void enqueue_step(hgks* h, int use_tend, bool capturing = false) {
   timed(h, 2, capturing, [&] { launch_flags(L, 1, 0, 0); });
   timed(h, 0, capturing, [&] { launch_flux(L, 2); });
   timed(h, 1, capturing, [&] { launch_update(L, 2); });
+  if (L.positivity) timed(h, 1, capturing, [&] { launch_repair(L); });
   timed(h, 3, capturing, [&] { launch_commit(L, use_tend); });
   if (h->recs.size() > 4096) collect_profile(h);
 }

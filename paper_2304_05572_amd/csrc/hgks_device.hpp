@@ -13,10 +13,22 @@ namespace hk {
 // ---------------------------------------------------------------------------------------------
 // Per-problem description and time state (device copies)
 // ---------------------------------------------------------------------------------------------
+// A prescribed-state side: ghost centres with tangential coordinate tau < s0 + sn * nu + st * t (nu the
+// normal coordinate, t the stage time) take state a, the others state b (rest == 4) or the ghost of
+// boundary kind rest.
+struct BcDev {
+  double a[4], b[4];         // (rho, rho U, rho V, rho E); rho V = 0 in 1D
+  double s0, sn, st;
+  int rest, pad;
+};
+
 struct ProbDev {
   int dim, nx, ny, ns;
   int bc[4];
   int recon, zeta1_mode;
+  int positivity;            // 1: non-physical reconstructed states drop to first order
+  int prescribed;            // 1 if any side is a prescribed-state side (bc == 4)
+  double x0, y0;             // lower-left corner (ghost centres of prescribed sides)
   double dx, dy, h;          // cell sizes; h = min(dx, dy) for the CFL step
   double gamma, K, mu, Pr, c1, c2;  // K: internal dof of the 2D model (1D problems embed into it)
   double Kp2, iKp2, kpr;     // K + 2, 1 / (K + 2), 1 / Pr - 1 (uniform values kept out of the lanes)
@@ -34,6 +46,7 @@ struct ProbDev {
   void* Fy;                  // y-interfaces [4][ny+1][nx]
   void* Gy;
   int* flag_count;           // [2] troubled cells counted at the last flag evaluation
+  BcDev bcd[4];              // read where bc[side] == 4
 };
 
 struct TimeDev {
@@ -53,12 +66,15 @@ __host__ __device__ inline void set_time_step(TimeDev& s, double dt) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Boundary conditions: index of the interior cell a (ghost) index reads, and velocity sign flips
+// Boundary conditions. Ghost cells are synthesised where a kernel loads them: x-sides on the
+// interior rows, y-sides across the full padded width (a corner follows the y-side's rule applied
+// to the x-ghost beside it).
 // ---------------------------------------------------------------------------------------------
-__host__ __device__ inline int bc_index(int i, int n, int lo, int hi, int& flip) {
+// Index of the interior cell that index i reads on a side of kind bc (0..3), and the velocity sign
+// flips (bit 0: normal momentum, bit 1: tangential momentum).
+__host__ __device__ inline int bc_index(int i, int n, int bc, int& flip) {
   flip = 0;
   if (i >= 0 && i < n) return i;
-  const int bc = (i < 0) ? lo : hi;
   if (bc == 0) {  // periodic
     int r = i % n;
     return r < 0 ? r + n : r;
@@ -69,11 +85,37 @@ __host__ __device__ inline int bc_index(int i, int n, int lo, int hi, int& flip)
   return m < 0 ? 0 : (m >= n ? n - 1 : m);
 }
 
-// Cell (i, j) of state W with ghost synthesis; returns (rho, rho U, rho V, rho E) (rho V = 0 in 1D).
-__device__ inline void load_cell(const ProbDev& P, const double* __restrict__ W, int i, int j, double q[4]) {
-  int fx, fy = 0;
-  const int ii = bc_index(i, P.nx, P.bc[0], P.bc[1], fx);
-  const int jj = (P.dim == 2) ? bc_index(j, P.ny, P.bc[2], P.bc[3], fy) : 0;
+// State of a prescribed side at a ghost centre (tangential coordinate tau, normal coordinate nu) at
+// stage time tb, or nullptr where the side's rest kind applies (returned in kind).
+__device__ inline const double* bc_state(const BcDev& B, double tau, double nu, double tb, int& kind) {
+#pragma clang fp contract(off)
+  kind = B.rest;
+  if (tau < B.s0 + B.sn * nu + B.st * tb) return B.a;
+  return B.rest == 4 ? B.b : nullptr;
+}
+
+__device__ inline double cell_centre(double x0, int i, double h) {
+#pragma clang fp contract(off)
+  return x0 + (i + 0.5) * h;
+}
+
+// Whether cell (i, j) is a ghost of a prescribed-state side (its value then comes from load_cell only).
+__device__ inline bool prescribed_ghost(const ProbDev& P, int i, int j) {
+  if (P.dim == 2 && (j < 0 || j >= P.ny) && P.bc[j < 0 ? 2 : 3] == 4) return true;
+  return (i < 0 || i >= P.nx) && P.bc[i < 0 ? 0 : 1] == 4;
+}
+
+// Cell (i, j) of state W with the ghost synthesis of the periodic, zero-gradient and wall sides;
+// a prescribed-state side is read as zero gradient here (the flux loader overwrites those ghosts with
+// load_cell in a separate pass, which keeps this, its hot loop, free of that logic).
+__device__ inline void load_cell_plain(const ProbDev& P, const double* __restrict__ W, int i, int j, double q[4]) {
+  int fx = 0, fy = 0, jj = 0;
+  if (P.dim == 2) {
+    const int ky = (j < 0) ? P.bc[2] : P.bc[3];
+    jj = bc_index(j, P.ny, ky == 4 ? 1 : ky, fy);
+  }
+  const int kx = (i < 0) ? P.bc[0] : P.bc[1];
+  const int ii = bc_index(i, P.nx, kx == 4 ? 1 : kx, fx);
   const size_t plane = (size_t)P.nx * P.ny;
   const size_t o = (size_t)jj * P.nx + ii;
   q[0] = W[o];
@@ -85,10 +127,53 @@ __device__ inline void load_cell(const ProbDev& P, const double* __restrict__ W,
     q[2] = 0.0;
     q[3] = W[2 * plane + o];
   }
+  const int negu = (fx & 1) ^ ((fy >> 1) & 1);
+  const int negv = ((fx >> 1) & 1) ^ (fy & 1);
+  if (negu) q[1] = -q[1];
+  if (negv) q[2] = -q[2];
+}
+
+// Cell (i, j) of state W with ghost synthesis at stage time tb, every side kind included; returns
+// (rho, rho U, rho V, rho E) (rho V = 0 in 1D).
+__device__ inline void load_cell(const ProbDev& P, const double* __restrict__ W, int i, int j, double tb,
+                                 double q[4]) {
+  int fx = 0, fy = 0, jj = 0;
+  const double* sy = nullptr;  // prescribed state of a y-side ghost row (whole padded width)
+  const double* sx = nullptr;  // prescribed state of an x-side ghost (on the row jj maps to)
+  const bool pres = P.prescribed;  // uniform: problems without prescribed sides skip all of it
+  if (P.dim == 2) {
+    int ky = (j < 0) ? P.bc[2] : P.bc[3];
+    if (pres && (j < 0 || j >= P.ny) && ky == 4)
+      sy = bc_state(P.bcd[j < 0 ? 2 : 3], cell_centre(P.x0, i, P.dx), cell_centre(P.y0, j, P.dy), tb, ky);
+    jj = bc_index(j, P.ny, ky == 4 ? 1 : ky, fy);
+  }
+  int kx = (i < 0) ? P.bc[0] : P.bc[1];
+  if (pres && (i < 0 || i >= P.nx) && kx == 4)
+    sx = bc_state(P.bcd[i < 0 ? 0 : 1], P.dim == 2 ? cell_centre(P.y0, jj, P.dy) : 0.0, cell_centre(P.x0, i, P.dx),
+                  tb, kx);
+  const int ii = bc_index(i, P.nx, kx == 4 ? 1 : kx, fx);
+  const size_t plane = (size_t)P.nx * P.ny;
+  const size_t o = (size_t)jj * P.nx + ii;
+  q[0] = W[o];
+  q[1] = W[plane + o];
+  if (P.dim == 2) {
+    q[2] = W[2 * plane + o];
+    q[3] = W[3 * plane + o];
+  } else {
+    q[2] = 0.0;
+    q[3] = W[2 * plane + o];
+  }
+  if (sx) {  // an x-ghost's own state; the y-side's wall rule still applies to it
+    fx = 0;
+    q[0] = sx[0]; q[1] = sx[1]; q[2] = sx[2]; q[3] = sx[3];
+  }
   const int negu = (fx & 1) ^ ((fy >> 1) & 1);  // x-walls flip U (and V if no-slip), y-walls the reverse
   const int negv = ((fx >> 1) & 1) ^ (fy & 1);
   if (negu) q[1] = -q[1];
   if (negv) q[2] = -q[2];
+  if (sy) {  // a y-ghost row's own state, ahead of everything else
+    q[0] = sy[0]; q[1] = sy[1]; q[2] = sy[2]; q[3] = sy[3];
+  }
 }
 
 // ---------------------------------------------------------------------------------------------

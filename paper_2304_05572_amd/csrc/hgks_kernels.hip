@@ -2,7 +2,8 @@
 //
 // One step of one or many problems (each with its own time step) is
 //   k_dt_finalize -> [k_flags -> k_flux(stage 1) -> k_update(stage 1)]
-//                 -> [k_flags -> k_flux(stage 2) -> k_update(stage 2, + CFL partials)] -> k_commit
+//                 -> [k_flags -> k_flux(stage 2) -> k_update(stage 2, + CFL partials)] (-> k_repair)
+//                 -> k_commit
 // Work is split into tiles; a prefix-sum table maps a flat block index to (problem, tile), so a batch
 // of uneven problems runs in the same launches as a single problem.
 #include <hip/hip_runtime.h>
@@ -154,12 +155,13 @@ __device__ inline int troubled_cell(const double q[5][4], double thr) {
   return t;
 }
 
-__device__ inline int widened_flag(const ProbDev& P, const double* W, int i, int j, int dir, double thr) {
+__device__ inline int widened_flag(const ProbDev& P, const double* W, int i, int j, int dir, double thr,
+                                   double tb) {
   double q[7][4];
 #pragma unroll
   for (int r = 0; r < 7; ++r) {
-    if (dir == 0) load_cell(P, W, i - 3 + r, j, q[r]);
-    else load_cell(P, W, i, j - 3 + r, q[r]);
+    if (dir == 0) load_cell(P, W, i - 3 + r, j, tb, q[r]);
+    else load_cell(P, W, i, j - 3 + r, tb, q[r]);
   }
   int f = 0;
 #pragma unroll
@@ -186,14 +188,15 @@ __global__ void __launch_bounds__(256) k_flags(const ProbDev* __restrict__ probs
   if (e < ex * ey) {
     const int i = e % ex - 2, j = (P.dim == 2) ? e / ex - 2 : 0;
     const double* W = use_stage_state ? P.Ws : P.W;
+    const double tb = use_stage_state ? ts[p].t + ts[p].dth : ts[p].t;  // the stage's time
     if (P.recon == 1) {
       fl = (P.dim == 2) ? 3 : 1;
     } else if (P.recon == 0) {
       const double tx = (P.zeta1_mode == 0) ? 5.0 * P.dx : 5.0 * P.dx * P.dx * P.dx;
-      fl = widened_flag(P, W, i, j, 0, tx);
+      fl = widened_flag(P, W, i, j, 0, tx, tb);
       if (P.dim == 2) {
         const double ty = (P.zeta1_mode == 0) ? 5.0 * P.dy : 5.0 * P.dy * P.dy * P.dy;
-        fl |= widened_flag(P, W, i, j, 1, ty) << 1;
+        fl |= widened_flag(P, W, i, j, 1, ty, tb) << 1;
       }
     }
     P.flags[e] = (uint8_t)fl;
@@ -243,13 +246,14 @@ __global__ void __launch_bounds__(kFThreads) k_flags2d(const ProbDev* __restrict
     for (int q = 0; q < RPT; ++q) fl[q] = 3;
   } else if (P.recon == 0) {
     const double* W = use_stage_state ? P.Ws : P.W;
+    const double tb = use_stage_state ? ts[p].t + ts[p].dth : ts[p].t;  // the stage's time
     // all of a thread's loads are issued before the first LDS store (unrolled, fixed trip count)
     constexpr int NL = (LX * LY + kFThreads - 1) / kFThreads;
     double q4[NL][4];
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
       const int e = tid + u * kFThreads;
-      if (e < LX * LY) load_cell(P, W, i0 - 3 + e % LX, j0 - 3 + e / LX, q4[u]);
+      if (e < LX * LY) load_cell(P, W, i0 - 3 + e % LX, j0 - 3 + e / LX, tb, q4[u]);
     }
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
@@ -313,6 +317,14 @@ __global__ void k_clear_counts(const ProbDev* __restrict__ probs, int nprob) {
   }
 }
 
+// Whether a reconstructed state (rho, normal momentum, tangential momentum, energy) has positive
+// density and pressure.
+template <typename T>
+__device__ inline bool admissible(const T* w, T gam) {
+  const T pr = (gam - T(1)) * (w[3] - T(0.5) * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+  return w[0] > T(0) && pr > T(0) && isfinite(pr);
+}
+
 // Stride (in values) of one interface entry of the normal-reconstruction rows in LDS.
 constexpr int kNRS = 17;
 
@@ -325,7 +337,7 @@ constexpr int flux_threads(int tn, int tt, int dim) { return (dim == 2 ? 2 : 1) 
 // tangential characteristic variables about the side's own centre-segment state when flagged.
 template <typename T, int TN, int R>
 __device__ inline void tangential_side(const T (*sNR)[TN][kNRS], int tt, int k, int s, int ft, int gp, T gam, T ghi,
-                                       T glo, T eps, T iht, T Ws[4], T Wxs[4], T Wys[4]) {
+                                       T glo, T eps, T iht, int pos, T Ws[4], T Wxs[4], T Wys[4]) {
   const int ov = 8 * s, od = 8 * s + 4;
   if (ft) {
     CharMat<T> m;
@@ -355,6 +367,14 @@ __device__ inline void tangential_side(const T (*sNR)[TN][kNRS], int tt, int k, 
       Ws[v] = vv;
       Wys[v] = dd * iht;
       Wxs[v] = vx;
+    }
+  }
+  if (pos && !admissible(Ws, gam)) {  // first order along the interface: the centre segment's line values
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ws[v] = sNR[tt + 2][k][ov + v];
+      Wys[v] = T(0);
+      Wxs[v] = sNR[tt + 2][k][od + v];
     }
   }
 }
@@ -399,6 +419,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
 
   // ---- phase 1: load cells (with ghost synthesis) and flags
   const double* __restrict__ Wsrc = (stage == 1) ? P.W : P.Ws;
+  const double tb = (stage == 1) ? tsp.t : tsp.t + tsp.dth;  // the stage's time (prescribed sides)
   // all of a thread's cell loads are issued before the first LDS store (unrolled, fixed trip count)
   constexpr int NL = (R * C + NTH - 1) / NTH;
   double q[NL][4];
@@ -412,8 +433,8 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
       const int n = n0 - 3 + c, t = (DIM == 2) ? t0 - RO + r : 0;
       const bool ok = n >= -4 && n <= nn + 3 && (DIM == 1 || (t >= -4 && t <= nt + 3));
       if (ok) {
-        if (dir == 0) load_cell(P, Wsrc, n, t, q[u]);
-        else load_cell(P, Wsrc, t, n, q[u]);
+        if (dir == 0) load_cell_plain(P, Wsrc, n, t, q[u]);
+        else load_cell_plain(P, Wsrc, t, n, q[u]);
       } else {
         q[u][0] = 1.0; q[u][1] = 0.0; q[u][2] = 0.0; q[u][3] = 2.5;
       }
@@ -429,6 +450,21 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
       if (dir) { const double sw = q[u][1]; q[u][1] = q[u][2]; q[u][2] = sw; }
 #pragma unroll
       for (int k = 0; k < 4; ++k) sW[k][r][c] = T(q[u][k]);
+    }
+  }
+  if (P.prescribed) {  // ghosts of prescribed-state sides, by the thread that stored the placeholder
+    for (int e = tid; e < R * C; e += NTH) {
+      int r, c;
+      if (dir == 0) { r = e / C; c = e % C; }
+      else { c = e / R; r = e % R; }
+      const int n = n0 - 3 + c, t = (DIM == 2) ? t0 - RO + r : 0;
+      const int gi = dir ? t : n, gj = dir ? n : t;
+      if (n < -4 || n > nn + 3 || (DIM == 2 && (t < -4 || t > nt + 3)) || !prescribed_ghost(P, gi, gj)) continue;
+      double g[4];
+      load_cell(P, Wsrc, gi, gj, tb, g);
+      if (dir) { const double sw = g[1]; g[1] = g[2]; g[2] = sw; }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sW[k][r][c] = T(g[k]);
     }
   }
   const int ex = P.nx + 4;
@@ -485,6 +521,16 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
         for (int v = 0; v < 4; ++v) { out[8 + v] = val[v]; out[12 + v] = der[v] * ihn; }
       }
     }
+    if (P.positivity) {  // first order where a side's value is not a physical state
+      if (!admissible(out, gam)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { out[v] = q6[2][v]; out[4 + v] = T(0); }
+      }
+      if (!admissible(out + 8, gam)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { out[8 + v] = q6[3][v]; out[12 + v] = T(0); }
+      }
+    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) sNR[r][k][v] = out[v];
   }
@@ -522,11 +568,13 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
     FluxAcc<T> acc;
     T Ws[4], Wxs[4], Wys[4];
     // tangential reconstruction of one side at this Gauss point, then its share of the flux
-    tangential_side<T, TN, R>(sNR, tt, k, 0, (sF[tt + 2][k] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
+    tangential_side<T, TN, R>(sNR, tt, k, 0, (sF[tt + 2][k] >> 1) & 1, gp, gam, ghi, glo, eps, iht, P.positivity, Ws,
+                              Wxs, Wys);
     __builtin_amdgcn_sched_barrier(0);
     flux_side<0, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
     __builtin_amdgcn_sched_barrier(0);
-    tangential_side<T, TN, R>(sNR, tt, k, 1, (sF[tt + 2][k + 1] >> 1) & 1, gp, gam, ghi, glo, eps, iht, Ws, Wxs, Wys);
+    tangential_side<T, TN, R>(sNR, tt, k, 1, (sF[tt + 2][k + 1] >> 1) & 1, gp, gam, ghi, glo, eps, iht, P.positivity,
+                              Ws, Wxs, Wys);
     __builtin_amdgcn_sched_barrier(0);
     flux_side<1, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
     __builtin_amdgcn_sched_barrier(0);
@@ -538,9 +586,10 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
     }
   }
 
-  // ---- write F (stage 1) and dF/dt in the grid's component order
+  // ---- write F (stage 1) and dF/dt in the grid's component order. The second stage's dF/dt goes to
+  // the F arrays (F^n is spent by then), which keeps the first stage's dF/dt for the time-order fallback.
   T* Fo = reinterpret_cast<T*>(dir ? P.Fy : P.Fx);
-  T* Go = reinterpret_cast<T*>(dir ? P.Gy : P.Gx);
+  T* Go = reinterpret_cast<T*>(stage == 1 ? (dir ? P.Gy : P.Gx) : (dir ? P.Fy : P.Fx));
   size_t o, plane;
   if (dir == 0) { plane = (size_t)P.ny * (P.nx + 1); o = (size_t)t * (P.nx + 1) + n; }
   else { plane = (size_t)(P.ny + 1) * P.nx; o = (size_t)n * P.nx + t; }
@@ -622,9 +671,10 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
     const double dt = tsp.dt;
     const double idx = 1.0 / P.dx, idy = (P.dim == 2) ? 1.0 / P.dy : 0.0;
     const T* Fx = reinterpret_cast<const T*>(P.Fx);
-    const T* Gx = reinterpret_cast<const T*>(P.Gx);
     const T* Fy = reinterpret_cast<const T*>(P.Fy);
-    const T* Gy = reinterpret_cast<const T*>(P.Gy);
+    // dF/dt: the first stage's in the G arrays, the second stage's in the F arrays
+    const T* Gx = reinterpret_cast<const T*>(stage == 1 ? P.Gx : P.Fx);
+    const T* Gy = reinterpret_cast<const T*>(stage == 1 ? P.Gy : P.Fy);
     const size_t px = (size_t)P.ny * (P.nx + 1), py = (size_t)(P.ny + 1) * P.nx;
     const size_t ox = (size_t)j * (P.nx + 1) + i, oy = (size_t)j * P.nx + i;
     double wn[4] = {0, 0, 0, 0};
@@ -665,13 +715,77 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
     const double ke = 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / rho;
     const double pr = (P.gamma - 1.0) * (wn[3] - ke);
     bad = !(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf());
-    if (bad) atomicOr(&tsp.status, 1);
+    if (bad && stage == 2 && P.positivity)  // left to k_repair: mark the cell (flag bit 2)
+      P.flags[(P.dim == 2 ? (size_t)(j + 2) * (P.nx + 4) : 0) + (i + 2)] |= 4;
+    else if (bad)
+      atomicOr(&tsp.status, 1);
     if (stage == 2) q = cfl_quantity(P, wn[0], wn[1], wn[2], wn[3]);
   }
   if (stage == 2) {
     q = block_min(q);
     if (threadIdx.x == 0) qpart[blockIdx.x] = q;
   }
+}
+
+// Time-order fallback after the second stage (problems with positivity = 1): every face next to a cell
+// that the fourth-order update left non-physical (flag bit 2) takes the one-stage flux F^n + dt/2 dF^n/dt
+// instead of the S2O4 flux F^n + dt/6 (dF^n/dt + 2 dF*/dt). The two differ by dt/3 (dF^n/dt - dF*/dt), so
+// a cell next to such a face changes by -dt^2/3 times that difference's divergence over its marked faces;
+// both neighbours of a face see the same flux, so the update stays conservative. Cells still
+// non-physical set the problem's status. The CFL minima of the blocks are recomputed from the final state.
+template <typename T>
+__global__ void __launch_bounds__(256) k_repair(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
+                                                const int* __restrict__ off, int nprob, double* __restrict__ qpart) {
+  const int p = find_prob(off, nprob, blockIdx.x);
+  const ProbDev& P = probs[p];
+  TimeDev& tsp = ts[p];
+  if (!tsp.active || !P.positivity) return;
+  const size_t ncell = (size_t)P.nx * P.ny;
+  const size_t cell = (size_t)(blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
+  double q = __builtin_inf();
+  if (cell < ncell) {
+    const int i = (int)(cell % P.nx), j = (int)(cell / P.nx);
+    const int two = P.dim == 2;
+    const size_t ex = (size_t)P.nx + 4;
+    auto marked = [&](int a, int b) -> int {
+      if (a < 0 || a >= P.nx || b < 0 || b >= P.ny) return 0;
+      return (P.flags[(two ? (size_t)(b + 2) * ex : 0) + (a + 2)] >> 2) & 1;
+    };
+    const int m0 = marked(i, j);
+    const int mxl = m0 | marked(i - 1, j), mxr = m0 | marked(i + 1, j);
+    const int myl = two ? (m0 | marked(i, j - 1)) : 0, myr = two ? (m0 | marked(i, j + 1)) : 0;
+    const int nc = P.dim + 2;
+    double wn[4] = {0, 0, 0, 0};
+    const double c3 = tsp.dt * tsp.dt / 3.0;
+    const double idx = 1.0 / P.dx, idy = two ? 1.0 / P.dy : 0.0;
+    const T* Gnx = reinterpret_cast<const T*>(P.Gx);
+    const T* Gsx = reinterpret_cast<const T*>(P.Fx);
+    const T* Gny = reinterpret_cast<const T*>(P.Gy);
+    const T* Gsy = reinterpret_cast<const T*>(P.Fy);
+    const size_t px = (size_t)P.ny * (P.nx + 1), py = (size_t)(P.ny + 1) * P.nx;
+    const size_t ox = (size_t)j * (P.nx + 1) + i, oy = (size_t)j * P.nx + i;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c >= nc) break;
+      double w = P.W[c * ncell + cell];
+      if (mxl | mxr | myl | myr) {
+        double d = 0.0;
+        if (mxr) d += (double(Gnx[c * px + ox + 1]) - double(Gsx[c * px + ox + 1])) * idx;
+        if (mxl) d -= (double(Gnx[c * px + ox]) - double(Gsx[c * px + ox])) * idx;
+        if (myr) d += (double(Gny[c * py + oy + P.nx]) - double(Gsy[c * py + oy + P.nx])) * idy;
+        if (myl) d -= (double(Gny[c * py + oy]) - double(Gsy[c * py + oy])) * idy;
+        w -= c3 * d;
+        P.W[c * ncell + cell] = w;
+      }
+      wn[c == nc - 1 ? 3 : c] = w;
+    }
+    const double rho = wn[0];
+    const double pr = (P.gamma - 1.0) * (wn[3] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / rho);
+    if (!(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf())) atomicOr(&tsp.status, 1);
+    q = cfl_quantity(P, wn[0], wn[1], wn[2], wn[3]);
+  }
+  q = block_min(q);
+  if (threadIdx.x == 0) qpart[blockIdx.x] = q;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -773,6 +887,15 @@ int flux_persistent_grid(const LaunchCtx& L) {
   if (L.fp32) launch_flux_t<float>(L, 0, &g);
   else launch_flux_t<double>(L, 0, &g);
   return g;
+}
+
+void launch_repair(const LaunchCtx& L) {
+  if (L.fp32)
+    hipLaunchKernelGGL(k_repair<float>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
+                       L.nprob, L.qpart);
+  else
+    hipLaunchKernelGGL(k_repair<double>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
+                       L.nprob, L.qpart);
 }
 
 void launch_update(const LaunchCtx& L, int stage) {

@@ -29,6 +29,7 @@ struct LaunchCtx {
   int persistent;        // 1: persistent flux launch of persistent_grid blocks
   int persistent_grid;
   int prfix;             // 1 if any problem is Navier-Stokes with Pr != 1
+  int positivity;        // 1 if any problem asks for the first-order fallbacks
   int cell_blocks, ext_blocks, flux_blocks;  // flux_blocks: tiles of all problems
 };
 
@@ -48,5 +49,6 @@ void launch_flags(const LaunchCtx& L, int stage_state, int count, int clear);
 void launch_flux(const LaunchCtx& L, int stage);
 int flux_persistent_grid(const LaunchCtx& L);  // blocks of the persistent flux launch for L's variant
 void launch_update(const LaunchCtx& L, int stage);
+void launch_repair(const LaunchCtx& L);
 
 }  // namespace hk

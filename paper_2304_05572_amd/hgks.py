@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libhgks.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EDT = 0, -1, -2, -3, -4, -5
 EULER, NS = 0, 1
-BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_NOSLIP = 0, 1, 2, 3
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_NOSLIP, BC_PRESCRIBED = 0, 1, 2, 3, 4
 RECON_HYBRID, RECON_WENOAO, RECON_LINEAR = 0, 1, 2
 FP64, FP32_BULK = 0, 1
 NUM_LAUNCH_CONFIGS = 12  # flux launch configurations: 6 tile shapes x (one block per tile, persistent)
@@ -42,6 +42,24 @@ class HgksError(RuntimeError):
         self.code = code
 
 
+class hgks_bc_data(C.Structure):
+    _fields_ = [("a", C.c_double * 4), ("b", C.c_double * 4), ("s0", C.c_double), ("sn", C.c_double),
+                ("st", C.c_double), ("rest", C.c_int32), ("reserved", C.c_int32)]
+
+
+@dataclasses.dataclass
+class BcData:
+    """A prescribed-state side (BC_PRESCRIBED): ghost cells take the conserved state ``a`` where their
+    tangential coordinate is below s0 + sn * (normal coordinate) + st * t, else the state ``b``
+    (rest = BC_PRESCRIBED) or the ghost of boundary kind ``rest``."""
+    a: tuple = (1.0, 0.0, 0.0, 2.5)
+    b: tuple = (1.0, 0.0, 0.0, 2.5)
+    s0: float = float("inf")
+    sn: float = 0.0
+    st: float = 0.0
+    rest: int = BC_PRESCRIBED
+
+
 class hgks_problem(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
@@ -50,7 +68,8 @@ class hgks_problem(C.Structure):
         ("cfl", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("fixed_dt", C.c_double),
         ("bc", C.c_int32 * 4), ("recon", C.c_int32),
         ("gamma_hi", C.c_double), ("gamma_lo", C.c_double), ("weno_eps", C.c_double),
-        ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32),
+        ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32), ("positivity", C.c_int32),
+        ("bcd", hgks_bc_data * 4),
     ]
 
 
@@ -85,6 +104,8 @@ class Problem:
     weno_eps: float = 1e-8
     zeta1_mode: int = 0
     tangential_flag_mode: int = 0
+    positivity: int = 0  # 1: first-order fallback for non-physical reconstructed states
+    bcd: tuple = ()  # BcData per side (x-low, x-high, y-low, y-high), read where bc is BC_PRESCRIBED
 
     @property
     def nc(self):
@@ -104,6 +125,13 @@ class Problem:
             v = getattr(self, f.name)
             if f.name == "bc":
                 s.bc = (C.c_int32 * 4)(*[int(b) for b in (list(v) + [0] * 4)[:4]])
+            elif f.name == "bcd":
+                for k, d in enumerate(list(v)[:4]):
+                    if isinstance(d, dict):
+                        d = BcData(**d)
+                    if d is not None:
+                        s.bcd[k] = hgks_bc_data((C.c_double * 4)(*d.a), (C.c_double * 4)(*d.b), d.s0, d.sn,
+                                                d.st, int(d.rest), 0)
             else:
                 setattr(s, f.name, v)
         return s

@@ -38,6 +38,14 @@ def test_problem_struct_layout_matches_header():
     assert [f[0] for f in H.hgks_opts._fields_] == names
 
 
+def test_bc_data_layout_matches_header():
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\} hgks_bc_data;", src, re.S).group(1)
+    names = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)(?:\[\d+\])?\s*[,;]", body)
+    assert [f[0] for f in H.hgks_bc_data._fields_] == names
+    assert C.sizeof(H.hgks_bc_data) == 8 * 11 + 8
+
+
 def test_status_strings():
     for code in (H.OK, H.EINVAL, H.ENOMEM, H.EDEVICE, H.ENONPHYS, H.EDT):
         assert H.hgks_status_str(code) and H.hgks_status_str(code) != "unknown status"
@@ -46,7 +54,15 @@ def test_status_strings():
 @pytest.mark.parametrize("bad", [
     dict(nx=4), dict(dim=3), dict(gamma=1.0), dict(bc=(0, 1, 1, 1)), dict(dim=1, ny=3),
     dict(eqn=1, Pr=0.0), dict(recon=5), dict(cfl=0.0), dict(x1=0.0), dict(gamma_hi=1.0),
-    dict(tangential_flag_mode=1),
+    dict(tangential_flag_mode=1), dict(positivity=2),
+    # prescribed-state sides: no data (rest 0), a periodic rest, NaN split, non-physical states
+    dict(bc=(4, 1, 1, 1)), dict(bc=(4, 1, 1, 1), bcd=(H.BcData(rest=0),)),
+    dict(bc=(0, 4, 1, 1), bcd=(None, H.BcData())),
+    dict(bc=(1, 1, 4, 1), bcd=(None, None, H.BcData(s0=float("nan")))),
+    dict(bc=(1, 1, 1, 4), bcd=(None, None, None, H.BcData(st=float("inf")))),
+    dict(bc=(4, 1, 1, 1), bcd=(H.BcData(a=(1.0, 0.0, 0.0, -1.0)),)),
+    dict(bc=(4, 1, 1, 1), bcd=(H.BcData(b=(-1.0, 0.0, 0.0, 2.5)),)),
+    dict(dim=1, ny=1, bc=(1, 4, 0, 0), bcd=(None, H.BcData(a=(1.0, 3.0, 0.0, 1.0), rest=2))),
 ])
 def test_invalid_problems_rejected_on_host(bad):
     P = H.Problem(**bad)

@@ -1,0 +1,190 @@
+"""Prescribed-state boundaries and the double Mach reflection (Sec. 3.5) through the C ABI against the
+oracle: the states of every step, the time steps and the troubled-cell flags on small grids, a uniform
+inflow kept bitwise, and the full 960 x 240 problem to its end time with windows of a late step checked
+against the oracle (windows that touch the domain edge carry the problem's own boundary data, which is
+given in absolute coordinates)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_05572_amd import hgks as H
+from paper_2304_05572_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def l1(a, b):
+    return float(np.abs(a - b).mean() / np.abs(b).mean())
+
+
+@pytest.mark.parametrize("walls", [True, False])
+def test_double_mach_steps_match_oracle(walls):
+    """10 FP64 steps of the 120 x 30 problem (walls: the reflection; no walls: the translating shock with
+    the exact moving state on top and bottom), each checked by an oracle step from the GPU's state before
+    it (at the same time): time steps bit-exact, states to 1e-12, flags bit-exact before the first and
+    after the last step. (Run freely, the two drift apart at the Mach 10 shock by more than rounding within
+    a few steps: the nonlinear weights amplify last-bit differences there.)"""
+    nx, ny = 120, 30
+    W0, kw = wl.double_mach(nx, ny, walls=walls)
+    Po, Ph = O.Problem(**kw), H.Problem(**kw)
+    say("double mach", "walls" if walls else "translating", nx, ny)
+    s = H.Solver(Ph)
+    s.set_ic(0, W0)
+    fx, fy = s.flags(0)
+    ox, oy = O.flags(Po, W0, 0.0)
+    assert np.array_equal(fx, ox) and np.array_equal(fy, oy) and ox.any()
+    Wg, tg = W0, 0.0
+    worst = 0.0
+    for k in range(10):
+        Wo, to, dto = O.step(Po, Wg, tg, nthreads=NT)
+        assert s.step()[0] == dto, k
+        Wg, tg = s.get_state(0)
+        assert tg == to, k
+        worst = max(worst, rel(Wg, Wo))
+    say("worst step rel", worst)
+    assert worst < 1e-12
+    fx, fy = s.flags(0)
+    ox, oy = O.flags(Po, Wg, tg)
+    assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
+
+
+def test_double_mach_fp32_bulk_close_to_oracle():
+    """FP32-bulk over 10 steps against the FP64 oracle. At the Mach 10 shock the nonlinear weights turn the
+    FP32 rounding of the reconstruction (~1e-7) into ~1e-3 local differences (as far as 1e-2 is allowed),
+    which then spread over the post-shock region at the 1e-7..1e-5 level; the mean stays near 2e-5."""
+    nx, ny = 120, 30
+    W0, kw = wl.double_mach(nx, ny)
+    say("double mach fp32-bulk")
+    s = H.Solver(H.Problem(**kw), precision=H.FP32_BULK, use_graph=True)
+    s.set_ic(0, W0)
+    Wo, t = W0.copy(), 0.0
+    for _ in range(10):
+        Wo, t, _ = O.step(O.Problem(**kw), Wo, t, nthreads=NT)
+    s.run(np.inf, 10)
+    Wg, _ = s.get_state(0)
+    say("L1", l1(Wg, Wo), "Linf", rel(Wg, Wo))
+    assert l1(Wg, Wo) < 1e-4 and rel(Wg, Wo) < 1e-2
+
+
+def test_prescribed_sides_1d_and_stage_time():
+    """1D: an inflow state prescribed on the left whose value switches (state b until t* = -s0/st, then a)
+    inside the run, so that some step has its two stages on either side of the switch; 40 steps, each
+    against an oracle step from the GPU's state."""
+    n = 100
+    qa = wl._cons_tuple((2.0, 1.5, 0.0, 3.0))
+    qb = wl._cons_tuple((1.0, 1.2, 0.0, 1.0))
+    bcd = (dict(a=qa, b=qb, s0=-0.02, sn=0.0, st=1.0, rest=4), None)  # 0 < -0.02 + t  <=>  t > 0.02
+    kw = dict(dim=1, nx=n, ny=1, bc=(4, 1, 0, 0), bcd=bcd, cfl=0.5)
+    W0 = np.stack([np.full(n, qb[0]), np.full(n, qb[1]), np.full(n, qb[3])])
+    Wo, t = W0.copy(), 0.0
+    s = H.Solver(H.Problem(**kw))
+    s.set_ic(0, W0)
+    say("1d prescribed switch")
+    straddled = False
+    worst = 0.0
+    Wg = W0
+    for k in range(40):
+        t_prev = t
+        Wo, t, dto = O.step(O.Problem(**kw), Wg, t, nthreads=NT)
+        straddled |= t_prev < 0.02 < t_prev + 0.5 * dto
+        assert s.step()[0] == dto, k
+        Wg, tg = s.get_state(0)
+        assert tg == t, k
+        worst = max(worst, rel(Wg, Wo))
+    assert t > 0.02 and worst < 1e-12
+    assert np.abs(Wg[0] - qb[0]).max() > 0.1  # the switched state has entered
+    say("a step straddled the switch between its stages:", straddled)
+
+
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32_BULK])
+def test_prescribed_uniform_stream_bitwise(precision):
+    rho, u, v, p = 1.3, 2.1, -0.4, 0.7
+    q = wl._cons_tuple((rho, u, v, p))
+    bcd = (dict(a=q, b=q), None, dict(a=q, b=q), None)
+    W0 = np.stack([np.full((20, 24), c) for c in q])
+    s = H.Solver(H.Problem(nx=24, ny=20, bc=(4, 1, 4, 1), bcd=bcd), precision=precision)
+    s.set_ic(0, W0)
+    s.run(np.inf, 5)
+    Wg, _ = s.get_state(0)
+    if precision == H.FP64:
+        assert np.array_equal(Wg, W0)
+    else:
+        assert rel(Wg, W0) < 1e-6
+
+
+def _dmr_windows(Wprev, Wnext, dt, t, kw, centres, half=20, margin=10):
+    nx, ny = kw["nx"], kw["ny"]
+    hx, hy = (kw["x1"] - kw["x0"]) / nx, (kw["y1"] - kw["y0"]) / ny
+    bc, bcd = kw["bc"], kw["bcd"]
+    worst = 0.0
+    for (ci, cj) in centres:
+        i0, i1 = max(ci - half - margin, 0), min(ci + half + margin, nx)
+        j0, j1 = max(cj - half - margin, 0), min(cj + half + margin, ny)
+        sub = np.ascontiguousarray(Wprev[:, j0:j1, i0:i1])
+        edge = (i0 == 0, i1 == nx, j0 == 0, j1 == ny)
+        wbc = tuple(bc[k] if edge[k] else 1 for k in range(4))
+        wbcd = tuple(bcd[k] if edge[k] else None for k in range(4))
+        P = O.Problem(**dict(kw, nx=i1 - i0, ny=j1 - j0, x0=i0 * hx, x1=i1 * hx, y0=j0 * hy, y1=j1 * hy, bc=wbc,
+                             bcd=wbcd, fixed_dt=dt))
+        Wo, _, _ = O.step(P, sub, t, nthreads=NT)
+        a0, a1 = (0 if edge[0] else margin), ((i1 - i0) if edge[1] else (i1 - i0 - margin))
+        b0, b1 = (0 if edge[2] else margin), ((j1 - j0) if edge[3] else (j1 - j0 - margin))
+        worst = max(worst, rel(Wnext[:, j0 + b0:j0 + b1, i0 + a0:i0 + a1], Wo[:, b0:b1, a0:a1]))
+    return worst
+
+
+def test_double_mach_960x240_to_end_time():
+    """The paper's grid to t = 0.2 in FP64 with the autotuned launch configuration, at CFL 0.5 (at the
+    paper's 0.8 this reading breaks down before t = 0.1 even with the first-order fallbacks): the 200th
+    step on windows over the wall corner at x = 1/6, the left inflow, the top boundary where the moving
+    shock enters, the Mach stem and the reflected shock against the oracle; at the end no non-physical
+    state, the incident shock's upper quarter on the exact line and the gas ahead of the structure
+    untouched."""
+    nx, ny = 960, 240
+    W0, kw = wl.double_mach(nx, ny, cfl=0.5)
+    say("dmr 960x240")
+    s = H.Solver(H.Problem(**kw), autotune=True, use_graph=True)
+    s.set_ic(0, W0)
+    s.run(np.inf, 199)
+    W199, t199 = s.get_state(0)
+    dt = s.step()[0]
+    W200, _ = s.get_state(0)
+    centres = [(40, 5), (5, 120), (400, 235), (330, 10), (300, 60), (600, 200)]
+    worst = _dmr_windows(W199, W200, dt, t199, kw, centres)
+    say("200th step windows worst rel", worst, "t", t199)
+    assert worst < 1e-12
+    steps = s.run(0.2)[0]
+    W, t = s.get_state(0)
+    say("end", t, "steps", int(steps) + 200)
+    assert t == 0.2
+    rho, _, _, p = wl.cons_to_prim(W)
+    assert rho.min() > 0 and p.min() > 0
+    h = 4.0 / nx
+    xc = (np.arange(nx) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) / ny
+    mid = 0.5 * (wl.DMR_PRE[0] + wl.DMR_POST[0])
+    off = []
+    for j in range(3 * ny // 4, ny):  # above the reflected structures
+        r = W[0, j]
+        k = np.nonzero((r[:-1] >= mid) & (r[1:] < mid))[0][-1]
+        xs = xc[k] + (r[k] - mid) / (r[k] - r[k + 1]) * h
+        off.append((xs - wl.dmr_shock_x(yc[j], t)) / h)
+    off = np.array(off)
+    say("incident shock offsets (cells) in the upper quarter: mean", off.mean(), "std", off.std(), "max", np.abs(off).max())
+    # straight, at 60 degrees and at the exact speed: a constant sub-cell offset of the midpoint crossing
+    assert np.abs(off).max() < 1.0 and off.std() < 0.2
+    ahead = np.broadcast_to(xc, (ny, nx)) > wl.dmr_shock_x(1.0, t) + 6 * h
+    pre = np.array(wl._cons_tuple(wl.DMR_PRE))
+    assert np.abs(W[:, ahead] - pre[:, None]).max() < 1e-6

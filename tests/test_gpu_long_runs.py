@@ -71,6 +71,27 @@ def test_blast_wave_reported_nonphysical_like_the_oracle():
     assert eg.value.code == H.ENONPHYS
 
 
+@pytest.mark.parametrize("precision,tol1", [(H.FP64, 1e-10), (H.FP32_BULK, 1e-4)])
+def test_blast_wave_with_fallbacks_to_end_time(precision, tol1):
+    """Sec. 3.2(c) with positivity = 1 (first-order fallbacks, among them the conservative one-stage flux
+    on the faces of a cell the S2O4 update would leave non-physical): the whole run to t = 0.038 on the
+    GPU against the oracle's, mass and energy conserved between the walls."""
+    kw = dict(dim=1, nx=400, ny=1, bc=(2, 2, 0, 0), cfl=0.5, positivity=1)
+    W0 = wl.blast_wave_1d(400)
+    say("blast wave with fallbacks, oracle")
+    Wo, to, no, _ = O.run(O.Problem(**kw), W0, 0.038, nthreads=NT)
+    say("blast wave with fallbacks, gpu", precision)
+    s = H.Solver(H.Problem(**kw), precision=precision, use_graph=True)
+    s.set_ic(0, W0)
+    steps = s.run(0.038)[0]
+    Wg, t = s.get_state(0)
+    say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+    assert t == 0.038 and abs(int(steps) - no) <= 2
+    assert l1(Wg, Wo) < tol1
+    for c in (0, 2):
+        assert abs(Wg[c].sum() - W0[c].sum()) < (1e-12 if precision == H.FP64 else 1e-6) * W0[c].sum()
+
+
 def test_riemann_256_to_end_time():
     """The seed-0 four-quadrant problem at 256^2 to t = 0.25 in FP64, GPU against oracle over the whole run
     (about 300 steps, each with its own bit-exact CFL step while the states agree to rounding)."""

@@ -179,11 +179,106 @@ def test_shu_osher_shock_front():
 def test_blast_wave_fails_at_first_step_as_read():
     """Sec. 3.2(c), read as stated (no positivity treatment is given): at the 1e5 pressure jump the
     second-stage dF/dt term of the first step drives a cell's pressure negative, which the oracle reports
-    as a non-physical state rather than producing NaNs."""
+    as a non-physical state rather than producing NaNs (positivity = 0, the default)."""
     P = O.Problem(dim=1, nx=400, ny=1, bc=(O.BC_REFLECT, O.BC_REFLECT, 0, 0), cfl=0.5)
     with pytest.raises(O.OracleError) as e:
         O.step(P, wl.blast_wave_1d(400), 0.0)
     assert e.value.code == O.ENONPHYS
+
+
+def _shock_offsets(W, nx, ny, t):
+    """Per row: position of the density midpoint crossing of the Mach 10 shock minus the exact shock
+    position, in cells."""
+    h = 4.0 / nx
+    xc = (np.arange(nx) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) / ny
+    mid = 0.5 * (wl.DMR_PRE[0] + wl.DMR_POST[0])
+    out = []
+    for j in range(ny):
+        r = W[0, j]
+        k = np.nonzero((r[:-1] >= mid) & (r[1:] < mid))[0][-1]
+        xs = xc[k] + (r[k] - mid) / (r[k] - r[k + 1]) * h
+        out.append((xs - wl.dmr_shock_x(yc[j], t)) / h)
+    return np.array(out)
+
+
+def test_translating_oblique_shock_with_exact_boundaries():
+    """The Mach 10 shock of Sec. 3.5 with the exact moving-shock state prescribed on the top and the bottom
+    (inflow on the left, zero gradient on the right): the exact solution translates the shock along its
+    normal at speed 10. After 25 steps every row, the two boundary rows included, has its shock within half
+    a cell of the exact position, which the prescribed sides only give if their split moves with time along
+    the shock line; the gas ahead stays at the pre-shock state."""
+    nx, ny = 120, 30
+    W0, kw = wl.double_mach(nx, ny, walls=False)
+    W, t, n, _ = O.run(O.Problem(**kw), W0, 0.05, nthreads=NT)
+    assert t == 0.05
+    off = _shock_offsets(W, nx, ny, t)
+    assert np.abs(off).max() < 0.5
+    h = 4.0 / nx
+    X, Y = np.meshgrid((np.arange(nx) + 0.5) * h, (np.arange(ny) + 0.5) / ny)
+    ahead = X > wl.dmr_shock_x(Y, t) + 6 * h
+    pre = np.array(wl._cons_tuple(wl.DMR_PRE))
+    assert np.abs(W[:, ahead] - pre[:, None]).max() < 1e-6
+
+
+def test_double_mach_reflection():
+    """Sec. 3.5 on a 120 x 30 grid to t = 0.2: the scheme as stated fails in the first step (a non-physical
+    Gauss-point state at the wall corner), with the first-order fallback for such states it runs; the upper
+    half of the incident shock sits within half a cell of the exact line, the Mach stem at the wall runs
+    ahead of it, and the gas ahead of the whole structure is untouched."""
+    nx, ny = 120, 30
+    W0, kw = wl.double_mach(nx, ny)
+    with pytest.raises(O.OracleError) as e:
+        O.step(O.Problem(**dict(kw, positivity=0)), W0, 0.0, nthreads=NT)
+    assert e.value.code == O.ENONPHYS
+    W, t, n, _ = O.run(O.Problem(**kw), W0, 0.2, nthreads=NT)
+    assert t == 0.2
+    rho, _, _, p = wl.cons_to_prim(W)
+    assert rho.min() > 0 and p.min() > 0
+    off = _shock_offsets(W, nx, ny, t)
+    assert np.abs(off[ny // 2:]).max() < 0.5
+    assert off[0] > 3.0  # the Mach stem
+    h = 4.0 / nx
+    X = np.broadcast_to((np.arange(nx) + 0.5) * h, (ny, nx))
+    ahead = X > wl.dmr_shock_x(1.0, t) + 6 * h
+    pre = np.array(wl._cons_tuple(wl.DMR_PRE))
+    assert ahead.sum() > 0 and np.abs(W[:, ahead] - pre[:, None]).max() < 1e-6
+
+
+def test_prescribed_inflow_preserves_a_uniform_flow():
+    """A prescribed side holding the flow's own state is exact: a uniform supersonic stream entering on the
+    left and leaving through zero-gradient ghosts stays bitwise uniform, in 1D and 2D."""
+    rho, u, v, pr = 1.3, 2.1, -0.4, 0.7
+    for dim in (1, 2):
+        q = wl._cons_tuple((rho, u, v if dim == 2 else 0.0, pr))
+        bcd = (O.BcData(a=q, b=q), None, O.BcData(a=q, b=q), None)
+        if dim == 1:
+            P = O.Problem(dim=1, nx=40, ny=1, bc=(O.BC_PRESCRIBED, O.BC_OUTFLOW, 0, 0), bcd=bcd)
+            W0 = np.stack([np.full(40, q[0]), np.full(40, q[1]), np.full(40, q[3])])
+        else:
+            P = O.Problem(nx=24, ny=20, bc=(O.BC_PRESCRIBED, O.BC_OUTFLOW, O.BC_PRESCRIBED, O.BC_OUTFLOW), bcd=bcd)
+            W0 = np.stack([np.full((20, 24), c) for c in q])
+        W, t, n, _ = O.run(P, W0, np.inf, max_steps=5, nthreads=NT)
+        assert n == 5 and np.array_equal(W, W0)
+
+
+def test_blast_wave_runs_with_the_first_order_fallbacks():
+    """Sec. 3.2(c) with positivity = 1: the faces of a cell that the S2O4 update would leave non-physical
+    take the one-stage flux, which is conservative, so the run reaches t = 0.038 with mass, momentum
+    (zero between the two walls) and energy conserved to rounding; the density peak of the colliding
+    blast waves sits near x = 0.78 at about 6 (the well-known value for this problem; the paper shows it
+    in a figure only)."""
+    kw = dict(dim=1, nx=400, ny=1, bc=(O.BC_REFLECT, O.BC_REFLECT, 0, 0), cfl=0.5, positivity=1)
+    W0 = wl.blast_wave_1d(400)
+    W, t, n, _ = O.run(O.Problem(**kw), W0, 0.038, nthreads=NT)
+    assert t == 0.038
+    rho, _, _, p = wl.cons_to_prim(W)
+    assert rho.min() > 0 and p.min() > 0
+    assert abs(W[0].sum() - W0[0].sum()) < 1e-12 * W0[0].sum()
+    assert abs(W[2].sum() - W0[2].sum()) < 1e-12 * W0[2].sum()
+    x = (np.arange(400) + 0.5) / 400
+    i = int(np.argmax(W[0]))
+    assert 5.5 < W[0, i] < 6.5 and abs(x[i] - 0.78) < 0.01
 
 
 def test_conservation_periodic():

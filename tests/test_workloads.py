@@ -1,5 +1,7 @@
 """The seeded four-quadrant generator: every edge carries exactly one elementary wave, checked with the
 exact 1D Riemann solver across each edge, and states stay within the stated ranges."""
+import math
+
 import numpy as np
 import pytest
 
@@ -35,3 +37,28 @@ def test_quadrant_edges_are_elementary_waves(seed):
 def test_batch_sizes_range():
     s = wl.batch_sizes(64, seed=0)
     assert len(s) == 64 and min(s) >= 128 and max(s) <= 1024
+
+
+def test_double_mach_states_satisfy_rankine_hugoniot():
+    """Sec. 3.5's post-shock state is the Rankine-Hugoniot state behind a Mach 10 shock (speed 10 into gas
+    with sound speed 1) whose normal points along (cos 30, -sin 30): in the shock frame mass, normal
+    momentum and energy fluxes are continuous and the tangential velocity is unchanged."""
+    g = wl.GAMMA
+    n = np.array([math.cos(math.pi / 6), -math.sin(math.pi / 6)])
+    tg = np.array([-n[1], n[0]])
+    r1, u1, v1, p1 = wl.DMR_PRE
+    r2, u2, v2, p2 = wl.DMR_POST
+    assert math.isclose(math.sqrt(g * p1 / r1), 1.0)
+    s = wl.DMR_SHOCK_SPEED
+    w1 = np.dot([u1, v1], n) - s
+    w2 = np.dot([u2, v2], n) - s
+    h1 = g / (g - 1) * p1 / r1 + 0.5 * w1 * w1
+    h2 = g / (g - 1) * p2 / r2 + 0.5 * w2 * w2
+    assert math.isclose(r1 * w1, r2 * w2, rel_tol=1e-12)
+    assert math.isclose(r1 * w1 * w1 + p1, r2 * w2 * w2 + p2, rel_tol=1e-12)
+    assert math.isclose(h1, h2, rel_tol=1e-12)
+    assert abs(np.dot([u2, v2], tg) - np.dot([u1, v1], tg)) < 1e-12
+    # the shock line passes through (1/6, 0) at 60 degrees and moves along x at s / cos 30
+    assert math.isclose(float(wl.dmr_shock_x(0.0, 0.0)), 1.0 / 6.0)
+    assert math.isclose(float(wl.dmr_shock_x(1.0, 0.0)) - 1.0 / 6.0, 1.0 / math.tan(math.pi / 3))
+    assert math.isclose(float(wl.dmr_shock_x(0.0, 0.1)) - 1.0 / 6.0, 0.1 * s / math.cos(math.pi / 6))
