@@ -41,7 +41,7 @@ PEAK_HBM = 8000.0  # GB/s
 # workload (seed 0, about 2% of the cells troubled): normal and tangential reconstruction, equilibrium
 # state and gas-kinetic flux, from the SQ_INSTS_VALU_FLOPS_FP64 counter (the tile's recomputation of halo
 # rows is below 0.5%; profiles/k_flux_rp1024_counters.txt).
-FLOPS_PER_GP_FP64 = 2511.6
+FLOPS_PER_GP_FP64 = 2513.1
 
 
 def log(*a):
