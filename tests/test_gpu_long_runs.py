@@ -113,6 +113,30 @@ def test_riemann_256_to_end_time():
     assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
 
 
+@pytest.mark.parametrize("name,states,cfl,t_end", [("configuration 1", wl.RP_CONFIG1, 0.5, 0.2),
+                                                   ("configuration 6", wl.RP_CONFIG6, 0.95, 0.6)])
+def test_paper_riemann_configurations_to_end_time(name, states, cfl, t_end):
+    """Sec. 3.4's configurations with their CFL numbers and end times, on a 128^2 grid: the whole FP64 run
+    on the GPU against the oracle's (same step count; states to rounding-order differences), and the flags
+    of the final state bit-exact."""
+    n = 128
+    kw = dict(dim=2, nx=n, ny=n, bc=(1, 1, 1, 1), cfl=cfl, c1=0.01, c2=1.0)
+    W0 = wl.quadrants(n, n, states)
+    say(name, "oracle")
+    Wo, to, no, _ = O.run(O.Problem(**kw), W0, t_end, nthreads=NT)
+    say(name, "gpu")
+    s = H.Solver(H.Problem(**kw), use_graph=True, autotune=True)
+    s.set_ic(0, W0)
+    steps = s.run(t_end)[0]
+    Wg, t = s.get_state(0)
+    say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+    assert t == t_end and steps == no
+    assert l1(Wg, Wo) < 1e-9 and linf(Wg, Wo) < 1e-6
+    fx, fy = s.flags(0)
+    ox, oy = O.flags(O.Problem(**kw), Wg)
+    assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
+
+
 def test_viscous_shock_tube_hundredth_step():
     """Navier-Stokes, 1000 x 500, Re = 200, Pr = 0.73: the 100th FP64 step on windows over the shock, the
     contact, the wall corners and the symmetry line against the oracle (each window one oracle step with
