@@ -38,10 +38,12 @@ PEAK_FP64_VALU = 78.6  # TFLOP/s, MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (packed)
 PEAK_HBM = 8000.0  # GB/s
 # FP64 operations (FMA = 2) per Gauss-point evaluation of the fused reconstruction + flux kernel on this
-# workload (seed 0, about 2% of the cells troubled): normal and tangential reconstruction, equilibrium
-# state and gas-kinetic flux, from the SQ_INSTS_VALU_FLOPS_FP64 counter (the tile's recomputation of halo
-# rows is below 0.5%; profiles/k_flux_rp1024_counters.txt).
-FLOPS_PER_GP_FP64 = 2513.1
+# workload (seed 0) in the default timed window (3 warm-up + 20 steps, 1.6-2% of the cells troubled):
+# normal and tangential reconstruction, equilibrium state and gas-kinetic flux, from the
+# SQ_INSTS_VALU_FLOPS_FP64 counter over the window's launches (profiles/k_flux_rp1024_counters.txt). The
+# counter counts active lanes, so this is the algorithmic count of the hybrid scheme to well under 1%
+# (linear path everywhere, WENO5-AO on troubled sides; profiles/k_flux_rp1024_recon_modes.txt).
+FLOPS_PER_GP_FP64 = 2545.5
 
 
 def log(*a):
@@ -183,19 +185,28 @@ def tile_sweep(args):
     from paper_2304_05572_amd import hgks as H
     from paper_2304_05572_amd import workloads as wl
     W0, _ = wl.riemann_2d(args.n, seed=args.seed)
+    recon = {"hybrid": H.RECON_HYBRID, "wenoao": H.RECON_WENOAO, "linear": H.RECON_LINEAR}[args.recon]
+    configs = range(H.NUM_LAUNCH_CONFIGS) if args.configs == "all" else [int(c) for c in args.configs.split(",")]
     for name, prec in (("fp64", H.FP64), ("fp32", H.FP32_BULK)):
         if name not in args.variants.split(","):
             continue
-        for c in range(H.NUM_LAUNCH_CONFIGS):
-            s = H.Solver(rp_problem(H, args.n), precision=prec, tile=c, profile=1)
+        for c in configs:
+            s = H.Solver(rp_problem(H, args.n, recon), precision=prec, tile=c, profile=1)
             s.set_ic(0, W0)
-            s.run(np.inf, 1)
-            p0 = s.profile()["flux"]
-            s.run(np.inf, 3)
-            p1 = s.profile()["flux"]
+            try:
+                s.run(np.inf, 1)
+                p0 = s.profile()["flux"]
+                s.run(np.inf, 3)
+                p1 = s.profile()["flux"]
+                ms = (p1[0] - p0[0]) / max(p1[1] - p0[1], 1)
+            except H.HgksError as e:  # forced linear reconstruction cannot hold the discontinuities
+                ms = None
+                log(f"[bench] tile sweep {name} config {c} {args.recon}: {e}")
             torch.cuda.synchronize()
-            print(json.dumps({"precision": name, "config": c, "tile": s.tile(),
-                              "flux_ms_per_launch": (p1[0] - p0[0]) / max(p1[1] - p0[1], 1)}), flush=True)
+            st = s.stats(0)
+            print(json.dumps({"precision": name, "config": c, "recon": args.recon, "tile": s.tile(),
+                              "flux_ms_per_launch": ms, "flagged_x": st["flagged_x"],
+                              "flagged_y": st["flagged_y"]}), flush=True)
             s.close()
 
 
@@ -303,6 +314,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="only run a plain copy (counter scaling)")
     ap.add_argument("--tile-sweep", action="store_true",
                     help="only time every flux launch configuration (FP64 and FP32-bulk, 3 steps each)")
+    ap.add_argument("--recon", default="hybrid", choices=("hybrid", "wenoao", "linear"),
+                    help="reconstruction of the --tile-sweep runs (every cell troubled / none)")
+    ap.add_argument("--configs", default="all", help="launch configurations of the --tile-sweep runs")
     ap.add_argument("--paper-cases", action="store_true",
                     help="only run the paper's 2D cases (Riemann configurations 1 and 6, double Mach reflection) "
                          "to their end times, hybrid against forced WENO5-AO")
