@@ -325,8 +325,12 @@ __device__ inline bool admissible(const T* w, T gam) {
   return w[0] > T(0) && pr > T(0) && isfinite(pr);
 }
 
-// Stride (in values) of one interface entry of the normal-reconstruction rows in LDS.
+// Stride (in values) of one interface entry of the normal-reconstruction rows in LDS, and of one row
+// of TN entries: FP64 rows take 2 more values so that rows four apart fall on different banks (the
+// y-interface blocks read rows tt and tt + 4 in one half-wavefront).
 constexpr int kNRS = 17;
+template <typename T, int TN>
+constexpr int nr_row() { return TN * kNRS + (sizeof(T) == 8 ? 2 : 0); }
 
 // Threads of a flux block: one per Gauss point in 2D (two per interface), one per interface in 1D.
 constexpr int flux_threads(int tn, int tt, int dim) { return (dim == 2 ? 2 : 1) * tn * tt; }
@@ -336,20 +340,24 @@ constexpr int flux_threads(int tn, int tt, int dim) { return (dim == 2 ? 2 : 1) 
 // point, tangential slope of W^s, value of W^s_x. Linear quartic per component, or WENO-AO in the
 // tangential characteristic variables about the side's own centre-segment state when flagged.
 template <typename T, int TN, int R>
-__device__ inline void tangential_side(const T (*sNR)[TN][kNRS], int tt, int k, int s, int ft, int gp, T gam, T ghi,
+__device__ inline void tangential_side(const T* sNR, int tt, int k, int s, int ft, int gp, T gam, T ghi,
                                        T glo, T eps, T iht, int pos, T Ws[4], T Wxs[4], T Wys[4]) {
+  constexpr int NRW = nr_row<T, TN>();
   const int ov = 8 * s, od = 8 * s + 4;
   if (ft) {
     CharMat<T> m;
     T own[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) own[v] = sNR[tt + 2][k][ov + v];
+    for (int v = 0; v < 4; ++v) own[v] = sNR[(tt + 2) * NRW + k * kNRS + ov + v];
     char_matrices(own, gam, 2, m);
     T qv[5][4], qd[5][4], val[4], der[4];
 #pragma unroll
     for (int r = 0; r < 5; ++r)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { qv[r][v] = sNR[tt + r][k][ov + v]; qd[r][v] = sNR[tt + r][k][od + v]; }
+      for (int v = 0; v < 4; ++v) {
+        qv[r][v] = sNR[(tt + r) * NRW + k * kNRS + ov + v];
+        qd[r][v] = sNR[(tt + r) * NRW + k * kNRS + od + v];
+      }
     ao_vector(qv, m, 2 + gp, ghi, glo, eps, val, der);
 #pragma unroll
     for (int v = 0; v < 4; ++v) { Ws[v] = val[v]; Wys[v] = der[v] * iht; }
@@ -361,7 +369,10 @@ __device__ inline void tangential_side(const T (*sNR)[TN][kNRS], int tt, int k, 
     for (int v = 0; v < 4; ++v) {
       T q[5], qx[5], vv, dd, vx, dx_;
 #pragma unroll
-      for (int r = 0; r < 5; ++r) { q[r] = sNR[tt + r][k][ov + v]; qx[r] = sNR[tt + r][k][od + v]; }
+      for (int r = 0; r < 5; ++r) {
+        q[r] = sNR[(tt + r) * NRW + k * kNRS + ov + v];
+        qx[r] = sNR[(tt + r) * NRW + k * kNRS + od + v];
+      }
       gauss_linear(q, gp, vv, dd);
       gauss_linear(qx, gp, vx, dx_);
       Ws[v] = vv;
@@ -372,9 +383,9 @@ __device__ inline void tangential_side(const T (*sNR)[TN][kNRS], int tt, int k, 
   if (pos && !admissible(Ws, gam)) {  // first order along the interface: the centre segment's line values
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      Ws[v] = sNR[tt + 2][k][ov + v];
+      Ws[v] = sNR[(tt + 2) * NRW + k * kNRS + ov + v];
       Wys[v] = T(0);
-      Wxs[v] = sNR[tt + 2][k][od + v];
+      Wxs[v] = sNR[(tt + 2) * NRW + k * kNRS + od + v];
     }
   }
 }
@@ -386,7 +397,8 @@ __device__ inline void tangential_side(const T (*sNR)[TN][kNRS], int tt, int k, 
 //   sF  : flags of the cells adjacent to each interface (bit 0 normal, bit 1 tangential)
 //   sNR : normal reconstruction of every row: W^l, W^l_x, W^r, W^r_x (16 values per interface, padded
 //         to 17 so that the lanes of a wavefront spread over the LDS banks: neighbouring interfaces and
-//         rows would otherwise sit a multiple of 128 bytes apart and hit the same banks)
+//         rows would otherwise sit a multiple of 128 bytes apart and hit the same banks; FP64 rows are
+//         padded by 2 more values, see nr_row)
 // then each thread takes one interface through the tangential reconstruction at the two Gauss
 // points, the equilibrium state and the flux (Sec. 2.3.3 Steps 1-3, Sec. 2.1-2.2).
 // Frame: slot 1 holds the normal momentum, slot 2 the tangential one (y-interfaces swap U and V).
@@ -400,7 +412,8 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   constexpr int NTH = flux_threads(TN, TT, DIM);  // 2D: two threads (Gauss points) per interface
   __shared__ T sW[4][R][C];
   __shared__ uint8_t sF[R][TN + 1];
-  __shared__ T sNR[R][TN][kNRS];
+  constexpr int NRW = nr_row<T, TN>();
+  __shared__ T sNR[R * NRW];
 
   const int p = find_prob(off, nprob, b);
   const ProbDev& P = probs[p];
@@ -532,7 +545,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
       }
     }
 #pragma unroll
-    for (int v = 0; v < 16; ++v) sNR[r][k][v] = out[v];
+    for (int v = 0; v < 16; ++v) sNR[r * NRW + k * kNRS + v] = out[v];
   }
   __syncthreads();
 
@@ -558,8 +571,8 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
     const T z[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      Wl[v] = sNR[0][k][v]; Wxl[v] = sNR[0][k][4 + v];
-      Wr[v] = sNR[0][k][8 + v]; Wxr[v] = sNR[0][k][12 + v];
+      Wl[v] = sNR[k * kNRS + v]; Wxl[v] = sNR[k * kNRS + 4 + v];
+      Wr[v] = sNR[k * kNRS + 8 + v]; Wxr[v] = sNR[k * kNRS + 12 + v];
     }
     gks_flux_gp<PRFIX>(Wl, Wxl, z, Wr, Wxr, z, fp, T(1), F, dF);
   } else {
