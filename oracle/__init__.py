@@ -50,7 +50,7 @@ class _Problem(C.Structure):
         ("bc", C.c_int32 * 4), ("recon", C.c_int32),
         ("gamma_hi", C.c_double), ("gamma_lo", C.c_double), ("weno_eps", C.c_double),
         ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32), ("positivity", C.c_int32),
-        ("bcd", _BcData * 4),
+        ("bcd", _BcData * 4), ("nz", C.c_int32), ("z0", C.c_double), ("z1", C.c_double), ("bcz", C.c_int32 * 2),
     ]
 
 
@@ -81,6 +81,10 @@ class Problem:
     tangential_flag_mode: int = 0
     positivity: int = 0  # 1: first-order fallback for non-physical reconstructed states
     bcd: tuple = ()  # BcData per side (x-low, x-high, y-low, y-high), read where bc is BC_PRESCRIBED
+    nz: int = 1      # 3D (dim = 3): cells along z on [z0, z1] and the kinds of the z sides
+    z0: float = 0.0
+    z1: float = 1.0
+    bcz: tuple = (BC_OUTFLOW, BC_OUTFLOW)
 
     @property
     def nc(self) -> int:
@@ -88,6 +92,8 @@ class Problem:
 
     @property
     def shape(self):
+        if self.dim == 3:
+            return (self.nc, self.nz, self.ny, self.nx)
         return (self.nc, self.nx) if self.dim == 1 else (self.nc, self.ny, self.nx)
 
     def c_struct(self) -> _Problem:
@@ -97,6 +103,8 @@ class Problem:
             if f.name == "bc":
                 arr = (C.c_int32 * 4)(*[int(b) for b in (list(v) + [0] * 4)[:4]])
                 s.bc = arr
+            elif f.name == "bcz":
+                s.bcz = (C.c_int32 * 2)(*[int(b) for b in v])
             elif f.name == "bcd":
                 for k, d in enumerate(list(v)[:4]):
                     if d is None:
@@ -138,6 +146,9 @@ def lib():
             "oracle_slope_solve": (None, [i32, vp, d, vp, vp]),
             "oracle_time_coeffs": (None, [d, d, vp]),
             "oracle_gp_flux": (None, [P, vp, vp, vp, vp, vp, vp, d, vp, vp, dp]),
+            "oracle_cfl_dt3": (d, [P, vp]),
+            "oracle_flags3": (i32, [P, vp, C.POINTER(vp)]),
+            "oracle_stage_fluxes3": (i32, [P, vp, d, C.POINTER(vp), C.POINTER(vp), i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -174,6 +185,34 @@ def flags(prob: Problem, W, t: float = 0.0):
         raise OracleError(rc)
     shp = (prob.nx,) if prob.dim == 1 else (prob.ny, prob.nx)
     return fx.reshape(shp), (fy.reshape(shp) if prob.dim == 2 else None)
+
+
+def flags3(prob: Problem, W):
+    """Widened troubled-cell flags of every cell of a 3D problem, per direction: (fx, fy, fz), [nz][ny][nx]."""
+    W = _f64(W)
+    ps = prob.c_struct()
+    f = [np.zeros((prob.nz, prob.ny, prob.nx), np.uint8) for _ in range(3)]
+    arr = (C.c_void_p * 3)(*[x.ctypes.data for x in f])
+    rc = lib().oracle_flags3(C.byref(ps), _ptr(W), arr)
+    if rc:
+        raise OracleError(rc)
+    return tuple(f)
+
+
+def stage_fluxes3(prob: Problem, W, dt: float, nthreads: int = 1):
+    """F and dF/dt of a 3D state at every face: ((Fx, Gx), (Fy, Gy), (Fz, Gz)); Fx [5][nz][ny][nx+1], ..."""
+    W = _f64(W)
+    ps = prob.c_struct()
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    shapes = [(5, nz, ny, nx + 1), (5, nz, ny + 1, nx), (5, nz + 1, ny, nx)]
+    F = [np.zeros(sh) for sh in shapes]
+    G = [np.zeros(sh) for sh in shapes]
+    fa = (C.c_void_p * 3)(*[x.ctypes.data for x in F])
+    ga = (C.c_void_p * 3)(*[x.ctypes.data for x in G])
+    rc = lib().oracle_stage_fluxes3(C.byref(ps), _ptr(W), float(dt), fa, ga, int(nthreads))
+    if rc:
+        raise OracleError(rc)
+    return tuple(zip(F, G))
 
 
 def cfl_dt(prob: Problem, W) -> float:

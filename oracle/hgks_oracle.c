@@ -1037,7 +1037,10 @@ static void update_cells(const oracle_problem* p, const double* W, const double*
       }
 }
 
+double oracle_cfl_dt3(const oracle_problem* p, const double* W);
+
 double oracle_cfl_dt(const oracle_problem* p, const double* W) {
+  if (p->dim == 3) return oracle_cfl_dt3(p, W);
   /* dt = CFL * min over cells of min(h/(|U| + c), h^2/(4 nu)), nu = mu/rho, h = min(dx, dy) */
   int nc = p->dim + 2;
   size_t ncell = (size_t)p->nx * p->ny;
@@ -1096,9 +1099,12 @@ int oracle_stage_fluxes(const oracle_problem* p, const double* W, double t, doub
   return ORACLE_OK;
 }
 
+static int step3(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken, int nthreads);
+
 int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken,
                 int nthreads) {
   oracle_init();
+  if (p->dim == 3) return step3(p, W, t, t_end, dt_taken, nthreads < 1 ? 1 : nthreads);
   int rc = check_problem(p);
   if (rc) return rc;
   if (nthreads < 1) nthreads = 1;
@@ -1296,4 +1302,713 @@ void oracle_gp_flux(const oracle_problem* p, const double* Wl, const double* Wxl
   params pp;
   make_params(p, &pp);
   gp_flux(&pp, Wl, Wxl, Wyl, Wr, Wxr, Wyr, dt, Fdt, Fdt2, tau_out);
+}
+
+/* ======================================================================== */
+/* 8. Three dimensions                                                       */
+/* ======================================================================== */
+/* The paper develops the scheme in 1D and 2D and states that the 3D extension is direct. It is taken
+ * here as: the same hybrid reconstruction along the normal of each face (its cell averages give face
+ * averages), then along the first and then the second tangential direction to the 2 x 2 tensor
+ * Gauss-Legendre points of the face (weights 1/4), each step flagged by the side cell's troubled flag
+ * in the direction of that step and, when flagged, WENO-AO in the characteristic variables of the state
+ * it starts from; at each point the gas-kinetic flux of Sec. 2.1 with three velocity components
+ * (u normal, v and w tangential) and K = (5 - 3 gamma)/(gamma - 1) internal degrees of freedom.
+ * Euler equations, or Navier-Stokes with Pr = 1. States: W[c][k][j][i], c in (rho, rho U, rho V,
+ * rho W, rho E). */
+
+#define NC3 5
+
+typedef struct {
+  double rho, U, V, Wv, lam;
+  double Mu[NMOM], Mh[NMOM], Mv[NMOM], Mw[NMOM], Mx[4];
+} maxw3;
+
+static void maxw3_from_W(double K, double gamma, const double* W, int side, maxw3* g) {
+  g->rho = W[0];
+  g->U = W[1] / W[0];
+  g->V = W[2] / W[0];
+  g->Wv = W[3] / W[0];
+  double p = (gamma - 1.0) * (W[4] - 0.5 * W[0] * (g->U * g->U + g->V * g->V + g->Wv * g->Wv));
+  g->lam = W[0] / (2.0 * p);
+  maxw m2;
+  maxw_moments(g->U, g->V, g->lam, K, side, &m2);  /* u (and half-line u) and v moments, xi^2 */
+  memcpy(g->Mu, m2.Mu, sizeof g->Mu);
+  memcpy(g->Mh, m2.Mh, sizeof g->Mh);
+  memcpy(g->Mv, m2.Mv, sizeof g->Mv);
+  memcpy(g->Mx, m2.Mx, sizeof g->Mx);
+  maxw m3;
+  maxw_moments(g->Wv, 0.0, g->lam, K, 0, &m3);  /* w moments: the same recurrence about W */
+  memcpy(g->Mw, m3.Mu, sizeof g->Mw);
+}
+
+/* coef * u^i v^j w^l (xi^2)^k */
+typedef struct {
+  double c;
+  int i, j, l, k;
+} term3;
+typedef struct {
+  int n;
+  term3 t[96];
+} poly3;
+
+static void p3_push(poly3* p, double c, int i, int j, int l, int k) {
+  p->t[p->n].c = c;
+  p->t[p->n].i = i;
+  p->t[p->n].j = j;
+  p->t[p->n].l = l;
+  p->t[p->n].k = k;
+  p->n++;
+}
+static void p3_mono(poly3* p, int i, int j, int l) {
+  p->n = 0;
+  p3_push(p, 1.0, i, j, l, 0);
+}
+
+/* psi: (1, u, v, w, (u^2 + v^2 + w^2 + xi^2)/2) */
+static void psi3(int alpha, poly3* p) {
+  p->n = 0;
+  if (alpha < 4) {
+    p3_push(p, 1.0, alpha == 1, alpha == 2, alpha == 3, 0);
+    return;
+  }
+  p3_push(p, 0.5, 2, 0, 0, 0);
+  p3_push(p, 0.5, 0, 2, 0, 0);
+  p3_push(p, 0.5, 0, 0, 2, 0);
+  p3_push(p, 0.5, 0, 0, 0, 1);
+}
+
+static void a3_poly(const double* a, poly3* p) {
+  poly3 ps;
+  p->n = 0;
+  for (int al = 0; al < NC3; ++al) {
+    psi3(al, &ps);
+    for (int s = 0; s < ps.n; ++s) p3_push(p, a[al] * ps.t[s].c, ps.t[s].i, ps.t[s].j, ps.t[s].l, ps.t[s].k);
+  }
+}
+
+static double mom3d(const maxw3* g, int half, int i, int j, int l, int k) {
+  return (half ? g->Mh[i] : g->Mu[i]) * g->Mv[j] * g->Mw[l] * g->Mx[k];
+}
+
+/* out[alpha] = < A B psi_alpha > of the normalised Maxwellian g (half: over its half line) */
+static void momvec3(const poly3* A, const poly3* B, const maxw3* g, int half, double* out) {
+  poly3 ps;
+  for (int al = 0; al < NC3; ++al) {
+    psi3(al, &ps);
+    double s = 0.0;
+    for (int a = 0; a < A->n; ++a)
+      for (int b = 0; b < B->n; ++b)
+        for (int r = 0; r < ps.n; ++r) {
+          const term3 *x = &A->t[a], *y = &B->t[b], *z = &ps.t[r];
+          s += x->c * y->c * z->c * mom3d(g, half, x->i + y->i + z->i, x->j + y->j + z->j, x->l + y->l + z->l,
+                                          x->k + y->k + z->k);
+        }
+    out[al] = s;
+  }
+}
+
+/* <a psi> = b with the 5 x 5 moment matrix <psi_alpha psi_beta> of g */
+static void solve_slope3(const maxw3* g, const double* b, double* a) {
+  double M[25], col[NC3];
+  poly3 one, ps;
+  p3_mono(&one, 0, 0, 0);
+  for (int be = 0; be < NC3; ++be) {
+    psi3(be, &ps);
+    momvec3(&ps, &one, g, 0, col);
+    for (int al = 0; al < NC3; ++al) M[al * NC3 + be] = col[al];
+  }
+  lin_solve(NC3, M, b, a);
+}
+
+/* Flux of Eq. (equ10) integrated over [0, dt] (Fd) and [0, dt/2] (Fh) at one point, frame components
+ * (rho, normal, first and second tangential momentum, energy); Wn, Wa, Wb: normal and tangential
+ * derivatives of each side's reconstructed state. */
+static void gp_flux3(const params* pp, const double* Wl, const double* Wnl, const double* Wal, const double* Wbl,
+                     const double* Wr, const double* Wnr, const double* War, const double* Wbr, double dt,
+                     double* Fd, double* Fh) {
+  const double* Ws[2] = {Wl, Wr};
+  const double* Dn[2] = {Wnl, Wnr};
+  const double* Da[2] = {Wal, War};
+  const double* Db[2] = {Wbl, Wbr};
+  poly3 one, pu, pv, pw, puu, puv, puw;
+  p3_mono(&one, 0, 0, 0);
+  p3_mono(&pu, 1, 0, 0);
+  p3_mono(&pv, 0, 1, 0);
+  p3_mono(&pw, 0, 0, 1);
+  p3_mono(&puu, 2, 0, 0);
+  p3_mono(&puv, 1, 1, 0);
+  p3_mono(&puw, 1, 0, 1);
+  double Wc[NC3] = {0}, Wnc[NC3] = {0}, Wac[NC3] = {0}, Wbc[NC3] = {0};
+  double M4a[NC3] = {0}, M4b[NC3] = {0}, M5[NC3] = {0};
+  double t1[NC3], t2[NC3], t3[NC3], b[NC3];
+  double pside[2];
+  for (int s = 0; s < 2; ++s) {
+    maxw3 g;
+    maxw3_from_W(pp->K, pp->gamma, Ws[s], s == 0 ? +1 : -1, &g); /* g_l over u > 0, g_r over u < 0 */
+    pside[s] = g.rho / (2.0 * g.lam);
+    double an[NC3], aa[NC3], ab[NC3], A[NC3];
+    for (int c = 0; c < NC3; ++c) b[c] = Dn[s][c] / g.rho;
+    solve_slope3(&g, b, an);
+    for (int c = 0; c < NC3; ++c) b[c] = Da[s][c] / g.rho;
+    solve_slope3(&g, b, aa);
+    for (int c = 0; c < NC3; ++c) b[c] = Db[s][c] / g.rho;
+    solve_slope3(&g, b, ab);
+    poly3 pan, paa, pab, pA;
+    a3_poly(an, &pan);
+    a3_poly(aa, &paa);
+    a3_poly(ab, &pab);
+    /* compatibility: <a_n u + a_a v + a_b w + A> = 0 */
+    momvec3(&pan, &pu, &g, 0, t1);
+    momvec3(&paa, &pv, &g, 0, t2);
+    momvec3(&pab, &pw, &g, 0, t3);
+    for (int c = 0; c < NC3; ++c) b[c] = -(t1[c] + t2[c] + t3[c]);
+    solve_slope3(&g, b, A);
+    a3_poly(A, &pA);
+    /* equilibrium state and its slopes, Eq. (equ46)-(equ47) */
+    momvec3(&one, &one, &g, 1, t1);
+    for (int c = 0; c < NC3; ++c) Wc[c] += g.rho * t1[c];
+    momvec3(&pan, &one, &g, 1, t1);
+    for (int c = 0; c < NC3; ++c) Wnc[c] += g.rho * t1[c];
+    momvec3(&paa, &one, &g, 1, t1);
+    for (int c = 0; c < NC3; ++c) Wac[c] += g.rho * t1[c];
+    momvec3(&pab, &one, &g, 1, t1);
+    for (int c = 0; c < NC3; ++c) Wbc[c] += g.rho * t1[c];
+    /* free transport terms of Eq. (equ10) */
+    momvec3(&one, &pu, &g, 1, t1);
+    for (int c = 0; c < NC3; ++c) M4a[c] += g.rho * t1[c];
+    momvec3(&pA, &pu, &g, 1, t1);
+    for (int c = 0; c < NC3; ++c) M4b[c] += g.rho * t1[c];
+    momvec3(&pan, &puu, &g, 1, t1);
+    momvec3(&paa, &puv, &g, 1, t2);
+    momvec3(&pab, &puw, &g, 1, t3);
+    for (int c = 0; c < NC3; ++c) M5[c] += g.rho * (t1[c] + t2[c] + t3[c]);
+  }
+  maxw3 g0;
+  maxw3_from_W(pp->K, pp->gamma, Wc, 0, &g0);
+  double a0[NC3], b0[NC3], c0[NC3], A0[NC3];
+  for (int c = 0; c < NC3; ++c) b[c] = Wnc[c] / g0.rho;
+  solve_slope3(&g0, b, a0);
+  for (int c = 0; c < NC3; ++c) b[c] = Wac[c] / g0.rho;
+  solve_slope3(&g0, b, b0);
+  for (int c = 0; c < NC3; ++c) b[c] = Wbc[c] / g0.rho;
+  solve_slope3(&g0, b, c0);
+  poly3 pa0, pb0, pc0, pA0;
+  a3_poly(a0, &pa0);
+  a3_poly(b0, &pb0);
+  a3_poly(c0, &pc0);
+  momvec3(&pa0, &pu, &g0, 0, t1);
+  momvec3(&pb0, &pv, &g0, 0, t2);
+  momvec3(&pc0, &pw, &g0, 0, t3);
+  for (int c = 0; c < NC3; ++c) b[c] = -(t1[c] + t2[c] + t3[c]);
+  solve_slope3(&g0, b, A0);
+  a3_poly(A0, &pA0);
+  double M1[NC3], M2[NC3], M3[NC3];
+  momvec3(&one, &pu, &g0, 0, M1);
+  momvec3(&pa0, &puu, &g0, 0, t1);
+  momvec3(&pb0, &puv, &g0, 0, t2);
+  momvec3(&pc0, &puw, &g0, 0, t3);
+  momvec3(&pA0, &pu, &g0, 0, M3);
+  for (int c = 0; c < NC3; ++c) {
+    M1[c] *= g0.rho;
+    M2[c] = g0.rho * (t1[c] + t2[c] + t3[c]);
+    M3[c] *= g0.rho;
+  }
+  double jump = fabs((pside[0] - pside[1]) / (pside[0] + pside[1]));
+  double p0 = g0.rho / (2.0 * g0.lam);
+  double tau = pp->ns ? pp->mu / p0 + pp->c2 * jump * dt : pp->c1 * dt + pp->c2 * jump * dt;
+  double deltas[2] = {dt, 0.5 * dt};
+  double* outs[2] = {Fd, Fh};
+  for (int m = 0; m < 2; ++m) {
+    double C[5];
+    time_coeffs(deltas[m], tau, C);
+    for (int c = 0; c < NC3; ++c)
+      outs[m][c] = C[0] * M1[c] + C[1] * M2[c] + C[2] * M3[c] + C[3] * (M4a[c] - tau * M4b[c]) - C[4] * M5[c];
+  }
+}
+
+/* Right eigenvectors of the 3D Euler flux Jacobian in frame slot dir (1: normal, 2, 3: tangential),
+ * state in frame components; columns: u_d - c, entropy, the two shear waves, u_d + c. */
+static void char_R3(int dir, const double* W, double gamma, double* R) {
+  double rho = W[0];
+  double u[3] = {W[1] / rho, W[2] / rho, W[3] / rho};
+  double q2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double p = (gamma - 1.0) * (W[4] - 0.5 * rho * q2);
+  double c = sqrt(gamma * p / rho);
+  double H = (W[4] + p) / rho;
+  int d = dir - 1;
+  memset(R, 0, sizeof(double) * 25);
+  R[0 * 5 + 0] = 1.0;
+  for (int m = 0; m < 3; ++m) R[(1 + m) * 5 + 0] = u[m] - (m == d ? c : 0.0);
+  R[4 * 5 + 0] = H - u[d] * c;
+  R[0 * 5 + 1] = 1.0;
+  for (int m = 0; m < 3; ++m) R[(1 + m) * 5 + 1] = u[m];
+  R[4 * 5 + 1] = 0.5 * q2;
+  int col = 2;
+  for (int m = 0; m < 3; ++m) {
+    if (m == d) continue;
+    R[(1 + m) * 5 + col] = 1.0;
+    R[4 * 5 + col] = u[m];
+    col++;
+  }
+  R[0 * 5 + 4] = 1.0;
+  for (int m = 0; m < 3; ++m) R[(1 + m) * 5 + 4] = u[m] + (m == d ? c : 0.0);
+  R[4 * 5 + 4] = H + u[d] * c;
+}
+
+/* 5-cell reconstruction of a 5-vector at xi (value and xi-derivative): linear quartic per component,
+ * or WENO-AO on R^{-1} q projected back with R. */
+static void recon5(const params* pp, const double q5[5][NC3], double xi, int flag, const double* R,
+                   const double* L, double* val, double* der) {
+  double q[5], c[5];
+  if (!flag) {
+    for (int cc = 0; cc < NC3; ++cc) {
+      for (int r = 0; r < 5; ++r) q[r] = q5[r][cc];
+      stencil_coeffs(3, q, c);
+      poly_eval(c, 4, xi, &val[cc], &der[cc]);
+    }
+    return;
+  }
+  double cv[NC3], cd[NC3];
+  for (int k = 0; k < NC3; ++k) {
+    for (int r = 0; r < 5; ++r) {
+      double s = 0.0;
+      for (int cc = 0; cc < NC3; ++cc) s += L[k * NC3 + cc] * q5[r][cc];
+      q[r] = s;
+    }
+    ao_eval(q, xi, pp->ghi, pp->glo, pp->eps, &cv[k], &cd[k]);
+  }
+  for (int cc = 0; cc < NC3; ++cc) {
+    double sv = 0.0, sd = 0.0;
+    for (int k = 0; k < NC3; ++k) {
+      sv += R[cc * NC3 + k] * cv[k];
+      sd += R[cc * NC3 + k] * cd[k];
+    }
+    val[cc] = sv;
+    der[cc] = sd;
+  }
+}
+
+/* padded 3D state G[c][k+NG][j+NG][i+NG]: x-sides on interior (j, k), then y-sides across the padded
+ * width in i (interior k), then z-sides across the padded i and j (corners follow the later side). */
+typedef struct {
+  int nx, ny, nz, px, py, pz;
+  double* G;
+} pad3;
+
+static double* g3(const pad3* g, int c, int k, int j, int i) {
+  return g->G + (((size_t)c * g->pz + (size_t)(k + NG)) * g->py + (size_t)(j + NG)) * g->px + (size_t)(i + NG);
+}
+
+static int mirror_src(int kind, int side, int idx, int n) {
+  if (kind == 0) return side ? idx - n : idx + n;
+  if (kind == 1) return side ? n - 1 : 0;
+  return side ? 2 * n - 1 - idx : -1 - idx;
+}
+
+static void pad_state3(const oracle_problem* p, const double* W, pad3* g) {
+  int nx = p->nx, ny = p->ny, nz = p->nz;
+  g->nx = nx; g->ny = ny; g->nz = nz;
+  g->px = nx + 2 * NG; g->py = ny + 2 * NG; g->pz = nz + 2 * NG;
+  g->G = (double*)malloc(sizeof(double) * NC3 * g->px * g->py * g->pz);
+  for (int c = 0; c < NC3; ++c)
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) *g3(g, c, k, j, i) = W[(((size_t)c * nz + k) * ny + j) * nx + i];
+  int kinds[3][2] = {{p->bc[0], p->bc[1]}, {p->bc[2], p->bc[3]}, {p->bcz[0], p->bcz[1]}};
+  for (int d = 0; d < 3; ++d) {
+    int n = d == 0 ? nx : d == 1 ? ny : nz;
+    /* ranges of the other two indices: interior for later directions, padded for earlier ones */
+    int lo[3] = {0, 0, 0}, hi[3] = {nx, ny, nz};
+    for (int e = 0; e < d; ++e) { lo[e] = -NG; hi[e] = (e == 0 ? nx : ny) + NG; }
+    for (int gk = 1; gk <= NG; ++gk)
+      for (int side = 0; side < 2; ++side) {
+        int idx = side ? n - 1 + gk : -gk;
+        int kind = kinds[d][side];
+        int src = mirror_src(kind, side, idx, n);
+        for (int a = (d == 0 ? lo[1] : lo[0]); a < (d == 0 ? hi[1] : hi[0]); ++a)
+          for (int b = (d == 2 ? lo[1] : lo[2]); b < (d == 2 ? hi[1] : hi[2]); ++b) {
+            /* (i, j, k) of the ghost and of its source */
+            int i, j, k, si, sj, sk;
+            if (d == 0) { j = a; k = b; i = idx; si = src; sj = j; sk = k; }
+            else if (d == 1) { i = a; k = b; j = idx; si = i; sj = src; sk = k; }
+            else { i = a; j = b; k = idx; si = i; sj = j; sk = src; }
+            for (int c = 0; c < NC3; ++c) {
+              double v = *g3(g, c, sk, sj, si);
+              if ((kind == 2 && c == 1 + d) || (kind == 3 && c >= 1 && c <= 3)) v = -v;
+              *g3(g, c, k, j, i) = v;
+            }
+          }
+      }
+  }
+}
+
+/* Frame of direction d: normal index n = axis d, first tangential a = axis (d+1)%3, second b = axis
+ * (d+2)%3, all padded by NG; components rotated to (rho, m_n, m_a, m_b, E). */
+typedef struct {
+  int nn, na, nb, pn, pa, pb;
+  double hn, ha, hb;
+  double* P;
+} frame3;
+
+static double* f3(const frame3* f, int c, int b, int a, int n) {
+  return f->P + (((size_t)c * f->pb + (size_t)(b + NG)) * f->pa + (size_t)(a + NG)) * f->pn + (size_t)(n + NG);
+}
+
+static void build_frame3(const oracle_problem* p, const pad3* g, int d, frame3* f) {
+  int N[3] = {p->nx, p->ny, p->nz};
+  double h[3] = {(p->x1 - p->x0) / p->nx, (p->y1 - p->y0) / p->ny, (p->z1 - p->z0) / p->nz};
+  int da = (d + 1) % 3, db = (d + 2) % 3;
+  f->nn = N[d]; f->na = N[da]; f->nb = N[db];
+  f->hn = h[d]; f->ha = h[da]; f->hb = h[db];
+  f->pn = f->nn + 2 * NG; f->pa = f->na + 2 * NG; f->pb = f->nb + 2 * NG;
+  f->P = (double*)malloc(sizeof(double) * NC3 * f->pn * f->pa * f->pb);
+  for (int b = -NG; b < f->nb + NG; ++b)
+    for (int a = -NG; a < f->na + NG; ++a)
+      for (int n = -NG; n < f->nn + NG; ++n) {
+        int ix[3];
+        ix[d] = n; ix[da] = a; ix[db] = b;
+        double v[NC3];
+        for (int c = 0; c < NC3; ++c) v[c] = *g3(g, c, ix[2], ix[1], ix[0]);
+        double m[3] = {v[1], v[2], v[3]};
+        v[1] = m[d]; v[2] = m[da]; v[3] = m[db];
+        for (int c = 0; c < NC3; ++c) *f3(f, c, b, a, n) = v[c];
+      }
+}
+
+/* troubled flag of padded cell (n, a, b) along frame axis ax (0 normal, 1 a, 2 b), widened: OR of the
+ * cell and its two neighbours along that axis, each an OR over the five components (Steps 1-4) */
+static int t3_cell(const frame3* f, const params* pp, int ax, int n, int a, int b) {
+  double q[5], xb, xh;
+  int st, T = 0;
+  double hh = ax == 0 ? f->hn : ax == 1 ? f->ha : f->hb;
+  for (int c = 0; c < NC3; ++c) {
+    for (int r = 0; r < 5; ++r) {
+      int o = r - 2;
+      q[r] = *f3(f, c, b + (ax == 2 ? o : 0), a + (ax == 1 ? o : 0), n + (ax == 0 ? o : 0));
+    }
+    T |= troubled_component(q, hh, pp->zeta1_mode, &xb, &xh, &st);
+  }
+  return T;
+}
+
+static int flag3(const frame3* f, const params* pp, int ax, int n, int a, int b) {
+  if (pp->recon == 1) return 1;
+  if (pp->recon == 2) return 0;
+  int F = 0;
+  for (int o = -1; o <= 1; ++o)
+    F |= t3_cell(f, pp, ax, n + (ax == 0 ? o : 0), a + (ax == 1 ? o : 0), b + (ax == 2 ? o : 0));
+  return F;
+}
+
+/* Fd, Fh: [c][b][a][n] (interfaces n = 0..nn) in frame components */
+static void frame_fluxes3(const frame3* f, const params* pp, double dt, double* Fd, double* Fh, int nthreads) {
+  int nn = f->nn, na = f->na, nb = f->nb;
+  int la = na + 4, lb = nb + 4;  /* line values on tangential rows -2..n+1 */
+  size_t lsz = (size_t)lb * la * (nn + 1);
+#define LV3(kind, c, b, a, k) LV[(((size_t)(kind) * NC3 + (c)) * lsz) + (((size_t)((b) + 2) * la + (size_t)((a) + 2)) * (nn + 1)) + (k)]
+  double* LV = (double*)malloc(sizeof(double) * 4 * NC3 * lsz);
+  /* normal reconstruction of every line (Sec. 2.3.1 applied along the face normal) */
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(dynamic, 1)
+  for (int b = -2; b < nb + 2; ++b)
+    for (int a = -2; a < na + 2; ++a)
+      for (int k = 0; k <= nn; ++k) {
+        double q5[5][NC3], R[25], L[25], avg[NC3], val[NC3], der[NC3];
+        int fl = flag3(f, pp, 0, k - 1, a, b), fr = flag3(f, pp, 0, k, a, b);
+        if (fl || fr) {
+          for (int c = 0; c < NC3; ++c) avg[c] = 0.5 * (*f3(f, c, b, a, k - 1) + *f3(f, c, b, a, k));
+          char_R3(1, avg, pp->gamma, R);
+          mat_inverse(NC3, R, L);
+        }
+        for (int s = 0; s < 2; ++s) {
+          int cell = k - 1 + s;
+          for (int r = 0; r < 5; ++r)
+            for (int c = 0; c < NC3; ++c) q5[r][c] = *f3(f, c, b, a, cell - 2 + r);
+          recon5(pp, q5, s == 0 ? 0.5 : -0.5, s == 0 ? fl : fr, R, L, val, der);
+          for (int c = 0; c < NC3; ++c) {
+            LV3(2 * s, c, b, a, k) = val[c];
+            LV3(2 * s + 1, c, b, a, k) = der[c] / f->hn;
+          }
+        }
+      }
+  const double eta = 1.0 / (2.0 * sqrt(3.0));
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(dynamic, 1)
+  for (int b = 0; b < nb; ++b)
+    for (int a = 0; a < na; ++a)
+      for (int k = 0; k <= nn; ++k) {
+        double sumd[NC3] = {0}, sumh[NC3] = {0};
+        for (int m1 = 0; m1 < 2; ++m1)
+          for (int m2 = 0; m2 < 2; ++m2) {
+            double x1 = m1 ? eta : -eta, x2 = m2 ? eta : -eta;
+            double Wp[2][NC3], Wn[2][NC3], Wa[2][NC3], Wb[2][NC3];
+            for (int s = 0; s < 2; ++s) {
+              int cell = k - 1 + s;
+              /* step 1: along a, on the five b-rows, at x1 */
+              double V1[5][NC3], D1[5][NC3], N1[5][NC3];
+              for (int r2 = 0; r2 < 5; ++r2) {
+                int bb = b - 2 + r2;
+                int fa = flag3(f, pp, 1, cell, a, bb);
+                double R[25], L[25], own[NC3], q5[5][NC3], val[NC3], der[NC3];
+                if (fa) {
+                  for (int c = 0; c < NC3; ++c) own[c] = LV3(2 * s, c, bb, a, k);
+                  char_R3(2, own, pp->gamma, R);
+                  mat_inverse(NC3, R, L);
+                }
+                for (int r = 0; r < 5; ++r)
+                  for (int c = 0; c < NC3; ++c) q5[r][c] = LV3(2 * s, c, bb, a - 2 + r, k);
+                recon5(pp, q5, x1, fa, R, L, val, der);
+                for (int c = 0; c < NC3; ++c) { V1[r2][c] = val[c]; D1[r2][c] = der[c] / f->ha; }
+                for (int r = 0; r < 5; ++r)
+                  for (int c = 0; c < NC3; ++c) q5[r][c] = LV3(2 * s + 1, c, bb, a - 2 + r, k);
+                recon5(pp, q5, x1, fa, R, L, val, der);
+                for (int c = 0; c < NC3; ++c) N1[r2][c] = val[c];
+              }
+              /* step 2: along b at x2 */
+              int fb = flag3(f, pp, 2, cell, a, b);
+              double R[25], L[25], val[NC3], der[NC3];
+              if (fb) {
+                char_R3(3, V1[2], pp->gamma, R);
+                mat_inverse(NC3, R, L);
+              }
+              recon5(pp, (const double(*)[NC3])V1, x2, fb, R, L, val, der);
+              for (int c = 0; c < NC3; ++c) { Wp[s][c] = val[c]; Wb[s][c] = der[c] / f->hb; }
+              recon5(pp, (const double(*)[NC3])D1, x2, fb, R, L, val, der);
+              for (int c = 0; c < NC3; ++c) Wa[s][c] = val[c];
+              recon5(pp, (const double(*)[NC3])N1, x2, fb, R, L, val, der);
+              for (int c = 0; c < NC3; ++c) Wn[s][c] = val[c];
+            }
+            double Fdg[NC3], Fhg[NC3];
+            gp_flux3(pp, Wp[0], Wn[0], Wa[0], Wb[0], Wp[1], Wn[1], Wa[1], Wb[1], dt, Fdg, Fhg);
+            for (int c = 0; c < NC3; ++c) {
+              sumd[c] += 0.25 * Fdg[c];
+              sumh[c] += 0.25 * Fhg[c];
+            }
+          }
+        for (int c = 0; c < NC3; ++c) {
+          size_t o = (((size_t)c * nb + b) * na + a) * (nn + 1) + k;
+          Fd[o] = sumd[c];
+          Fh[o] = sumh[c];
+        }
+      }
+#undef LV3
+  free(LV);
+}
+
+/* time-integrated fluxes of the three directions in grid components:
+ * x [5][nz][ny][nx+1], y [5][nz][ny+1][nx], z [5][nz+1][ny][nx] */
+static void all_fluxes3(const oracle_problem* p, const params* pp, const double* W, double dt, double* Fd[3],
+                        double* Fh[3], int nthreads) {
+  pad3 g;
+  pad_state3(p, W, &g);
+  int N[3] = {p->nx, p->ny, p->nz};
+  for (int d = 0; d < 3; ++d) {
+    frame3 f;
+    build_frame3(p, &g, d, &f);
+    int da = (d + 1) % 3, db = (d + 2) % 3;
+    size_t nf = (size_t)NC3 * f.nb * f.na * (f.nn + 1);
+    double* td = (double*)malloc(sizeof(double) * nf);
+    double* th = (double*)malloc(sizeof(double) * nf);
+    frame_fluxes3(&f, pp, dt, td, th, nthreads);
+    free(f.P);
+    int M[3] = {N[0], N[1], N[2]};
+    M[d] += 1;
+    for (int c = 0; c < NC3; ++c) {
+      int cs = c;  /* frame slot of grid component c */
+      if (c >= 1 && c <= 3) {
+        int axis = c - 1;
+        cs = axis == d ? 1 : axis == da ? 2 : 3;
+      }
+      for (int b = 0; b < f.nb; ++b)
+        for (int a = 0; a < f.na; ++a)
+          for (int n = 0; n <= f.nn; ++n) {
+            int ix[3];
+            ix[d] = n; ix[da] = a; ix[db] = b;
+            size_t go = (((size_t)c * M[2] + ix[2]) * M[1] + ix[1]) * M[0] + ix[0];
+            size_t fo = (((size_t)cs * f.nb + b) * f.na + a) * (f.nn + 1) + n;
+            Fd[d][go] = td[fo];
+            Fh[d][go] = th[fo];
+          }
+    }
+    free(td);
+    free(th);
+  }
+  free(g.G);
+}
+
+static int admissible3(const oracle_problem* p, const double* W, size_t s) {
+  size_t nc = (size_t)p->nx * p->ny * p->nz;
+  double rho = W[s], mx = W[nc + s], my = W[2 * nc + s], mz = W[3 * nc + s], E = W[4 * nc + s];
+  double pr = (p->gamma - 1.0) * (E - 0.5 * (mx * mx + my * my + mz * mz) / rho);
+  return rho > 0.0 && pr > 0.0 && isfinite(E);
+}
+
+double oracle_cfl_dt3(const oracle_problem* p, const double* W) {
+  size_t nc = (size_t)p->nx * p->ny * p->nz;
+  double h = fmin(fmin((p->x1 - p->x0) / p->nx, (p->y1 - p->y0) / p->ny), (p->z1 - p->z0) / p->nz);
+  double qmin = INFINITY;
+  for (size_t s = 0; s < nc; ++s) {
+    double rho = W[s], U = W[nc + s] / rho, V = W[2 * nc + s] / rho, Z = W[3 * nc + s] / rho;
+    double pr = (p->gamma - 1.0) * (W[4 * nc + s] - 0.5 * rho * (U * U + V * V + Z * Z));
+    double c = sqrt(p->gamma * pr / rho);
+    double q = h / (sqrt(U * U + V * V + Z * Z) + c);
+    if (p->eqn == 1) q = fmin(q, (h * h) / (4.0 * (p->mu / rho)));
+    qmin = fmin(qmin, q);
+  }
+  return p->cfl * qmin;
+}
+
+static int check_problem3(const oracle_problem* p) {
+  if (p->nx < 5 || p->ny < 5 || p->nz < 5) return ORACLE_EINVAL;
+  if (!(p->gamma > 1.0) || !(p->x1 > p->x0) || !(p->y1 > p->y0) || !(p->z1 > p->z0)) return ORACLE_EINVAL;
+  if (p->eqn == 1 && !(p->Pr == 1.0 && p->mu >= 0.0)) return ORACLE_EINVAL;
+  if (p->positivity != 0) return ORACLE_EINVAL;
+  int k[6] = {p->bc[0], p->bc[1], p->bc[2], p->bc[3], p->bcz[0], p->bcz[1]};
+  for (int s = 0; s < 6; ++s)
+    if (k[s] < 0 || k[s] > 3) return ORACLE_EINVAL;
+  for (int s = 0; s < 6; s += 2)
+    if ((k[s] == 0) != (k[s + 1] == 0)) return ORACLE_EINVAL;
+  return ORACLE_OK;
+}
+
+static void make_params3(const oracle_problem* p, params* pp) {
+  make_params(p, pp);
+  pp->dim = 3;
+  pp->nc = NC3;
+  pp->K = (5.0 - 3.0 * p->gamma) / (p->gamma - 1.0);
+}
+
+int oracle_stage_fluxes3(const oracle_problem* p, const double* W, double dt, double* F[3], double* G[3],
+                         int nthreads) {
+  oracle_init();
+  int rc = check_problem3(p);
+  if (rc) return rc;
+  params pp;
+  make_params3(p, &pp);
+  int N[3] = {p->nx, p->ny, p->nz};
+  double *Fd[3], *Fh[3];
+  size_t nf[3];
+  for (int d = 0; d < 3; ++d) {
+    nf[d] = (size_t)NC3 * (N[0] + (d == 0)) * (N[1] + (d == 1)) * (N[2] + (d == 2));
+    Fd[d] = (double*)malloc(sizeof(double) * nf[d]);
+    Fh[d] = (double*)malloc(sizeof(double) * nf[d]);
+  }
+  all_fluxes3(p, &pp, W, dt, Fd, Fh, nthreads);
+  for (int d = 0; d < 3; ++d) {
+    for (size_t s = 0; s < nf[d]; ++s) {
+      F[d][s] = (4.0 * Fh[d][s] - Fd[d][s]) / dt;
+      G[d][s] = 4.0 * (Fd[d][s] - 2.0 * Fh[d][s]) / (dt * dt);
+    }
+    free(Fd[d]);
+    free(Fh[d]);
+  }
+  return ORACLE_OK;
+}
+
+int oracle_flags3(const oracle_problem* p, const double* W, uint8_t* f[3]) {
+  oracle_init();
+  int rc = check_problem3(p);
+  if (rc) return rc;
+  params pp;
+  make_params3(p, &pp);
+  pad3 g;
+  pad_state3(p, W, &g);
+  for (int d = 0; d < 3; ++d) {
+    frame3 fr;
+    build_frame3(p, &g, d, &fr);
+    int da = (d + 1) % 3, db = (d + 2) % 3;
+    for (int b = 0; b < fr.nb; ++b)
+      for (int a = 0; a < fr.na; ++a)
+        for (int n = 0; n < fr.nn; ++n) {
+          int ix[3];
+          ix[d] = n; ix[da] = a; ix[db] = b;
+          f[d][((size_t)ix[2] * p->ny + ix[1]) * p->nx + ix[0]] = (uint8_t)flag3(&fr, &pp, 0, n, a, b);
+        }
+    free(fr.P);
+  }
+  free(g.G);
+  return ORACLE_OK;
+}
+
+/* one S2O4 step (Sec. 2.2) of a 3D problem */
+static int step3(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken, int nthreads) {
+  int rc = check_problem3(p);
+  if (rc) return rc;
+  params pp;
+  make_params3(p, &pp);
+  if (dt_taken) *dt_taken = 0.0;
+  if (*t >= t_end) return ORACLE_OK;
+  double dt = (p->fixed_dt > 0.0) ? p->fixed_dt : oracle_cfl_dt3(p, W);
+  if (!(dt > 0.0) || !isfinite(dt)) return ORACLE_EDT;
+  double tnew;
+  if (*t + dt >= t_end) { dt = t_end - *t; tnew = t_end; }
+  else tnew = *t + dt;
+  int N[3] = {p->nx, p->ny, p->nz};
+  double h[3] = {(p->x1 - p->x0) / p->nx, (p->y1 - p->y0) / p->ny, (p->z1 - p->z0) / p->nz};
+  size_t ncell = (size_t)N[0] * N[1] * N[2];
+  double *Fd[3], *Fh[3], *F[3], *Gn[3];
+  size_t nf[3];
+  for (int d = 0; d < 3; ++d) {
+    nf[d] = (size_t)NC3 * (N[0] + (d == 0)) * (N[1] + (d == 1)) * (N[2] + (d == 2));
+    Fd[d] = (double*)malloc(sizeof(double) * nf[d]);
+    Fh[d] = (double*)malloc(sizeof(double) * nf[d]);
+    F[d] = (double*)malloc(sizeof(double) * nf[d]);
+    Gn[d] = (double*)malloc(sizeof(double) * nf[d]);
+  }
+  double* Ws = (double*)malloc(sizeof(double) * NC3 * ncell);
+  /* face index of the low face of cell (i,j,k) in direction d, and the stride to its high face */
+#define FACE(d, c, i, j, k) ((((size_t)(c) * (N[2] + ((d) == 2)) + (k)) * (N[1] + ((d) == 1)) + (j)) * (N[0] + ((d) == 0)) + (i))
+  all_fluxes3(p, &pp, W, dt, Fd, Fh, nthreads);
+  for (int d = 0; d < 3; ++d)
+    for (size_t s = 0; s < nf[d]; ++s) {
+      F[d][s] = (4.0 * Fh[d][s] - Fd[d][s]) / dt;
+      Gn[d][s] = 4.0 * (Fd[d][s] - 2.0 * Fh[d][s]) / (dt * dt);
+    }
+  /* W* = W^n - sum_d [F(dt/2)_hi - F(dt/2)_lo] / h_d */
+  for (int c = 0; c < NC3; ++c)
+    for (int k = 0; k < N[2]; ++k)
+      for (int j = 0; j < N[1]; ++j)
+        for (int i = 0; i < N[0]; ++i) {
+          double sdiv = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            size_t lo = FACE(d, c, i, j, k);
+            size_t hi = FACE(d, c, i + (d == 0), j + (d == 1), k + (d == 2));
+            sdiv += (Fh[d][hi] - Fh[d][lo]) / h[d];
+          }
+          size_t o = (size_t)c * ncell + ((size_t)k * N[1] + j) * N[0] + i;
+          Ws[o] = W[o] - sdiv;
+        }
+  for (size_t s = 0; s < ncell && !rc; ++s)
+    if (!admissible3(p, Ws, s)) rc = ORACLE_ENONPHYS;
+  if (!rc) {
+    all_fluxes3(p, &pp, Ws, dt, Fd, Fh, nthreads);
+    for (int d = 0; d < 3; ++d)
+      for (size_t s = 0; s < nf[d]; ++s) {
+        double Gs = 4.0 * (Fd[d][s] - 2.0 * Fh[d][s]) / (dt * dt);
+        F[d][s] = F[d][s] + dt / 6.0 * (Gn[d][s] + 2.0 * Gs);
+      }
+    for (int c = 0; c < NC3; ++c)
+      for (int k = 0; k < N[2]; ++k)
+        for (int j = 0; j < N[1]; ++j)
+          for (int i = 0; i < N[0]; ++i) {
+            double sdiv = 0.0;
+            for (int d = 0; d < 3; ++d) {
+              size_t lo = FACE(d, c, i, j, k);
+              size_t hi = FACE(d, c, i + (d == 0), j + (d == 1), k + (d == 2));
+              sdiv += (F[d][hi] - F[d][lo]) / h[d];
+            }
+            size_t o = (size_t)c * ncell + ((size_t)k * N[1] + j) * N[0] + i;
+            Ws[o] = W[o] - dt * sdiv;
+          }
+    for (size_t s = 0; s < ncell && !rc; ++s)
+      if (!admissible3(p, Ws, s)) rc = ORACLE_ENONPHYS;
+    if (!rc) {
+      memcpy(W, Ws, sizeof(double) * NC3 * ncell);
+      *t = tnew;
+      if (dt_taken) *dt_taken = dt;
+    }
+  }
+#undef FACE
+  for (int d = 0; d < 3; ++d) { free(Fd[d]); free(Fh[d]); free(F[d]); free(Gn[d]); }
+  free(Ws);
+  return rc;
 }

@@ -52,6 +52,9 @@ typedef struct {
                                    zero slopes; and the faces of a cell that the S2O4 update leaves
                                    non-physical take the one-stage flux F^n + dt/2 dF^n/dt */
   oracle_bc_data bcd[4];        /* per side, read where bc[side] == 4 */
+  int32_t nz;                   /* 3D (dim == 3): cells along z on [z0, z1], kinds of the z-low and z-high */
+  double z0, z1;                /* sides in bcz (0..3); bc[0..3] hold the x and y sides */
+  int32_t bcz[2];
 } oracle_problem;
 
 enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_ENONPHYS = -4, ORACLE_EDT = -5 };
@@ -69,6 +72,14 @@ int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, dou
  * Fx, Gx: [nc][ny][nx+1]; Fy, Gy: [nc][ny+1][nx] (2D only). */
 int oracle_stage_fluxes(const oracle_problem* p, const double* W, double t, double dt,
                         double* Fx, double* Gx, double* Fy, double* Gy, int nthreads);
+
+/* --- three dimensions: W[c][k][j][i], c in (rho, rho U, rho V, rho W, rho E) -------------- */
+/* oracle_step and oracle_cfl_dt take 3D problems too. Flags per direction: f[d][k][j][i]. Stage fluxes:
+ * F[0], G[0]: [5][nz][ny][nx+1]; F[1], G[1]: [5][nz][ny+1][nx]; F[2], G[2]: [5][nz+1][ny][nx]. */
+double oracle_cfl_dt3(const oracle_problem* p, const double* W);
+int oracle_flags3(const oracle_problem* p, const double* W, uint8_t* f[3]);
+int oracle_stage_fluxes3(const oracle_problem* p, const double* W, double dt, double* F[3], double* G[3],
+                         int nthreads);
 
 /* --- unit-level entry points (for tests) --------------------------------- */
 /* Sub-stencil polynomial k (0,1,2: quadratics on cells {-2..0},{-1..1},{0..2}; 3: quartic on

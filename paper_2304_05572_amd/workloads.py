@@ -67,6 +67,39 @@ def advection_2d(n: int, t: float = 0.0, gamma=GAMMA):
     return prim_to_cons(rho, one, one, one, gamma)
 
 
+def advection_3d(n: int, t: float = 0.0, gamma=GAMMA):
+    """rho = 1 + 0.2 sin(pi (x + y + z - 3 t)), U = V = W = 1, p = 1 on [0, 2]^3: exact cell averages,
+    W[c][k][j][i] with c in (rho, rho U, rho V, rho W, rho E)."""
+    h = 2.0 / n
+    xc = (np.arange(n) + 0.5) * h
+    Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
+    s = _sinc(np.pi * h / 2)
+    rho = 1.0 + 0.2 * np.sin(np.pi * (X + Y + Z - 3.0 * t)) * s ** 3
+    return prim_to_cons3(rho, np.ones_like(rho), np.ones_like(rho), np.ones_like(rho), np.ones_like(rho), gamma)
+
+
+def prim_to_cons3(rho, u, v, w, p, gamma=GAMMA):
+    rho = np.asarray(rho, np.float64)
+    E = np.asarray(p, np.float64) / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E])
+
+
+def embed_2d_in_3d(W2, nz: int, axis: int = 2):
+    """A 2D state W2[c][j][i] (c in rho, rho U, rho V, rho E) as a 3D state uniform along `axis`: axis 2 keeps
+    (x, y) -> (x, y); axis 0 maps (x, y) -> (y, z); axis 1 maps (x, y) -> (z, x). Returns W3[c][k][j][i]."""
+    rho, mu, mv, E = W2
+    zero = np.zeros_like(rho)
+    if axis == 2:   # uniform in z: W3[c][k][j][i] = W2[c][j][i]
+        comps = [rho, mu, mv, zero, E]
+        return np.stack([np.broadcast_to(q[None, :, :], (nz,) + rho.shape) for q in comps]).copy()
+    if axis == 0:   # uniform in x: 2D x -> y, 2D y -> z: W3[c][k][j][i] = W2[c][k][j]
+        comps = [rho, zero, mu, mv, E]
+        return np.stack([np.broadcast_to(q[:, :, None], rho.shape + (nz,)) for q in comps]).copy()
+    # uniform in y: 2D x -> z, 2D y -> x: W3[c][k][j][i] = W2[c][i][k]
+    comps = [rho, mv, zero, mu, E]
+    return np.stack([np.broadcast_to(q.T[:, None, :], (rho.shape[1], nz, rho.shape[0])) for q in comps]).copy()
+
+
 # ------------------------------------------------------------------ shock tubes
 def sod_1d(n: int, gamma=GAMMA):
     """Sod: (1, 0, 1) for x < 0.5, (0.125, 0, 0.1) for x > 0.5 on [0, 1] (x = 0.5 is a face for even n)."""
