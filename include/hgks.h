@@ -93,7 +93,12 @@ typedef enum { HGKS_FP64 = 0, HGKS_FP32_BULK = 1 } hgks_precision;
  * one block per tile or as a persistent grid of co-resident blocks. */
 #define HGKS_NUM_LAUNCH_CONFIGS 12
 
-/* One problem (Sec. 2 statement; parameters of Sec. 3). */
+/* One problem (Sec. 2 statement; parameters of Sec. 3). dim 1, 2 or 3. Three dimensions are the direct
+ * extension the paper names: the same hybrid reconstruction along the face normal, then along the two
+ * tangential directions in turn to the 2 x 2 Gauss points of each face, and the gas-kinetic flux with three
+ * velocity components; states W[c][k][j][i], c in (rho, rho U, rho V, rho W, rho E). 3D problems take the
+ * Euler equations or Navier-Stokes with Pr = 1, no prescribed-state sides, no positivity fallbacks and no
+ * compensated accumulation. */
 typedef struct {
   int32_t dim, nx, ny;          /* dim 1 or 2; ny must be 1 when dim == 1; nx, ny >= 5 */
   double x0, x1, y0, y1;        /* uniform Cartesian cells on [x0,x1] x [y0,y1] */
@@ -118,6 +123,9 @@ typedef struct {
                                    gives no positivity treatment; its double Mach reflection and blast wave
                                    do not run without one. */
   hgks_bc_data bcd[4];          /* per side, read where bc[side] == HGKS_BC_PRESCRIBED */
+  int32_t nz;                   /* dim == 3: cells along z on [z0, z1] (>= 5) and the kinds of the z-low and */
+  double z0, z1;                /* z-high sides in bcz (periodic, outflow, reflect or no-slip; bc[0..3] hold  */
+  int32_t bcz[2];               /* x and y). Ignored for dim 1 and 2. */
 } hgks_problem;
 
 typedef struct {
@@ -178,6 +186,12 @@ hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy);
 
 /* Interface flux F and its time derivative dF/dt of the current state at its current time for time
  * step dt, as used by the first stage (Sec. 2.2). Host arrays, FP64: Fx, Gx [nc][ny][nx+1]; Fy, Gy [nc][ny+1][nx] (2D). */
+/* Three-dimensional forms of the two calls above (dim == 3 only; the 2D forms reject 3D problems):
+ * flags [nz][ny][nx] per direction; Fx, Gx [5][nz][ny][nx+1]; Fy, Gy [5][nz][ny+1][nx]; Fz, Gz [5][nz+1][ny][nx]. */
+hgks_status hgks_debug_flags3(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy, uint8_t* fz);
+hgks_status hgks_debug_stage_fluxes3(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx, double* Fy,
+                                     double* Gy, double* Fz, double* Gz);
+
 hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx,
                                     double* Fy, double* Gy);
 

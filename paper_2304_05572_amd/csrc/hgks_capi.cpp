@@ -37,7 +37,7 @@ struct hgks {
   bool own_stream = false;
   std::vector<hgks_problem> hp;
   std::vector<ProbDev> pd;
-  std::vector<size_t> off_W, off_Ws, off_S, off_E, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_cnt;
+  std::vector<size_t> off_W, off_Ws, off_S, off_E, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_Fz, off_Gz, off_cnt;
   size_t off_probs = 0, off_ts = 0, off_tab = 0, off_qpart = 0, ws_bytes = 0;
   char* ws = nullptr;
   bool own_ws = false, ready = false;
@@ -60,7 +60,29 @@ struct hgks {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+static size_t cells_of(const hgks_problem& q) { return (size_t)q.nx * q.ny * (q.dim == 3 ? q.nz : 1); }
+
+static hgks_status validate3(const hgks_problem& p) {
+  if (p.nx < 5 || p.ny < 5 || p.nz < 5) return HGKS_EINVAL;
+  if (!(p.gamma > 1.0) || !(p.x1 > p.x0) || !(p.y1 > p.y0) || !(p.z1 > p.z0)) return HGKS_EINVAL;
+  if (!(p.cfl > 0.0) && !(p.fixed_dt > 0.0)) return HGKS_EINVAL;
+  if (p.eqn != HGKS_EULER && p.eqn != HGKS_NS) return HGKS_EINVAL;
+  if (p.eqn == HGKS_NS && !(p.Pr == 1.0 && p.mu >= 0.0)) return HGKS_EINVAL;  // no Prandtl correction in 3D
+  if (p.c1 < 0.0 || p.c2 < 0.0 || p.recon < 0 || p.recon > 2 || p.tangential_flag_mode != 0) return HGKS_EINVAL;
+  if (p.positivity != 0) return HGKS_EINVAL;
+  if (!(p.gamma_hi > 0.0 && p.gamma_hi < 1.0) || !(p.gamma_lo > 0.0 && p.gamma_lo < 1.0) || !(p.weno_eps > 0.0))
+    return HGKS_EINVAL;
+  const int k[6] = {p.bc[0], p.bc[1], p.bc[2], p.bc[3], p.bcz[0], p.bcz[1]};
+  for (int s = 0; s < 6; ++s)
+    if (k[s] < 0 || k[s] > HGKS_BC_NOSLIP_ADIABATIC) return HGKS_EINVAL;
+  for (int s = 0; s < 6; s += 2)
+    if ((k[s] == HGKS_BC_PERIODIC) != (k[s + 1] == HGKS_BC_PERIODIC)) return HGKS_EINVAL;
+  if ((size_t)p.nx * p.ny * p.nz > (size_t)1 << 28) return HGKS_EINVAL;
+  return HGKS_OK;
+}
+
 static hgks_status validate(const hgks_problem& p) {
+  if (p.dim == 3) return validate3(p);
   if (p.dim != 1 && p.dim != 2) return HGKS_EINVAL;
   if (p.nx < 5 || (p.dim == 2 && p.ny < 5) || (p.dim == 1 && p.ny != 1)) return HGKS_EINVAL;
   if (!(p.gamma > 1.0) || !(p.x1 > p.x0) || (p.dim == 2 && !(p.y1 > p.y0))) return HGKS_EINVAL;
@@ -99,10 +121,11 @@ static void plan(hgks* h) {
   const int np = h->nprob;
   h->off_W.resize(np); h->off_Ws.resize(np); h->off_S.resize(np); h->off_E.resize(np); h->off_flags.resize(np);
   h->off_Fx.resize(np); h->off_Gx.resize(np); h->off_Fy.resize(np); h->off_Gy.resize(np); h->off_cnt.resize(np);
+  h->off_Fz.resize(np); h->off_Gz.resize(np);
   for (int p = 0; p < np; ++p) {
     const hgks_problem& q = h->hp[p];
-    const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny;
-    const size_t state = nc * nx * ny * sizeof(double);
+    const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny, nz = (q.dim == 3) ? q.nz : 1;
+    const size_t state = nc * cells_of(q) * sizeof(double);
     h->off_W[p] = o; o = align256(o + state);
     h->off_Ws[p] = o; o = align256(o + state);
     h->off_S[p] = o; o = align256(o + state);
@@ -111,14 +134,20 @@ static void plan(hgks* h) {
     } else {
       h->off_E[p] = 0;
     }
-    h->off_flags[p] = o; o = align256(o + (nx + 4) * (q.dim == 2 ? ny + 4 : 1));
-    h->off_Fx[p] = o; o = align256(o + nc * ny * (nx + 1) * ts);
-    h->off_Gx[p] = o; o = align256(o + nc * ny * (nx + 1) * ts);
-    if (q.dim == 2) {
-      h->off_Fy[p] = o; o = align256(o + nc * (ny + 1) * nx * ts);
-      h->off_Gy[p] = o; o = align256(o + nc * (ny + 1) * nx * ts);
+    h->off_flags[p] = o; o = align256(o + (nx + 4) * (q.dim >= 2 ? ny + 4 : 1) * (q.dim == 3 ? nz + 4 : 1));
+    h->off_Fx[p] = o; o = align256(o + nc * nz * ny * (nx + 1) * ts);
+    h->off_Gx[p] = o; o = align256(o + nc * nz * ny * (nx + 1) * ts);
+    if (q.dim >= 2) {
+      h->off_Fy[p] = o; o = align256(o + nc * nz * (ny + 1) * nx * ts);
+      h->off_Gy[p] = o; o = align256(o + nc * nz * (ny + 1) * nx * ts);
     } else {
       h->off_Fy[p] = h->off_Gy[p] = 0;
+    }
+    if (q.dim == 3) {
+      h->off_Fz[p] = o; o = align256(o + nc * (nz + 1) * ny * nx * ts);
+      h->off_Gz[p] = o; o = align256(o + nc * (nz + 1) * ny * nx * ts);
+    } else {
+      h->off_Fz[p] = h->off_Gz[p] = 0;
     }
     h->off_cnt[p] = o; o = align256(o + 2 * sizeof(int));
   }
@@ -127,7 +156,7 @@ static void plan(hgks* h) {
   // tables: cell, ext, and one flux table per tile shape, each nprob+1 ints
   h->off_tab = o; o = align256(o + (size_t)(2 + kNumTiles) * (np + 1) * sizeof(int));
   long cell_blocks = 0;
-  for (int p = 0; p < np; ++p) cell_blocks += ((long)h->hp[p].nx * h->hp[p].ny + 255) / 256;
+  for (int p = 0; p < np; ++p) cell_blocks += ((long)cells_of(h->hp[p]) + 255) / 256;
   h->off_qpart = o; o = align256(o + (size_t)cell_blocks * sizeof(double));
   h->ws_bytes = o;
   // prefix sums
@@ -136,13 +165,15 @@ static void plan(hgks* h) {
   for (int t = 0; t < kNumTiles; ++t) h->tab_flux[t].assign(np + 1, 0);
   for (int p = 0; p < np; ++p) {
     const hgks_problem& q = h->hp[p];
-    const long cells = (long)q.nx * q.ny;
-    const long ext = (long)(q.nx + 4) * (q.dim == 2 ? q.ny + 4 : 1);
+    const long cells = (long)cells_of(q);
+    const long ext = (long)(q.nx + 4) * (q.dim >= 2 ? q.ny + 4 : 1) * (q.dim == 3 ? q.nz + 4 : 1);
     h->tab_cell[p + 1] = h->tab_cell[p] + (int)((cells + 255) / 256);
     // flag blocks: 32 x 16 tiles of the extended range in 2D, runs of 256 cells in 1D
     const long fblocks = (q.dim == 2) ? (long)((q.nx + 4 + 31) / 32) * ((q.ny + 4 + 15) / 16) : (ext + 255) / 256;
     h->tab_ext[p + 1] = h->tab_ext[p] + (int)fblocks;
-    for (int t = 0; t < kNumTiles; ++t) h->tab_flux[t][p + 1] = h->tab_flux[t][p] + flux_tiles(q.dim, q.nx, q.ny, t);
+    for (int t = 0; t < kNumTiles; ++t)
+      h->tab_flux[t][p + 1] =
+          h->tab_flux[t][p] + (q.dim == 3 ? flux_tiles3(q.nx, q.ny, q.nz) : flux_tiles(q.dim, q.nx, q.ny, t));
   }
 }
 
@@ -209,14 +240,20 @@ static hgks_status materialise(hgks* h) {
       B.rest = q.bcd[s].rest;
     }
     d.recon = q.recon; d.zeta1_mode = q.zeta1_mode; d.positivity = q.positivity;
-    d.x0 = q.x0; d.y0 = q.dim == 2 ? q.y0 : 0.0;
+    d.x0 = q.x0; d.y0 = q.dim >= 2 ? q.y0 : 0.0;
+    d.nz = q.dim == 3 ? q.nz : 1;
+    d.bcz[0] = q.dim == 3 ? q.bcz[0] : 0;
+    d.bcz[1] = q.dim == 3 ? q.bcz[1] : 0;
+    d.dz = q.dim == 3 ? (q.z1 - q.z0) / q.nz : 1.0;
+    d.ihz = 1.0 / d.dz;
     d.dx = (q.x1 - q.x0) / q.nx;
-    d.dy = q.dim == 2 ? (q.y1 - q.y0) / q.ny : 1.0;
-    d.h = q.dim == 2 ? std::min(d.dx, d.dy) : d.dx;
+    d.dy = q.dim >= 2 ? (q.y1 - q.y0) / q.ny : 1.0;
+    d.h = q.dim == 2 ? std::min(d.dx, d.dy) : q.dim == 3 ? std::min(std::min(d.dx, d.dy), d.dz) : d.dx;
     d.gamma = q.gamma;
     // internal degrees of freedom of the 2D model (K + 2 = 2/(gamma-1)); a 1D problem runs as the 2D
     // model with V = 0, which has the same u-moments as the 1D model with K + 1 = 2/(gamma-1)
     d.K = (4.0 - 2.0 * q.gamma) / (q.gamma - 1.0);
+    if (q.dim == 3) d.K = (5.0 - 3.0 * q.gamma) / (q.gamma - 1.0);  // K + 3 = 2/(gamma-1) with three velocities
     d.mu = q.mu; d.Pr = q.Pr; d.c1 = q.c1; d.c2 = q.c2;
     d.Kp2 = d.K + 2.0;
     d.iKp2 = 1.0 / d.Kp2;
@@ -232,8 +269,10 @@ static hgks_status materialise(hgks* h) {
     d.flags = reinterpret_cast<uint8_t*>(h->ws + h->off_flags[p]);
     d.Fx = h->ws + h->off_Fx[p];
     d.Gx = h->ws + h->off_Gx[p];
-    d.Fy = q.dim == 2 ? h->ws + h->off_Fy[p] : nullptr;
-    d.Gy = q.dim == 2 ? h->ws + h->off_Gy[p] : nullptr;
+    d.Fy = q.dim >= 2 ? h->ws + h->off_Fy[p] : nullptr;
+    d.Gy = q.dim >= 2 ? h->ws + h->off_Gy[p] : nullptr;
+    d.Fz = q.dim == 3 ? h->ws + h->off_Fz[p] : nullptr;
+    d.Gz = q.dim == 3 ? h->ws + h->off_Gz[p] : nullptr;
     d.flag_count = reinterpret_cast<int*>(h->ws + h->off_cnt[p]);
   }
   HIPOK(hipMemcpyAsync(h->ws + h->off_probs, h->pd.data(), h->nprob * sizeof(ProbDev), hipMemcpyHostToDevice,
@@ -445,7 +484,7 @@ static hgks_status build_graph(hgks* h, int use_tend) {
 }
 
 static hgks_status issue_steps(hgks* h, int use_tend, int64_t nsteps) {
-  if (h->autotune && !h->tuned) {
+  if (h->autotune && !h->tuned && h->dim != 3) {
     // first step: finalize once so that dt is valid, time the tile shapes on this state, then
     // recompute the CFL minimum the finalize consumed (the state is unchanged) and run the step
     launch_dt_finalize(ctx(h), use_tend);
@@ -487,6 +526,10 @@ hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opt
   h->profile = opts ? opts->profile : 0;
   h->tile = (opts && opts->tile >= 0 && opts->tile < kNumConfigs) ? opts->tile : 0;
   h->compensated = opts ? (opts->compensated != 0) : 0;
+  if (h->dim == 3 && h->compensated) {
+    delete h;
+    return HGKS_EINVAL;
+  }
   for (int c = 0; c < kNumConfigs; ++c) h->pgrid[c] = 0;
   if (opts && (opts->precision < 0 || opts->precision > 1)) {
     delete h;
@@ -526,7 +569,7 @@ hgks_status hgks_set_ic(hgks_t* h, int32_t prob, const double* W, int32_t on_dev
   hgks_status s = materialise(h);
   if (s) return s;
   const hgks_problem& q = h->hp[prob];
-  const size_t bytes = (size_t)(q.dim + 2) * q.nx * q.ny * sizeof(double);
+  const size_t bytes = (size_t)(q.dim + 2) * cells_of(q) * sizeof(double);
   HIPOK(hipMemcpyAsync(h->ws + h->off_W[prob], W, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                        h->stream));
   if (h->compensated) HIPOK(hipMemsetAsync(h->ws + h->off_E[prob], 0, bytes, h->stream));
@@ -620,7 +663,7 @@ hgks_status hgks_get_state(const hgks_t* hc, int32_t prob, double* W, int32_t on
   hgks* h = const_cast<hgks*>(hc);
   if (!h || !W || prob < 0 || prob >= h->nprob || !h->ready) return HGKS_EINVAL;
   const hgks_problem& q = h->hp[prob];
-  const size_t bytes = (size_t)(q.dim + 2) * q.nx * q.ny * sizeof(double);
+  const size_t bytes = (size_t)(q.dim + 2) * cells_of(q) * sizeof(double);
   HIPOK(hipMemcpyAsync(W, h->ws + h->off_W[prob], bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                        h->stream));
   std::vector<TimeDev> ts;
@@ -634,7 +677,7 @@ hgks_status hgks_get_state_lo(const hgks_t* hc, int32_t prob, double* E, int32_t
   hgks* h = const_cast<hgks*>(hc);
   if (!h || !E || prob < 0 || prob >= h->nprob || !h->ready) return HGKS_EINVAL;
   const hgks_problem& q = h->hp[prob];
-  const size_t bytes = (size_t)(q.dim + 2) * q.nx * q.ny * sizeof(double);
+  const size_t bytes = (size_t)(q.dim + 2) * cells_of(q) * sizeof(double);
   if (h->compensated)
     HIPOK(hipMemcpyAsync(E, h->ws + h->off_E[prob], bytes,
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
@@ -646,7 +689,7 @@ hgks_status hgks_get_state_lo(const hgks_t* hc, int32_t prob, double* E, int32_t
   return HGKS_OK;
 }
 
-hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy) {
+static hgks_status debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy, uint8_t* fz) {
   if (!h || !fx || prob < 0 || prob >= h->nprob) return HGKS_EINVAL;
   if (!h->ready || !h->ic_set[prob]) return HGKS_EINVAL;
   std::vector<TimeDev> ts, saved;
@@ -660,32 +703,46 @@ hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy) 
   launch_flags(ctx(h), 0, 1, 1);
   HIPOK(hipGetLastError());
   const hgks_problem& q = h->hp[prob];
-  const size_t ex = q.nx + 4, ey = q.dim == 2 ? q.ny + 4 : 1;
-  std::vector<uint8_t> buf(ex * ey);
+  const size_t ex = q.nx + 4, ey = q.dim >= 2 ? q.ny + 4 : 1, ez = q.dim == 3 ? q.nz + 4 : 1;
+  std::vector<uint8_t> buf(ex * ey * ez);
   HIPOK(hipMemcpyAsync(buf.data(), h->ws + h->off_flags[prob], buf.size(), hipMemcpyDeviceToHost, h->stream));
   int cnt[2];
   HIPOK(hipMemcpyAsync(cnt, h->ws + h->off_cnt[prob], sizeof cnt, hipMemcpyDeviceToHost, h->stream));
   s = guard.restore();  // synchronises the stream: buf and cnt are complete
   if (s) return s;
-  const int jo = q.dim == 2 ? 2 : 0;
-  for (int j = 0; j < q.ny; ++j)
-    for (int i = 0; i < q.nx; ++i) {
-      const uint8_t v = buf[(size_t)(j + jo) * ex + i + 2];
-      fx[(size_t)j * q.nx + i] = v & 1;
-      if (fy && q.dim == 2) fy[(size_t)j * q.nx + i] = (v >> 1) & 1;
-    }
-  const double cells = (double)q.nx * q.ny;
+  const int jo = q.dim >= 2 ? 2 : 0, ko = q.dim == 3 ? 2 : 0, nz = q.dim == 3 ? q.nz : 1;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < q.ny; ++j)
+      for (int i = 0; i < q.nx; ++i) {
+        const uint8_t v = buf[((size_t)(k + ko) * ey + (j + jo)) * ex + i + 2];
+        const size_t o = ((size_t)k * q.ny + j) * q.nx + i;
+        fx[o] = v & 1;
+        if (fy && q.dim >= 2) fy[o] = (v >> 1) & 1;
+        if (fz && q.dim == 3) fz[o] = (v >> 2) & 1;
+      }
+  const double cells = (double)cells_of(q);
   h->last_frac_x[prob] = cnt[0] / cells;
   h->last_frac_y[prob] = cnt[1] / cells;
   return HGKS_OK;
 }
 
-hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx, double* Fy,
-                                    double* Gy) {
+hgks_status hgks_debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy) {
+  if (h && prob >= 0 && prob < h->nprob && h->hp[prob].dim == 3) return HGKS_EINVAL;
+  return debug_flags(h, prob, fx, fy, nullptr);
+}
+
+hgks_status hgks_debug_flags3(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy, uint8_t* fz) {
+  if (!h || prob < 0 || prob >= h->nprob || h->hp[prob].dim != 3 || !fy || !fz) return HGKS_EINVAL;
+  return debug_flags(h, prob, fx, fy, fz);
+}
+
+static hgks_status debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx, double* Fy,
+                                      double* Gy, double* Fz, double* Gz) {
   if (!h || prob < 0 || prob >= h->nprob || !Fx || !Gx || !(dt > 0.0)) return HGKS_EINVAL;
   if (!h->ready || !h->ic_set[prob]) return HGKS_EINVAL;
   const hgks_problem& q = h->hp[prob];
-  if (q.dim == 2 && (!Fy || !Gy)) return HGKS_EINVAL;
+  if (q.dim >= 2 && (!Fy || !Gy)) return HGKS_EINVAL;
+  if (q.dim == 3 && (!Fz || !Gz)) return HGKS_EINVAL;
   std::vector<TimeDev> ts, saved;
   hgks_status s = read_ts(h, ts);
   if (s) return s;
@@ -701,8 +758,9 @@ hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* 
   launch_flags(L, 0, 0, 0);
   launch_flux(L, 1);
   HIPOK(hipGetLastError());
-  const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny;
-  const size_t nxf = nc * ny * (nx + 1), nyf = q.dim == 2 ? nc * (ny + 1) * nx : 0;
+  const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny, nz = q.dim == 3 ? q.nz : 1;
+  const size_t nxf = nc * nz * ny * (nx + 1), nyf = q.dim >= 2 ? nc * nz * (ny + 1) * nx : 0;
+  const size_t nzf = q.dim == 3 ? nc * (nz + 1) * ny * nx : 0;
   auto fetch = [&](size_t off, size_t n, double* dst) -> hgks_status {
     if (h->fp32) {
       std::vector<float> tmp(n);
@@ -717,11 +775,27 @@ hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* 
   };
   if ((s = fetch(h->off_Fx[prob], nxf, Fx))) return s;
   if ((s = fetch(h->off_Gx[prob], nxf, Gx))) return s;
-  if (q.dim == 2) {
+  if (q.dim >= 2) {
     if ((s = fetch(h->off_Fy[prob], nyf, Fy))) return s;
     if ((s = fetch(h->off_Gy[prob], nyf, Gy))) return s;
   }
+  if (q.dim == 3) {
+    if ((s = fetch(h->off_Fz[prob], nzf, Fz))) return s;
+    if ((s = fetch(h->off_Gz[prob], nzf, Gz))) return s;
+  }
   return guard.restore();
+}
+
+hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx, double* Fy,
+                                    double* Gy) {
+  if (h && prob >= 0 && prob < h->nprob && h->hp[prob].dim == 3) return HGKS_EINVAL;
+  return debug_stage_fluxes(h, prob, dt, Fx, Gx, Fy, Gy, nullptr, nullptr);
+}
+
+hgks_status hgks_debug_stage_fluxes3(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx, double* Fy,
+                                     double* Gy, double* Fz, double* Gz) {
+  if (!h || prob < 0 || prob >= h->nprob || h->hp[prob].dim != 3) return HGKS_EINVAL;
+  return debug_stage_fluxes(h, prob, dt, Fx, Gx, Fy, Gy, Fz, Gz);
 }
 
 hgks_status hgks_get_stats(const hgks_t* hc, int32_t prob, double* out) {
@@ -733,7 +807,7 @@ hgks_status hgks_get_stats(const hgks_t* hc, int32_t prob, double* out) {
   int cnt[2];
   HIPOK(hipMemcpy(cnt, h->ws + h->off_cnt[prob], sizeof cnt, hipMemcpyDeviceToHost));
   const hgks_problem& q = h->hp[prob];
-  const double cells = (double)q.nx * q.ny;
+  const double cells = (double)cells_of(q);
   out[0] = (double)ts[prob].steps;
   out[1] = cells;
   out[2] = ts[prob].t;

@@ -25,6 +25,7 @@ struct BcDev {
 struct ProbDev {
   int dim, nx, ny, ns;
   int bc[4];
+  int nz, bcz[2];            // 3D: cells along z and the kinds of the z sides (nz = 1 otherwise)
   int recon, zeta1_mode;
   int positivity;            // 1: non-physical reconstructed states drop to first order
   int prescribed;            // 1 if any side is a prescribed-state side (bc == 4)
@@ -33,6 +34,7 @@ struct ProbDev {
   double gamma, K, mu, Pr, c1, c2;  // K: internal dof of the 2D model (1D problems embed into it)
   double Kp2, iKp2, kpr;     // K + 2, 1 / (K + 2), 1 / Pr - 1 (uniform values kept out of the lanes)
   double ihx, ihy;           // 1 / dx, 1 / dy
+  double dz, ihz;            // 3D: z cell size and its inverse
   double cfl, fixed_dt;
   double ghi, glo, eps;
   double* W;                 // state W^n        [nc][ny][nx]
@@ -45,6 +47,8 @@ struct ProbDev {
   void* Gx;                  // x-interfaces: dF/dt
   void* Fy;                  // y-interfaces [4][ny+1][nx]
   void* Gy;
+  void* Fz;                  // 3D: z-interfaces [5][nz+1][ny][nx]
+  void* Gz;
   int* flag_count;           // [2] troubled cells counted at the last flag evaluation
   BcDev bcd[4];              // read where bc[side] == 4
 };

@@ -40,6 +40,17 @@ inline int flux_tiles(int dim, int nx, int ny, int tile) {
   return ((nx + 1 + tn - 1) / tn) * ((ny + tt - 1) / tt) + ((ny + 1 + tn - 1) / tn) * ((nx + tt - 1) / tt);
 }
 
+// 3D flux tiles: TN3 faces along the normal x TA3 x TB3 along the two tangential directions, one block
+// of 4 threads per face (its 2 x 2 Gauss points)
+constexpr int kTN3 = 4, kTA3 = 4, kTB3 = 4;
+inline int flux_tiles3(int nx, int ny, int nz) {
+  const int N[3] = {nx, ny, nz};
+  int t = 0;
+  for (int d = 0; d < 3; ++d)
+    t += ((N[d] + 1 + kTN3 - 1) / kTN3) * ((N[(d + 1) % 3] + kTA3 - 1) / kTA3) * ((N[(d + 2) % 3] + kTB3 - 1) / kTB3);
+  return t;
+}
+
 void launch_cfl(const LaunchCtx& L);
 void launch_dt_finalize(const LaunchCtx& L, int use_tend);
 void launch_commit(const LaunchCtx& L, int use_tend);

@@ -29,7 +29,7 @@ NUM_LAUNCH_CONFIGS = 12  # flux launch configurations: 6 tile shapes x (one bloc
 
 ENTRY_POINTS = ("hgks_create", "hgks_workspace_bytes", "hgks_bind_workspace", "hgks_set_ic", "hgks_step",
                 "hgks_run", "hgks_get_state", "hgks_get_state_lo", "hgks_debug_flags", "hgks_debug_stage_fluxes",
-                "hgks_get_stats", "hgks_get_tile", "hgks_get_profile", "hgks_destroy", "hgks_status_str")
+                "hgks_debug_flags3", "hgks_debug_stage_fluxes3", "hgks_get_stats", "hgks_get_tile", "hgks_get_profile", "hgks_destroy", "hgks_status_str")
 
 
 class HgksLibraryMissing(ImportError):
@@ -70,6 +70,7 @@ class hgks_problem(C.Structure):
         ("gamma_hi", C.c_double), ("gamma_lo", C.c_double), ("weno_eps", C.c_double),
         ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32), ("positivity", C.c_int32),
         ("bcd", hgks_bc_data * 4),
+        ("nz", C.c_int32), ("z0", C.c_double), ("z1", C.c_double), ("bcz", C.c_int32 * 2),
     ]
 
 
@@ -81,7 +82,8 @@ class hgks_opts(C.Structure):
 
 @dataclasses.dataclass
 class Problem:
-    """Problem statement (paper Sec. 2; parameters of Sec. 3)."""
+    """Problem statement (paper Sec. 2; parameters of Sec. 3). dim 1, 2 or 3; for dim 3 the grid is
+    nx x ny x nz on [x0, x1] x [y0, y1] x [z0, z1], bc holds the x and y sides and bcz the z sides."""
     dim: int = 2
     nx: int = 64
     ny: int = 64
@@ -106,6 +108,10 @@ class Problem:
     tangential_flag_mode: int = 0
     positivity: int = 0  # 1: first-order fallback for non-physical reconstructed states
     bcd: tuple = ()  # BcData per side (x-low, x-high, y-low, y-high), read where bc is BC_PRESCRIBED
+    nz: int = 1
+    z0: float = 0.0
+    z1: float = 1.0
+    bcz: tuple = (BC_OUTFLOW,) * 2
 
     @property
     def nc(self):
@@ -113,11 +119,13 @@ class Problem:
 
     @property
     def shape(self):
-        return (self.nc, self.nx) if self.dim == 1 else (self.nc, self.ny, self.nx)
+        if self.dim == 1:
+            return (self.nc, self.nx)
+        return (self.nc, self.ny, self.nx) if self.dim == 2 else (self.nc, self.nz, self.ny, self.nx)
 
     @property
     def cells(self):
-        return self.nx * (self.ny if self.dim == 2 else 1)
+        return self.nx * (self.ny if self.dim >= 2 else 1) * (self.nz if self.dim == 3 else 1)
 
     def c_struct(self) -> hgks_problem:
         s = hgks_problem()
@@ -125,6 +133,8 @@ class Problem:
             v = getattr(self, f.name)
             if f.name == "bc":
                 s.bc = (C.c_int32 * 4)(*[int(b) for b in (list(v) + [0] * 4)[:4]])
+            elif f.name == "bcz":
+                s.bcz = (C.c_int32 * 2)(*[int(b) for b in (list(v) + [0] * 2)[:2]])
             elif f.name == "bcd":
                 for k, d in enumerate(list(v)[:4]):
                     if isinstance(d, dict):
@@ -166,6 +176,8 @@ def lib():
             "hgks_get_state_lo": (i32, [vp, i32, vp, i32]),
             "hgks_debug_flags": (i32, [vp, i32, vp, vp]),
             "hgks_debug_stage_fluxes": (i32, [vp, i32, d, vp, vp, vp, vp]),
+            "hgks_debug_flags3": (i32, [vp, i32, vp, vp, vp]),
+            "hgks_debug_stage_fluxes3": (i32, [vp, i32, d, vp, vp, vp, vp, vp, vp]),
             "hgks_get_stats": (i32, [vp, i32, vp]),
             "hgks_get_tile": (i32, [vp, vp]),
             "hgks_get_profile": (i32, [vp, vp]),
@@ -267,6 +279,16 @@ def hgks_debug_stage_fluxes(h, prob: int, dt: float, Fx, Gx, Fy, Gy):
     _check(lib().hgks_debug_stage_fluxes(h, int(prob), float(dt), *ptrs), "hgks_debug_stage_fluxes")
 
 
+def hgks_debug_flags3(h, prob: int, fx: np.ndarray, fy: np.ndarray, fz: np.ndarray):
+    _check(lib().hgks_debug_flags3(h, int(prob), *[a.ctypes.data_as(C.c_void_p) for a in (fx, fy, fz)]),
+           "hgks_debug_flags3")
+
+
+def hgks_debug_stage_fluxes3(h, prob: int, dt: float, Fx, Gx, Fy, Gy, Fz, Gz):
+    ptrs = [a.ctypes.data_as(C.c_void_p) for a in (Fx, Gx, Fy, Gy, Fz, Gz)]
+    _check(lib().hgks_debug_stage_fluxes3(h, int(prob), float(dt), *ptrs), "hgks_debug_stage_fluxes3")
+
+
 def hgks_get_stats(h, prob: int):
     out = np.zeros(6)
     _check(lib().hgks_get_stats(h, int(prob), out.ctypes.data_as(C.c_void_p)), "hgks_get_stats")
@@ -347,6 +369,10 @@ class Solver:
 
     def flags(self, prob: int = 0):
         P = self.problems[prob]
+        if P.dim == 3:
+            fx, fy, fz = (np.zeros((P.nz, P.ny, P.nx), np.uint8) for _ in range(3))
+            hgks_debug_flags3(self.h, prob, fx, fy, fz)
+            return fx, fy, fz
         shp = (P.nx,) if P.dim == 1 else (P.ny, P.nx)
         fx = np.zeros(shp, np.uint8)
         fy = np.zeros(shp, np.uint8) if P.dim == 2 else None
@@ -354,7 +380,15 @@ class Solver:
         return fx, fy
 
     def stage_fluxes(self, prob: int, dt: float):
+        """(F, G) per direction at the interfaces: F the time-averaged flux and G its time derivative."""
         P = self.problems[prob]
+        if P.dim == 3:
+            nx, ny, nz = P.nx, P.ny, P.nz
+            Fx, Gx = np.zeros((5, nz, ny, nx + 1)), np.zeros((5, nz, ny, nx + 1))
+            Fy, Gy = np.zeros((5, nz, ny + 1, nx)), np.zeros((5, nz, ny + 1, nx))
+            Fz, Gz = np.zeros((5, nz + 1, ny, nx)), np.zeros((5, nz + 1, ny, nx))
+            hgks_debug_stage_fluxes3(self.h, prob, dt, Fx, Gx, Fy, Gy, Fz, Gz)
+            return (Fx, Gx), (Fy, Gy), (Fz, Gz)
         nc, nx, ny = P.nc, P.nx, (P.ny if P.dim == 2 else 1)
         Fx = np.zeros((nc, ny, nx + 1))
         Gx = np.zeros_like(Fx)

@@ -84,6 +84,21 @@ def prim_to_cons3(rho, u, v, w, p, gamma=GAMMA):
     return np.stack([rho, rho * u, rho * v, rho * w, E])
 
 
+def octants_3d(nx: int, ny: int, nz: int, seed: int = 0, wiggle: float = 0.0, gamma=GAMMA):
+    """Eight constant states (rho, p in [0.5, 1.5], each velocity component in [-0.3, 0.3]) on the octants of
+    the unit cube split at its centre, times 1 + wiggle * (a smooth seeded product of sines) in rho and p:
+    planar discontinuities meeting at a point, smooth regions in between. W[c][k][j][i]."""
+    rng = np.random.default_rng(seed)
+    zc, yc, xc = ((np.arange(n) + 0.5) / n for n in (nz, ny, nx))
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    code = (X >= 0.5).astype(int) * 4 + (Y >= 0.5).astype(int) * 2 + (Z >= 0.5).astype(int)
+    rho, p = rng.uniform(0.5, 1.5, 8)[code], rng.uniform(0.5, 1.5, 8)[code]
+    vel = [rng.uniform(-0.3, 0.3, 8)[code] for _ in range(3)]
+    ph = rng.uniform(0.0, 2.0 * np.pi, 3)
+    bump = np.sin(2 * np.pi * X + ph[0]) * np.sin(2 * np.pi * Y + ph[1]) * np.sin(2 * np.pi * Z + ph[2])
+    return prim_to_cons3(rho * (1.0 + wiggle * bump), *vel, p * (1.0 + wiggle * bump), gamma)
+
+
 def embed_2d_in_3d(W2, nz: int, axis: int = 2):
     """A 2D state W2[c][j][i] (c in rho, rho U, rho V, rho E) as a 3D state uniform along `axis`: axis 2 keeps
     (x, y) -> (x, y); axis 0 maps (x, y) -> (y, z); axis 1 maps (x, y) -> (z, x). Returns W3[c][k][j][i]."""

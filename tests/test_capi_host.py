@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "hgks.h")
 def _declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(hgks_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(hgks_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_entry_point():
@@ -63,11 +63,21 @@ def test_status_strings():
     dict(bc=(4, 1, 1, 1), bcd=(H.BcData(a=(1.0, 0.0, 0.0, -1.0)),)),
     dict(bc=(4, 1, 1, 1), bcd=(H.BcData(b=(-1.0, 0.0, 0.0, 2.5)),)),
     dict(dim=1, ny=1, bc=(1, 4, 0, 0), bcd=(None, H.BcData(a=(1.0, 3.0, 0.0, 1.0), rest=2))),
+    # three dimensions: too few z cells, unpaired or unknown z sides, what the 3D path does not take
+    dict(dim=3, nz=4), dict(dim=3, nz=8, bcz=(0, 1)), dict(dim=3, nz=8, bcz=(1, 4)), dict(dim=3, nz=8, z1=0.0),
+    dict(dim=3, nz=8, eqn=1, mu=1e-3, Pr=0.72), dict(dim=3, nz=8, positivity=1),
+    dict(dim=3, nz=8, bc=(4, 1, 1, 1), bcd=(H.BcData(),)),
 ])
 def test_invalid_problems_rejected_on_host(bad):
     P = H.Problem(**bad)
     with pytest.raises(H.HgksError) as e:
         H.hgks_create([P])
+    assert e.value.code == H.EINVAL
+
+
+def test_compensated_accumulation_rejected_in_3d():
+    with pytest.raises(H.HgksError) as e:
+        H.hgks_create([H.Problem(dim=3, nx=8, ny=8, nz=8)], compensated=1)
     assert e.value.code == H.EINVAL
 
 

@@ -1,0 +1,178 @@
+"""The three-dimensional scheme through the C ABI against the oracle: troubled-cell flags bit-exact, the
+stage fluxes F and dF/dt of every face of the three directions to FP64 rounding, steps (time steps
+bit-exact), a state uniform along z against the 2D GPU path, a batch of uneven 3D problems, the FP32 bulk
+mode, and smooth advection at fifth order. Grids are ragged against the 4 x 4 x 4 face tiles."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_05572_amd import hgks as H
+from paper_2304_05572_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _kw(nx, ny, nz, bc=(1, 1, 1, 1), bcz=(1, 1), **extra):
+    kw = dict(dim=3, nx=nx, ny=ny, nz=nz, bc=bc, bcz=bcz, c1=0.01, c2=1.0)
+    kw.update(extra)
+    return kw
+
+
+CASES = {
+    # name: (grid, boundary kinds, extra parameters, state seed, wiggle)
+    "outflow": ((13, 11, 9), dict(bc=(1, 1, 1, 1), bcz=(1, 1)), {}, 1, 0.05),
+    "walls": ((9, 14, 10), dict(bc=(2, 2, 3, 3), bcz=(2, 3)), {}, 2, 0.02),
+    "periodic": ((10, 9, 13), dict(bc=(0, 0, 0, 0), bcz=(0, 0)), {}, 3, 0.0),
+    "ns": ((11, 10, 12), dict(bc=(1, 1, 0, 0), bcz=(3, 3)), dict(eqn=1, mu=2e-3, Pr=1.0), 4, 0.05),
+    "wenoao": ((9, 9, 9), dict(bc=(1, 1, 1, 1), bcz=(1, 1)), dict(recon=1), 5, 0.05),
+    "linear": ((9, 10, 11), dict(bc=(0, 0, 0, 0), bcz=(0, 0)), dict(recon=2), 6, 0.05),
+}
+
+
+def _case(name):
+    (nx, ny, nz), bcs, extra, seed, wig = CASES[name]
+    kw = _kw(nx, ny, nz, **bcs, **extra)
+    W = wl.octants_3d(nx, ny, nz, seed=seed, wiggle=wig)
+    if name in ("periodic", "linear"):  # periodic sides: a smooth state with one sharp layer inside
+        rng = np.random.default_rng(seed)
+        zc, yc, xc = ((np.arange(n) + 0.5) / n for n in (nz, ny, nx))
+        Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        rho = 1.0 + 0.3 * np.sin(2 * np.pi * X + ph[0]) * np.cos(2 * np.pi * Y + ph[1]) + 0.4 * (np.abs(Z - 0.5) < 0.2)
+        W = wl.prim_to_cons3(rho, 0.2 + 0.1 * np.sin(2 * np.pi * Z + ph[2]), -0.1 + 0 * X, 0.15 + 0 * X,
+                             1.0 + 0.2 * np.cos(2 * np.pi * (X + Y) + ph[2]))
+    return kw, W
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_flags_and_stage_fluxes_match_oracle(name):
+    kw, W = _case(name)
+    say("3d fluxes", name, kw["nx"], kw["ny"], kw["nz"])
+    s = H.Solver(H.Problem(**kw))
+    s.set_ic(0, W)
+    f = s.flags(0)
+    o = O.flags3(O.Problem(**kw), W)
+    for d in range(3):
+        assert np.array_equal(f[d], o[d]), d
+    if kw.get("recon", 0) == 0:
+        assert any(x.any() for x in o) and not all(x.all() for x in o)
+    dt = O.cfl_dt(O.Problem(**kw), W)
+    g = s.stage_fluxes(0, dt)
+    r = O.stage_fluxes3(O.Problem(**kw), W, dt, nthreads=NT)
+    worst = 0.0
+    for d in range(3):
+        for k in range(2):
+            worst = max(worst, rel(g[d][k], r[d][k]))
+    say("worst rel", worst)
+    assert worst < 1e-12
+
+
+@pytest.mark.parametrize("name", ["outflow", "walls", "ns"])
+def test_steps_match_oracle(name):
+    """Eight FP64 steps, each against an oracle step from the GPU's state before it: time steps bit-exact,
+    states to 1e-12."""
+    kw, W = _case(name)
+    Po = O.Problem(**kw)
+    s = H.Solver(H.Problem(**kw), use_graph=True)
+    s.set_ic(0, W)
+    say("3d steps", name)
+    Wg, tg, worst = W, 0.0, 0.0
+    for k in range(8):
+        Wo, to, dto = O.step(Po, Wg, tg, nthreads=NT)
+        assert s.step()[0] == dto, k
+        Wg, tg = s.get_state(0)
+        assert tg == to, k
+        worst = max(worst, rel(Wg, Wo))
+    say("worst step rel", worst)
+    assert worst < 1e-12
+
+
+def test_uniform_along_z_equals_2d_gpu_path():
+    """A 2D Riemann problem embedded uniformly along z (periodic in z) through the 3D kernels against the
+    same problem through the 2D kernels, five steps from the same start."""
+    n, m = 24, 5
+    W2, _ = wl.riemann_2d(n, seed=7)
+    s2 = H.Solver(H.Problem(nx=n, ny=n, bc=(1, 1, 1, 1)))
+    s3 = H.Solver(H.Problem(**_kw(n, n, m, bcz=(0, 0), z1=m / n)))
+    s2.set_ic(0, W2)
+    s3.set_ic(0, wl.embed_2d_in_3d(W2, m, 2))
+    say("3d vs 2d embedding")
+    for k in range(5):
+        dt2, dt3 = s2.step()[0], s3.step()[0]
+        assert abs(dt3 - dt2) <= 1e-14 * dt2, k
+    a, _ = s2.get_state(0)
+    b, _ = s3.get_state(0)
+    e = wl.embed_2d_in_3d(a, m, 2)
+    say("rel", rel(b, e))
+    assert rel(b, e) < 1e-12
+
+
+def test_batch_of_uneven_problems():
+    """Three 3D problems of different shapes advanced together: each to its own end time, equal to the
+    same problem run alone."""
+    names = ["outflow", "walls", "ns"]
+    kws, Ws = zip(*[_case(nm) for nm in names])
+    t_end = [0.02, 0.015, 0.01]
+    s = H.Solver([H.Problem(**k) for k in kws])
+    for p, W in enumerate(Ws):
+        s.set_ic(p, W)
+    s.run(t_end)
+    say("3d batch")
+    for p, (k, W) in enumerate(zip(kws, Ws)):
+        one = H.Solver(H.Problem(**k))
+        one.set_ic(0, W)
+        one.run(t_end[p])
+        a, ta = s.get_state(p)
+        b, tb = one.get_state(0)
+        assert ta == tb == t_end[p]
+        assert np.array_equal(a, b), p
+
+
+def test_fp32_bulk_close_to_oracle():
+    kw, W = _case("outflow")
+    s = H.Solver(H.Problem(**kw), precision=H.FP32_BULK)
+    s.set_ic(0, W)
+    Wo, t = W.copy(), 0.0
+    for _ in range(5):
+        Wo, t, _ = O.step(O.Problem(**kw), Wo, t, nthreads=NT)
+    s.run(np.inf, 5)
+    Wg, tg = s.get_state(0)
+    say("fp32 3d", rel(Wg, Wo), abs(tg - t) / t)
+    assert rel(Wg, Wo) < 1e-4 and abs(tg - t) < 1e-5 * t
+
+
+def test_smooth_advection_fifth_order_on_gpu():
+    """rho = 1 + 0.2 sin(pi (x + y + z - 3t)) on [0, 2]^3, periodic, to t = 2/3 at CFL 0.5 on 16^3 and 24^3:
+    the error falls at about fifth order; the first six steps at 16^3 equal the oracle's to 1e-12."""
+    errs = []
+    for n in (16, 24):
+        kw = _kw(n, n, n, bc=(0, 0, 0, 0), bcz=(0, 0), x1=2, y1=2, z1=2, c1=0.0, c2=0.0, cfl=0.5)
+        s = H.Solver(H.Problem(**kw), use_graph=True)
+        s.set_ic(0, wl.advection_3d(n))
+        if n == 16:
+            s.run(np.inf, 6)
+            Wo, to = wl.advection_3d(n), 0.0
+            for _ in range(6):
+                Wo, to, _ = O.step(O.Problem(**kw), Wo, to, nthreads=NT)
+            W, t = s.get_state(0)
+            say("16^3 six steps vs oracle", rel(W, Wo))
+            assert abs(t - to) <= 1e-14 * to and rel(W, Wo) < 1e-12
+        s.run(2.0 / 3.0)
+        W, t = s.get_state(0)
+        assert t == 2.0 / 3.0
+        errs.append(np.abs(W[0] - wl.advection_3d(n, 2.0 / 3.0)[0]).mean())
+    order = np.log(errs[0] / errs[1]) / np.log(1.5)
+    say("errors", errs, "order", order)
+    assert 4.5 < order < 5.6
