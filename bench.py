@@ -10,7 +10,8 @@ reduction), inputs resident in device memory.
 `value` is the plain FP64 path in Mcell-updates/s, timed over K steps issued eagerly with HIP events
 around the flux launches only. The same line carries: the FP32-bulk path on the same workload; FP32-bulk
 with compensated state; (with --variants ...,wenoao) forced WENO5-AO against the hybrid scheme; the batched
-path (64 uneven problems in one set of launches); per-kernel-group times and graph-replay step times from
+path (64 uneven problems in one set of launches); the three-dimensional scheme on an eight-octant Riemann
+problem (FP64 and FP32-bulk); per-kernel-group times and graph-replay step times from
 short side windows; the rate with host transfers included; the L1/Linf distance of the first step of each
 precision to the CPU oracle over the full grid; the roofline position of the dominant kernel (fused
 reconstruction + flux, VALU-bound: algorithmic FP64 flops per Gauss point x Gauss points per launch over
@@ -53,7 +54,7 @@ def log(*a):
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("hgks_kernels.hip", "hgks_device.hpp"):
+    for f in ("hgks_kernels.hip", "hgks_device.hpp", "hgks_grid.hpp"):
         with open(os.path.join(ROOT, "paper_2304_05572_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -177,6 +178,29 @@ def oracle_leg(W0, n):
            "sample": f"one S2O4 step of the full {n}x{n} Riemann problem from its initial data, FP64 C oracle, "
                      f"{nth} OpenMP threads, {el:.1f} s wall"}
     return W, dt, rec
+
+
+def octant_problem(H, n, recon=0):
+    return H.Problem(dim=3, nx=n, ny=n, nz=n, bc=(H.BC_OUTFLOW,) * 4, bcz=(H.BC_OUTFLOW,) * 2, cfl=0.5, c1=0.01,
+                     c2=1.0, recon=recon)
+
+
+def time_3d(H, wl, n, seed, steps, warmup):
+    """The three-dimensional scheme on a seeded eight-octant Riemann problem, n^3 cells, FP64 and FP32-bulk:
+    Mcell-updates/s over eagerly issued steps and the flux kernel's HIP-event mean launch time."""
+    W0 = wl.octants_3d(n, n, n, seed=seed)
+    out = {"workload": f"3D eight-octant Riemann problem, Euler, {n}^3 cells, seeded octant states (seed {seed}), "
+                       "hybrid WENO5-AO GKS, 2 x 2 Gauss points per face, S2O4, CFL 0.5, outflow"}
+    for name, prec in (("fp64", H.FP64), ("fp32_bulk", H.FP32_BULK)):
+        log(f"[bench] timing 3d {name}: {n}^3, {warmup} warm-up + {steps} steps")
+        el, flux_ms, stats, _, prof = time_solver(H, [octant_problem(H, n)], [W0], prec, steps, warmup, 0)
+        gps = 4 * 3 * (n + 1) * n * n
+        out[name] = {"value": n ** 3 * steps / el / 1e6, "ms_per_step": el / steps * 1e3,
+                     "flux_ms_per_launch": flux_ms, "gauss_points_per_launch": gps,
+                     "kernel": "k_flux3<%s>" % ("double" if prec == H.FP64 else "float"),
+                     "flagged_x": stats[0]["flagged_x"], "flagged_y": stats[0]["flagged_y"]}
+        log(f"[bench] 3d {name}: {out[name]['value']:.1f} Mcell-updates/s, flux {flux_ms:.3f} ms/launch")
+    return out
 
 
 def tile_sweep(args):
@@ -306,8 +330,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tile", type=int, default=-1, help="tile-shape index; -1 autotunes")
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--variants", default="fp64,fp32,batched,fp32c",
+    ap.add_argument("--n3", type=int, default=128, help="cells per side of the 3D variant")
+    ap.add_argument("--variants", default="fp64,fp32,batched,fp32c,3d",
                     help="comma list of fp64, fp32, batched, fp32c (FP32-bulk with compensated state), "
+                         "3d (the three-dimensional scheme on an n3^3 octant problem), "
                          "wenoao (FP64 with every cell troubled: the WENO5-AO scheme the hybrid one is "
                          "compared against; not in the default run, whose FP64 flux-kernel statistics "
                          "would mix both)")
@@ -382,6 +408,8 @@ def main():
                      problems=len(sizes), min_n=min(sizes), max_n=max(sizes), launch_config=launch_config(tile))
         log(f"[bench] batched: {batch['mcells']:.1f} Mcell-updates/s")
         del bstates
+
+    res3 = time_3d(H, wl, args.n3, args.seed, args.steps, args.warmup) if "3d" in variants else None
 
     parity, cpu = {}, None
     if not args.no_oracle:
@@ -467,6 +495,8 @@ def main():
             "value": f["mcells"], "ms_per_step": f["ms_per_step"], "kernel_ms_per_step": f["kernel_ms_per_step"],
             "graph_ms_per_step": f["graph_ms_per_step"], "dtype": "f32 (f64 state + f64 compensation)",
             "launch_config": launch_config(f["tile"])}
+    if res3:
+        out["variants"]["three_dimensional"] = res3
     if batch:
         out["variants"]["batched"] = dict(batch, value=batch["mcells"], dtype="f32 (f64 state/flags/CFL)",
                                           workload=f"{batch['problems']} independent Riemann problems, N in "

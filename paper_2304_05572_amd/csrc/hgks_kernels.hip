@@ -9,28 +9,10 @@
 #include <hip/hip_runtime.h>
 
 #include "hgks_device.hpp"
-#include "hgks_device3.hpp"
+#include "hgks_grid.hpp"
 #include "hgks_launch.h"
 
 namespace hk {
-
-__device__ inline int find_prob(const int* __restrict__ off, int nprob, int b) {
-  int lo = 0, hi = nprob;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (off[mid] <= b) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD receives a contiguous
-// range of tiles and neighbouring tiles share its L2.
-__device__ inline int xcd_swizzle(int b, int nblocks) {
-  const int q = nblocks >> 3, r = nblocks & 7;
-  const int x = b & 7, idx = b >> 3;
-  return x * q + (x < r ? x : r) + idx;
-}
 
 // ---------------------------------------------------------------------------------------------
 // CFL quantity of one cell: min(h / (|U| + c), h^2 / (4 mu / rho)) (Sec. 3), FP64, no contraction,
@@ -50,27 +32,6 @@ __device__ inline double cfl_quantity(const ProbDev& P, double rho, double mu_, 
     q = fmin(q, qv);
   }
   return q;
-}
-
-__device__ inline double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Block-wide minimum (wavefront shuffles, then the waves' minima through LDS); thread 0 returns it.
-__device__ inline double block_min(double q) {
-  __shared__ double red[16];
-  q = wave_min(q);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) red[w] = q;
-  __syncthreads();
-  double m = red[0];
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int k = 1; k < nw; ++k) m = fmin(m, red[k]);
-  }
-  return m;
 }
 
 // The CFL minimum is reduced in two levels: every block of the cell-wise kernels (this one and the
@@ -803,393 +764,6 @@ __global__ void __launch_bounds__(256) k_repair(const ProbDev* __restrict__ prob
 }
 
 
-// =============================================================================================
-// Three dimensions: flags, fused reconstruction + flux over 4 x 4 x 4 face tiles, stage updates
-// =============================================================================================
-
-// Widened troubled-cell flags of every cell of the extended range [-2, n+1]^3: bit d for direction d.
-__global__ void __launch_bounds__(256) k_flags3(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
-                                                const int* __restrict__ off, int nprob, int use_stage_state,
-                                                int count) {
-  const int p = find_prob(off, nprob, blockIdx.x);
-  const ProbDev& P = probs[p];
-  if (!ts[p].active) return;
-  const int ex = P.nx + 4, ey = P.ny + 4, ez = P.nz + 4;
-  const int e = (blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
-  int fl = 0, interior = 0;
-  if (e < ex * ey * ez) {
-    const int i = e % ex - 2, j = (e / ex) % ey - 2, k = e / (ex * ey) - 2;
-    const double* W = use_stage_state ? P.Ws : P.W;
-    if (P.recon == 1) {
-      fl = 7;
-    } else if (P.recon == 0) {
-      const double h[3] = {P.dx, P.dy, P.dz};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double thr = (P.zeta1_mode == 0) ? 5.0 * h[d] : 5.0 * h[d] * h[d] * h[d];
-        double q[7][5];
-#pragma unroll
-        for (int r = 0; r < 7; ++r)
-          load_cell3(P, W, i + (d == 0 ? r - 3 : 0), j + (d == 1 ? r - 3 : 0), k + (d == 2 ? r - 3 : 0), q[r]);
-        int f = 0;
-#pragma unroll
-        for (int s = 0; s < 3; ++s)
-#pragma unroll
-          for (int c = 0; c < 5; ++c)
-            f |= troubled5(q[s][c], q[s + 1][c], q[s + 2][c], q[s + 3][c], q[s + 4][c], thr);
-        fl |= f << d;
-      }
-    }
-    P.flags[e] = (uint8_t)fl;
-    interior = (i >= 0 && i < P.nx && j >= 0 && j < P.ny && k >= 0 && k < P.nz);
-  }
-  if (count) {
-    const unsigned long long bx = __ballot(interior && (fl & 1));
-    const unsigned long long by = __ballot(interior && (fl & 2));
-    if ((threadIdx.x & 63) == 0) {
-      if (bx) atomicAdd(&P.flag_count[0], __popcll(bx));
-      if (by) atomicAdd(&P.flag_count[1], __popcll(by));
-    }
-  }
-}
-
-__device__ inline uint8_t flag3_at(const ProbDev& P, int i, int j, int k) {
-  if (i < -2 || i > P.nx + 1 || j < -2 || j > P.ny + 1 || k < -2 || k > P.nz + 1) return 0;
-  return P.flags[((size_t)(k + 2) * (P.ny + 4) + (j + 2)) * (P.nx + 4) + (i + 2)];
-}
-
-// One block per tile of kTN3 x kTA3 x kTB3 faces of one direction: phase 1 stages the cells in frame
-// components, phase 2 reconstructs every line along the normal (both sides, values and normal slopes),
-// phase 3 gives each thread one of the 2 x 2 Gauss points of a face: the two tangential sweeps of each
-// side, then the gas-kinetic flux; the four points of a face are averaged with lane exchanges.
-template <typename T>
-__global__ void __launch_bounds__(256) k_flux3(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
-                                               const int* __restrict__ off, int nprob, int stage) {
-  constexpr int TN = kTN3, TA = kTA3, TB = kTB3;
-  constexpr int CN = TN + 5, CA = TA + 4, CB = TB + 4;  // staged cells: normal -3..TN+1, tangential -2..T+1
-  constexpr int NRS = 21;                              // 20 values per line-interface, padded
-  __shared__ T sW[5][CB][CA][CN];
-  __shared__ T sNR[CB][CA][TN][NRS];
-  const int b = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int p = find_prob(off, nprob, b);
-  const ProbDev& P = probs[p];
-  const TimeDev& tsp = ts[p];
-  if (!tsp.active) return;
-  const int tid = threadIdx.x;
-  const int N[3] = {P.nx, P.ny, P.nz};
-  int lt = b - off[p];
-  int d = 0, nt = 0;
-  for (; d < 3; ++d) {
-    nt = ((N[d] + 1 + TN - 1) / TN) * ((N[(d + 1) % 3] + TA - 1) / TA) * ((N[(d + 2) % 3] + TB - 1) / TB);
-    if (lt < nt) break;
-    lt -= nt;
-  }
-  const int da = (d + 1) % 3, db = (d + 2) % 3;
-  const int nn = N[d], na = N[da], nb = N[db];
-  const int tn = (nn + 1 + TN - 1) / TN, ta = (na + TA - 1) / TA;
-  const int n0 = (lt % tn) * TN, a0 = ((lt / tn) % ta) * TA, b0 = (lt / (tn * ta)) * TB;
-  const double* __restrict__ Wsrc = (stage == 1) ? P.W : P.Ws;
-
-  // ---- phase 1: cells (frame components: rho, m_d, m_da, m_db, E)
-  for (int e = tid; e < CN * CA * CB; e += 256) {
-    const int cn = e % CN, ca = (e / CN) % CA, cb = e / (CN * CA);
-    int ix[3];
-    ix[d] = n0 - 3 + cn;
-    ix[da] = a0 - 2 + ca;
-    ix[db] = b0 - 2 + cb;
-    double q[5];
-    load_cell3(P, Wsrc, ix[0], ix[1], ix[2], q);
-    sW[0][cb][ca][cn] = T(q[0]);
-    sW[1][cb][ca][cn] = T(q[1 + d]);
-    sW[2][cb][ca][cn] = T(q[1 + da]);
-    sW[3][cb][ca][cn] = T(q[1 + db]);
-    sW[4][cb][ca][cn] = T(q[4]);
-  }
-  __syncthreads();
-
-  // ---- phase 2: normal reconstruction of every line (tangential halo 2) at the TN faces
-  const T gam = T(P.gamma), ghi = T(P.ghi), glo = T(P.glo), eps = T(P.eps);
-  const double hh[3] = {P.dx, P.dy, P.dz};
-  const T ihn = T(1.0 / hh[d]), iha = T(1.0 / hh[da]), ihb = T(1.0 / hh[db]);
-  for (int e = tid; e < CA * CB * TN; e += 256) {
-    const int kl = e % TN, al = (e / TN) % CA, bl = e / (TN * CA);
-    T q6[6][5];
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) q6[m][v] = sW[v][bl][al][kl + m];
-    int ixl[3], ixr[3];
-    ixl[d] = n0 + kl - 1; ixl[da] = a0 - 2 + al; ixl[db] = b0 - 2 + bl;
-    ixr[d] = n0 + kl;     ixr[da] = ixl[da];     ixr[db] = ixl[db];
-    const int fl = (flag3_at(P, ixl[0], ixl[1], ixl[2]) >> d) & 1;
-    const int fr = (flag3_at(P, ixr[0], ixr[1], ixr[2]) >> d) & 1;
-    T out[20];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      out[v] = (T(2) * q6[0][v] - T(13) * q6[1][v] + T(47) * q6[2][v] + T(27) * q6[3][v] - T(3) * q6[4][v]) *
-               T(1.0 / 60.0);
-      const T sl = (q6[1][v] - T(15) * q6[2][v] + T(15) * q6[3][v] - q6[4][v]) * (T(1.0 / 12.0) * ihn);
-      out[5 + v] = sl;
-      out[15 + v] = sl;
-      out[10 + v] = (T(-3) * q6[1][v] + T(27) * q6[2][v] + T(47) * q6[3][v] - T(13) * q6[4][v] + T(2) * q6[5][v]) *
-                    T(1.0 / 60.0);
-    }
-    if (fl | fr) {
-      CharMat5<T> m;
-      T avg[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) avg[v] = T(0.5) * (q6[2][v] + q6[3][v]);
-      char_matrices5(avg, gam, 1, m);
-      T val[5], der[5];
-      if (fl) {
-        ao_vector5(reinterpret_cast<const T(*)[5]>(&q6[0][0]), m, 0, ghi, glo, eps, val, der);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) { out[v] = val[v]; out[5 + v] = der[v] * ihn; }
-      }
-      if (fr) {
-        ao_vector5(reinterpret_cast<const T(*)[5]>(&q6[1][0]), m, 1, ghi, glo, eps, val, der);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) { out[10 + v] = val[v]; out[15 + v] = der[v] * ihn; }
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < 20; ++v) sNR[bl][al][kl][v] = out[v];
-  }
-  __syncthreads();
-
-  // ---- phase 3: Gauss point (g1, g2) of face (kl, al, bl)
-  const int f = tid >> 2, g = tid & 3, g1 = g & 1, g2 = g >> 1;
-  const int kl = f % TN, al = (f / TN) % TA, bl = f / (TN * TA);
-  const int n = n0 + kl, a = a0 + al, bb = b0 + bl;
-  if (n > nn || a >= na || bb >= nb) return;  // the four lanes of a face leave together
-
-  FluxParams fp;
-  fp.gamma = P.gamma; fp.K = P.K; fp.mu = P.mu; fp.Pr = P.Pr; fp.c1 = P.c1; fp.c2 = P.c2;
-  fp.Kp2 = P.Kp2; fp.iKp2 = P.iKp2; fp.kpr = P.kpr;
-  fp.dt = tsp.dt; fp.dth = tsp.dth; fp.idt = tsp.idt; fp.idt2 = tsp.idt2;
-  fp.ns = P.ns; fp.want_F = (stage == 1);
-  const T K = T(P.K), Kp3 = T(P.K + 3.0), iKp3 = T(1.0 / (P.K + 3.0));
-  FluxAcc3<T> acc;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    int ix[3];
-    ix[d] = n - 1 + s;
-    ix[da] = a;
-    const int ov = 10 * s, od = 10 * s + 5;
-    // sweep 1 along da on the five db-rows, at Gauss coordinate g1: values and da-derivatives of W^s
-    T V[5][5], D[5][5], Wp[5], Wn[5], Wa[5], Wb[5];
-#pragma unroll
-    for (int r2 = 0; r2 < 5; ++r2) {
-      ix[db] = bb - 2 + r2;
-      const int fa = (flag3_at(P, ix[0], ix[1], ix[2]) >> da) & 1;
-      if (fa) {
-        CharMat5<T> m;
-        T own[5], qv[5][5], val[5], der[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) own[v] = sNR[bl + r2][al + 2][kl][ov + v];
-        char_matrices5(own, gam, 2, m);
-#pragma unroll
-        for (int r = 0; r < 5; ++r)
-#pragma unroll
-          for (int v = 0; v < 5; ++v) qv[r][v] = sNR[bl + r2][al + r][kl][ov + v];
-        ao_vector5(qv, m, 2 + g1, ghi, glo, eps, val, der);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) { V[r2][v] = val[v]; D[r2][v] = der[v] * iha; }
-      } else {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          T q[5], vv, dd;
-#pragma unroll
-          for (int r = 0; r < 5; ++r) q[r] = sNR[bl + r2][al + r][kl][ov + v];
-          gauss_linear(q, g1, vv, dd);
-          V[r2][v] = vv;
-          D[r2][v] = dd * iha;
-        }
-      }
-    }
-    // sweep 2 along db at g2 (flag of the side cell along db, characteristic state of the sweep's centre)
-    ix[db] = bb;
-    const int fb = (flag3_at(P, ix[0], ix[1], ix[2]) >> db) & 1;
-    CharMat5<T> m2;
-    if (fb) {
-      char_matrices5(V[2], gam, 3, m2);
-      T der[5], tmp[5];
-      ao_vector5(V, m2, 2 + g2, ghi, glo, eps, Wp, der);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Wb[v] = der[v] * ihb;
-      ao_vector5(D, m2, 2 + g2, ghi, glo, eps, Wa, tmp);
-    } else {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        T q[5], vv, dd;
-#pragma unroll
-        for (int r = 0; r < 5; ++r) q[r] = V[r][v];
-        gauss_linear(q, g2, vv, dd);
-        Wp[v] = vv;
-        Wb[v] = dd * ihb;
-#pragma unroll
-        for (int r = 0; r < 5; ++r) q[r] = D[r][v];
-        gauss_linear(q, g2, vv, dd);
-        Wa[v] = vv;
-      }
-    }
-    // the normal slopes W_n^s through the same two sweeps (values only)
-#pragma unroll
-    for (int r2 = 0; r2 < 5; ++r2) {
-      ix[db] = bb - 2 + r2;
-      const int fa = (flag3_at(P, ix[0], ix[1], ix[2]) >> da) & 1;
-      if (fa) {
-        CharMat5<T> m;
-        T own[5], qv[5][5], val[5], der[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) own[v] = sNR[bl + r2][al + 2][kl][ov + v];
-        char_matrices5(own, gam, 2, m);
-#pragma unroll
-        for (int r = 0; r < 5; ++r)
-#pragma unroll
-          for (int v = 0; v < 5; ++v) qv[r][v] = sNR[bl + r2][al + r][kl][od + v];
-        ao_vector5(qv, m, 2 + g1, ghi, glo, eps, val, der);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) V[r2][v] = val[v];
-      } else {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          T q[5], vv, dd;
-#pragma unroll
-          for (int r = 0; r < 5; ++r) q[r] = sNR[bl + r2][al + r][kl][od + v];
-          gauss_linear(q, g1, vv, dd);
-          V[r2][v] = vv;
-        }
-      }
-    }
-    if (fb) {
-      T der[5];
-      ao_vector5(V, m2, 2 + g2, ghi, glo, eps, Wn, der);
-    } else {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        T q[5], vv, dd;
-#pragma unroll
-        for (int r = 0; r < 5; ++r) q[r] = V[r][v];
-        gauss_linear(q, g2, vv, dd);
-        Wn[v] = vv;
-      }
-    }
-    if (s == 0) flux3_side<0>(Wp, Wn, Wa, Wb, gam, K, Kp3, iKp3, acc);
-    else flux3_side<1>(Wp, Wn, Wa, Wb, gam, K, Kp3, iKp3, acc);
-  }
-  T F[5] = {0, 0, 0, 0, 0}, dF[5] = {0, 0, 0, 0, 0};
-  flux3_finish(acc, fp, Kp3, iKp3, T(0.25), F, dF);
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    F[v] += __shfl_xor(F[v], 1, 64);
-    F[v] += __shfl_xor(F[v], 2, 64);
-    dF[v] += __shfl_xor(dF[v], 1, 64);
-    dF[v] += __shfl_xor(dF[v], 2, 64);
-  }
-  if (g != 0) return;
-  // grid component of each frame slot; the second stage's dF/dt goes to the F arrays (as in 2D)
-  void* Fv[3] = {P.Fx, P.Fy, P.Fz};
-  void* Gv[3] = {P.Gx, P.Gy, P.Gz};
-  T* Fo = reinterpret_cast<T*>(Fv[d]);
-  T* Go = reinterpret_cast<T*>(stage == 1 ? Gv[d] : Fv[d]);
-  int ix[3];
-  ix[d] = n; ix[da] = a; ix[db] = bb;
-  const int M0 = P.nx + (d == 0), M1 = P.ny + (d == 1), M2 = P.nz + (d == 2);
-  const size_t plane = (size_t)M0 * M1 * M2;
-  const size_t o = ((size_t)ix[2] * M1 + ix[1]) * M0 + ix[0];
-  const int gc[5] = {0, 1 + d, 1 + da, 1 + db, 4};
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    if (stage == 1) Fo[gc[v] * plane + o] = F[v];
-    Go[gc[v] * plane + o] = dF[v];
-  }
-}
-
-__device__ inline double cfl_quantity3(const ProbDev& P, double rho, double mx, double my, double mz, double E) {
-#pragma clang fp contract(off)
-  const double U = mx / rho, V = my / rho, Z = mz / rho;
-  const double pr = (P.gamma - 1.0) * (E - 0.5 * rho * (U * U + V * V + Z * Z));
-  const double c = sqrt(P.gamma * pr / rho);
-  double q = P.h / (sqrt(U * U + V * V + Z * Z) + c);
-  if (P.ns) q = fmin(q, (P.h * P.h) / (4.0 * (P.mu / rho)));
-  return q;
-}
-
-__global__ void __launch_bounds__(256) k_cfl3(const ProbDev* __restrict__ probs, const int* __restrict__ off,
-                                              int nprob, double* __restrict__ qpart) {
-  const int p = find_prob(off, nprob, blockIdx.x);
-  const ProbDev& P = probs[p];
-  const size_t ncell = (size_t)P.nx * P.ny * P.nz;
-  const size_t cell = (size_t)(blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
-  double q = __builtin_inf();
-  if (cell < ncell) {
-    const double* W = P.W;
-    q = cfl_quantity3(P, W[cell], W[ncell + cell], W[2 * ncell + cell], W[3 * ncell + cell], W[4 * ncell + cell]);
-  }
-  q = block_min(q);
-  if (threadIdx.x == 0) qpart[blockIdx.x] = q;
-}
-
-// S2O4 stage updates of a 3D problem (the same sums as k_update, over six faces)
-template <typename T>
-__global__ void __launch_bounds__(256) k_update3(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
-                                                 const int* __restrict__ off, int nprob, int stage,
-                                                 double* __restrict__ qpart) {
-  const int p = find_prob(off, nprob, blockIdx.x);
-  const ProbDev& P = probs[p];
-  TimeDev& tsp = ts[p];
-  if (!tsp.active) return;
-  const size_t ncell = (size_t)P.nx * P.ny * P.nz;
-  const size_t cell = (size_t)(blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
-  double q = __builtin_inf();
-  if (cell < ncell) {
-    const int i = (int)(cell % P.nx), j = (int)((cell / P.nx) % P.ny), k = (int)(cell / ((size_t)P.nx * P.ny));
-    const double dt = tsp.dt;
-    const double ih[3] = {1.0 / P.dx, 1.0 / P.dy, 1.0 / P.dz};
-    const T* Fa[3] = {reinterpret_cast<const T*>(P.Fx), reinterpret_cast<const T*>(P.Fy),
-                      reinterpret_cast<const T*>(P.Fz)};
-    const T* Ga[3] = {reinterpret_cast<const T*>(stage == 1 ? P.Gx : P.Fx),
-                      reinterpret_cast<const T*>(stage == 1 ? P.Gy : P.Fy),
-                      reinterpret_cast<const T*>(stage == 1 ? P.Gz : P.Fz)};
-    size_t plane[3], lo[3], step[3];
-    plane[0] = (size_t)P.nz * P.ny * (P.nx + 1); lo[0] = ((size_t)k * P.ny + j) * (P.nx + 1) + i; step[0] = 1;
-    plane[1] = (size_t)P.nz * (P.ny + 1) * P.nx; lo[1] = ((size_t)k * (P.ny + 1) + j) * P.nx + i; step[1] = P.nx;
-    plane[2] = (size_t)(P.nz + 1) * P.ny * P.nx; lo[2] = ((size_t)k * P.ny + j) * P.nx + i;
-    step[2] = (size_t)P.ny * P.nx;
-    double wn[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      double fs = 0.0, gs = 0.0;
-#pragma unroll
-      for (int dd = 0; dd < 3; ++dd) {
-        const size_t o = c * plane[dd] + lo[dd];
-        gs += (double(Ga[dd][o + step[dd]]) - double(Ga[dd][o])) * ih[dd];
-        if (stage == 1) fs += (double(Fa[dd][o + step[dd]]) - double(Fa[dd][o])) * ih[dd];
-      }
-      const double w = P.W[c * ncell + cell];
-      if (stage == 1) {
-        const double ws = w - dt * (0.5 * fs + 0.125 * dt * gs);
-        P.Ws[c * ncell + cell] = ws;
-        P.S[c * ncell + cell] = w - dt * (fs + dt / 6.0 * gs);
-        wn[c] = ws;
-      } else {
-        const double wnew = P.S[c * ncell + cell] - dt * dt / 3.0 * gs;
-        P.W[c * ncell + cell] = wnew;
-        wn[c] = wnew;
-      }
-    }
-    const double rho = wn[0];
-    const double pr = (P.gamma - 1.0) * (wn[4] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2] + wn[3] * wn[3]) / rho);
-    if (!(rho > 0.0) || !(pr > 0.0) || !(wn[4] < __builtin_inf())) atomicOr(&tsp.status, 1);
-    if (stage == 2) q = cfl_quantity3(P, wn[0], wn[1], wn[2], wn[3], wn[4]);
-  }
-  if (stage == 2) {
-    q = block_min(q);
-    if (threadIdx.x == 0) qpart[blockIdx.x] = q;
-  }
-}
-
 // ---------------------------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------------------------
@@ -1197,7 +771,7 @@ static inline unsigned nblk(int n, int b) { return (unsigned)((n + b - 1) / b); 
 
 void launch_cfl(const LaunchCtx& L) {
   if (L.dim == 3)
-    hipLaunchKernelGGL(k_cfl3, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.off_cell, L.nprob, L.qpart);
+    launch_cfl3(L);
   else
     hipLaunchKernelGGL(k_cfl, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.off_cell, L.nprob, L.qpart);
 }
@@ -1214,8 +788,7 @@ void launch_commit(const LaunchCtx& L, int use_tend) {
 void launch_flags(const LaunchCtx& L, int stage_state, int count, int clear) {
   if (clear) hipLaunchKernelGGL(k_clear_counts, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.probs, L.nprob);
   if (L.dim == 3)
-    hipLaunchKernelGGL(k_flags3, dim3(L.ext_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_ext, L.nprob,
-                       stage_state, count);
+    launch_flags3(L, stage_state, count);
   else if (L.dim == 2)
     hipLaunchKernelGGL(k_flags2d, dim3(L.ext_blocks), dim3(kFThreads), 0, L.stream, L.probs, L.ts, L.off_ext,
                        L.nprob, stage_state, count);
@@ -1287,12 +860,7 @@ static void launch_flux_t(const LaunchCtx& L, int stage, int* grid) {
 
 void launch_flux(const LaunchCtx& L, int stage) {
   if (L.dim == 3) {
-    if (L.fp32)
-      hipLaunchKernelGGL(k_flux3<float>, dim3(L.flux_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_flux,
-                         L.nprob, stage);
-    else
-      hipLaunchKernelGGL(k_flux3<double>, dim3(L.flux_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_flux,
-                         L.nprob, stage);
+    launch_flux3(L, stage);
     return;
   }
   if (L.fp32) launch_flux_t<float>(L, stage, nullptr);
@@ -1318,12 +886,7 @@ void launch_repair(const LaunchCtx& L) {
 
 void launch_update(const LaunchCtx& L, int stage) {
   if (L.dim == 3) {
-    if (L.fp32)
-      hipLaunchKernelGGL(k_update3<float>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
-                         L.nprob, stage, L.qpart);
-    else
-      hipLaunchKernelGGL(k_update3<double>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
-                         L.nprob, stage, L.qpart);
+    launch_update3(L, stage);
     return;
   }
   if (L.fp32)

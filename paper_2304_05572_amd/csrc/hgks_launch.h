@@ -61,5 +61,10 @@ void launch_flux(const LaunchCtx& L, int stage);
 int flux_persistent_grid(const LaunchCtx& L);  // blocks of the persistent flux launch for L's variant
 void launch_update(const LaunchCtx& L, int stage);
 void launch_repair(const LaunchCtx& L);
+// the 3D kernels (own source file; the launchers above dispatch to these when L.dim == 3)
+void launch_cfl3(const LaunchCtx& L);
+void launch_flags3(const LaunchCtx& L, int stage_state, int count);
+void launch_flux3(const LaunchCtx& L, int stage);
+void launch_update3(const LaunchCtx& L, int stage);
 
 }  // namespace hk
