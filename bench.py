@@ -424,7 +424,8 @@ def main():
                     f"dt equal {parity[name][2]}")
 
     if "fp64" not in res:
-        print(json.dumps({"metric": METRIC, "value": None, "note": "fp64 variant not run"}), flush=True)
+        print(json.dumps({"metric": METRIC, "value": None, "note": "fp64 variant not run",
+                          "variants": {"three_dimensional": res3}}), flush=True)
         return
     r = res["fp64"]
     gps = 2 * ((n + 1) * n * 2)  # two Gauss points on every x- and y-interface

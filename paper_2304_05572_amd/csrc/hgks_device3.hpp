@@ -230,99 +230,77 @@ __device__ inline void flux3_finish(FluxAcc3<T>& acc, const FluxParams& fp, T Kp
 }
 
 // ---------------------------------------------------------------------------------------------
-// Characteristic variables of the 3D Euler equations along frame slot d (1 normal, 2, 3 tangential):
-// R in closed form (columns u_d - c, entropy, the two shear waves, u_d + c), L = R^{-1} by Gauss-Jordan
-// elimination with partial pivoting (WENO-AO runs on troubled cells only).
+// Characteristic variables of the 3D Euler equations along frame slot D (1 normal, 2 and 3 tangential):
+// right eigenvectors R with columns u_D - c, entropy, the two shear waves (the other two slots in
+// ascending order, columns (0, e_k, u_k)), u_D + c; L = R^{-1} in closed form. Neither matrix is
+// stored: the projections are applied from nine scalars of the state, which keeps the troubled-cell
+// path's register footprint small.
 // ---------------------------------------------------------------------------------------------
 template <typename T>
-struct CharMat5 {
-  T R[5][5], L[5][5];
+struct Char5 {
+  T u[3], c, ic, H, b1, b2, hq2;
 };
 
 template <typename T>
-__device__ inline void char_matrices5(const T w[5], T gamma, int d, CharMat5<T>& m) {
+__device__ inline void char5(const T w[5], T gamma, Char5<T>& m) {
   const T ir = drcp(w[0]);
-  const T u[3] = {w[1] * ir, w[2] * ir, w[3] * ir};
-  const T q2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const T p = (gamma - 1) * (w[4] - T(0.5) * w[0] * q2);
-  const T c = dsqrt(gamma * p * ir);
-  const T H = (w[4] + p) * ir;
-  const int dd = d - 1;
-  for (int a = 0; a < 5; ++a)
-    for (int b = 0; b < 5; ++b) m.R[a][b] = 0;
-  m.R[0][0] = 1;
-  m.R[0][1] = 1;
-  m.R[0][4] = 1;
-  for (int k = 0; k < 3; ++k) {
-    m.R[1 + k][0] = u[k] - (k == dd ? c : T(0));
-    m.R[1 + k][1] = u[k];
-    m.R[1 + k][4] = u[k] + (k == dd ? c : T(0));
-  }
-  m.R[4][0] = H - u[dd] * c;
-  m.R[4][1] = T(0.5) * q2;
-  m.R[4][4] = H + u[dd] * c;
-  int col = 2;
-  for (int k = 0; k < 3; ++k) {
-    if (k == dd) continue;
-    m.R[1 + k][col] = 1;
-    m.R[4][col] = u[k];
-    ++col;
-  }
-  T A[5][10];
-  for (int a = 0; a < 5; ++a)
-    for (int b = 0; b < 5; ++b) {
-      A[a][b] = m.R[a][b];
-      A[a][5 + b] = (a == b) ? T(1) : T(0);
-    }
-  for (int k = 0; k < 5; ++k) {
-    int piv = k;
-    for (int a = k + 1; a < 5; ++a)
-      if (fabs(A[a][k]) > fabs(A[piv][k])) piv = a;
-    if (piv != k)
-      for (int b = 0; b < 10; ++b) { const T t = A[k][b]; A[k][b] = A[piv][b]; A[piv][b] = t; }
-    const T inv = T(1) / A[k][k];
-    for (int b = 0; b < 10; ++b) A[k][b] *= inv;
-    for (int a = 0; a < 5; ++a) {
-      if (a == k) continue;
-      const T f = A[a][k];
-      for (int b = 0; b < 10; ++b) A[a][b] -= f * A[k][b];
-    }
-  }
-  for (int a = 0; a < 5; ++a)
-    for (int b = 0; b < 5; ++b) m.L[a][b] = A[a][5 + b];
+  m.u[0] = w[1] * ir;
+  m.u[1] = w[2] * ir;
+  m.u[2] = w[3] * ir;
+  m.hq2 = T(0.5) * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
+  const T p = (gamma - 1) * (w[4] - w[0] * m.hq2);
+  m.c = dsqrt(gamma * p * ir);
+  m.ic = drcp(m.c);
+  m.H = (w[4] + p) * ir;
+  m.b1 = (gamma - 1) * m.ic * m.ic;
+  m.b2 = m.b1 * m.hq2;
 }
 
-// WENO-AO of a 5-vector in characteristic space; ev 0/1: face +1/2 / -1/2, ev 2/3: Gauss point -eta / +eta
-template <typename T>
-__device__ inline void ao_vector5(const T qc[5][5], const CharMat5<T>& m, int ev, T ghi, T glo, T eps, T val[5],
+// L q: (acoustic -, entropy, shear, shear, acoustic +)
+template <int D, typename T>
+__device__ inline void to_char5(const Char5<T>& m, const T q[5], T out[5]) {
+  constexpr int t0 = (D == 1) ? 1 : 0, t1 = (D == 3) ? 1 : 2;  // the two other velocity slots (0-based)
+  const T um = m.u[0] * q[1] + m.u[1] * q[2] + m.u[2] * q[3];
+  const T A = m.b2 * q[0] - m.b1 * um + m.b1 * q[4];
+  const T X = m.ic * (m.u[D - 1] * q[0] - q[D]);
+  out[0] = T(0.5) * (A + X);
+  out[1] = q[0] - A;
+  out[2] = q[1 + t0] - m.u[t0] * q[0];
+  out[3] = q[1 + t1] - m.u[t1] * q[0];
+  out[4] = T(0.5) * (A - X);
+}
+
+// R cv
+template <int D, typename T>
+__device__ inline void from_char5(const Char5<T>& m, const T cv[5], T out[5]) {
+  constexpr int t0 = (D == 1) ? 1 : 0, t1 = (D == 3) ? 1 : 2;
+  const T s = cv[0] + cv[1] + cv[4], dl = cv[4] - cv[0];
+  out[0] = s;
+  out[1 + t0] = m.u[t0] * s + cv[2];
+  out[1 + t1] = m.u[t1] * s + cv[3];
+  out[D] = m.u[D - 1] * s + m.c * dl;
+  out[4] = m.H * (cv[0] + cv[4]) + m.u[D - 1] * m.c * dl + m.hq2 * cv[1] + m.u[t0] * cv[2] + m.u[t1] * cv[3];
+}
+
+// WENO-AO of a 5-vector in the characteristic variables of slot D; ev 0/1: face +1/2 / -1/2, ev 2/3: Gauss
+// point -eta / +eta. Value and xi-derivative.
+template <int D, typename T>
+__device__ inline void ao_vector5(const T qc[5][5], const Char5<T>& m, int ev, T ghi, T glo, T eps, T val[5],
                                   T der[5]) {
-  T cv[5], cd[5];
+  T ch[5][5], cv[5], cd[5];
+#pragma unroll
+  for (int r = 0; r < 5; ++r) to_char5<D>(m, qc[r], ch[r]);
+#pragma unroll
   for (int k = 0; k < 5; ++k) {
-    T q[5];
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
-      T s = 0;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) s += m.L[k][c] * qc[r][c];
-      q[r] = s;
-    }
+    const T q[5] = {ch[0][k], ch[1][k], ch[2][k], ch[3][k], ch[4][k]};
     T beta[4], pv[4], pd[4];
     smoothness(q, beta);
     if (ev < 2) face_polys(q, ev, pv, pd);
     else gauss_polys(q, ev - 2, pv, pd);
     ao_combine(beta, pv, pd, ghi, glo, eps, cv[k], cd[k]);
   }
-#pragma unroll
-  for (int a = 0; a < 5; ++a) {
-    T sv = 0, sd = 0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      sv += m.R[a][k] * cv[k];
-      sd += m.R[a][k] * cd[k];
-    }
-    val[a] = sv;
-    der[a] = sd;
-  }
+  from_char5<D>(m, cv, val);
+  from_char5<D>(m, cd, der);
 }
 
 // Cell (i, j, k) of a 3D state with ghost synthesis (periodic, zero-gradient, slip wall, no-slip

@@ -65,71 +65,107 @@ __device__ inline uint8_t flag3_at(const ProbDev& P, int i, int j, int k) {
   return P.flags[((size_t)(k + 2) * (P.ny + 4) + (j + 2)) * (P.nx + 4) + (i + 2)];
 }
 
-// One block per tile of kTN3 x kTA3 x kTB3 faces of one direction: phase 1 stages the cells in frame
-// components, phase 2 reconstructs every line along the normal (both sides, values and normal slopes),
-// phase 3 gives each thread one of the 2 x 2 Gauss points of a face: the two tangential sweeps of each
-// side, then the gas-kinetic flux; the four points of a face are averaged with lane exchanges.
+// Grid indices (i, j, k) of frame indices (along d, along d+1, along d+2): selects rather than arrays
+// indexed by d, which would live in scratch memory.
+__device__ inline void grid_of_frame(int d, int n, int a, int b, int& i, int& j, int& k) {
+  i = d == 0 ? n : (d == 2 ? a : b);
+  j = d == 1 ? n : (d == 0 ? a : b);
+  k = d == 2 ? n : (d == 1 ? a : b);
+}
+
+__device__ inline int sel3(int d, int x, int y, int z) { return d == 0 ? x : (d == 1 ? y : z); }
+__device__ inline double sel3(int d, double x, double y, double z) { return d == 0 ? x : (d == 1 ? y : z); }
+
+// Linear (fifth-order) or, on a troubled side cell, WENO-AO reconstruction of five 5-vectors q[r] along one
+// tangential axis at Gauss point gp (0: -eta, 1: +eta): value and xi-derivative.
+template <int D, typename T>
+__device__ inline void sweep5(const T q[5][5], int troubled, const Char5<T>& m, int gp, T ghi, T glo, T eps,
+                              T val[5], T der[5]) {
+  if (troubled) {
+    ao_vector5<D>(q, m, 2 + gp, ghi, glo, eps, val, der);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const T c[5] = {q[0][v], q[1][v], q[2][v], q[3][v], q[4][v]};
+      gauss_linear(c, gp, val[v], der[v]);
+    }
+  }
+}
+
+// One block per tile of kTN3 x kTA3 x kTB3 faces of one direction d (tangential axes da = d+1, db = d+2):
+//  1. the block's cells, in frame components (rho, m_d, m_da, m_db, E), into LDS;
+//  2. every line along d reconstructed at the tile's faces (both sides: values and normal slopes), for the
+//     TA + 4 x TB + 4 lines the tangential sweeps need;
+//  3. per side of the faces: (a) sweep 1 along da at the two Gauss coordinates, once per row of the tile
+//     and its db-halo, into LDS (each result serves the five faces along db whose stencils hold the row);
+//     (b) each thread takes one Gauss point (g1, g2) of a face: sweep 2 along db over five rows of (a),
+//     then that side's part of the gas-kinetic flux;
+//  4. the flux and its time derivative, averaged over the four Gauss points with lane exchanges.
+// LDS: 72 KiB in FP64, so two blocks share a CU; the register allocator works to two waves per SIMD (in
+// FP64 it spills a little, which measures faster than one wave per SIMD without spills).
 template <typename T>
-__global__ void __launch_bounds__(256) k_flux3(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_flux3(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
                                                const int* __restrict__ off, int nprob, int stage) {
   constexpr int TN = kTN3, TA = kTA3, TB = kTB3;
+  static_assert(TN == 4 && TA == 4 && TB == 4, "thread mappings below assume 4 x 4 x 4 faces and 256 threads");
   constexpr int CN = TN + 5, CA = TA + 4, CB = TB + 4;  // staged cells: normal -3..TN+1, tangential -2..T+1
-  constexpr int NRS = 21;                              // 20 values per line-interface, padded
-  __shared__ T sW[5][CB][CA][CN];
+  constexpr int NRS = 21;  // 20 values per line and face, odd stride: conflict-free 8-byte LDS reads
+  constexpr int S1 = 15;   // per sweep-1 result: value, da-derivative, value of the normal slope
+  constexpr int NW = 5 * CB * CA * CN, NS1 = CB * TA * TN * 2 * S1;
   __shared__ T sNR[CB][CA][TN][NRS];
+  __shared__ T sU[NW > NS1 ? NW : NS1];  // cells (phases 1-2), then one side's sweep-1 results (phase 3)
+#define SW(v, cb, ca, cn) sU[(((v) * CB + (cb)) * CA + (ca)) * CN + (cn)]
   const int b = xcd_swizzle(blockIdx.x, gridDim.x);
   const int p = find_prob(off, nprob, b);
   const ProbDev& P = probs[p];
   const TimeDev& tsp = ts[p];
   if (!tsp.active) return;
   const int tid = threadIdx.x;
-  const int N[3] = {P.nx, P.ny, P.nz};
   int lt = b - off[p];
-  int d = 0, nt = 0;
-  for (; d < 3; ++d) {
-    nt = ((N[d] + 1 + TN - 1) / TN) * ((N[(d + 1) % 3] + TA - 1) / TA) * ((N[(d + 2) % 3] + TB - 1) / TB);
-    if (lt < nt) break;
-    lt -= nt;
+  int d = 0;
+  {
+    const int nt0 = ((P.nx + TN) / TN) * ((P.ny + TA - 1) / TA) * ((P.nz + TB - 1) / TB);
+    const int nt1 = ((P.ny + TN) / TN) * ((P.nz + TA - 1) / TA) * ((P.nx + TB - 1) / TB);
+    if (lt >= nt0) { lt -= nt0; d = 1; }
+    if (d == 1 && lt >= nt1) { lt -= nt1; d = 2; }
   }
   const int da = (d + 1) % 3, db = (d + 2) % 3;
-  const int nn = N[d], na = N[da], nb = N[db];
+  const int nn = sel3(d, P.nx, P.ny, P.nz), na = sel3(da, P.nx, P.ny, P.nz), nb = sel3(db, P.nx, P.ny, P.nz);
   const int tn = (nn + 1 + TN - 1) / TN, ta = (na + TA - 1) / TA;
   const int n0 = (lt % tn) * TN, a0 = ((lt / tn) % ta) * TA, b0 = (lt / (tn * ta)) * TB;
   const double* __restrict__ Wsrc = (stage == 1) ? P.W : P.Ws;
 
-  // ---- phase 1: cells (frame components: rho, m_d, m_da, m_db, E)
+  // ---- 1: cells
   for (int e = tid; e < CN * CA * CB; e += 256) {
     const int cn = e % CN, ca = (e / CN) % CA, cb = e / (CN * CA);
-    int ix[3];
-    ix[d] = n0 - 3 + cn;
-    ix[da] = a0 - 2 + ca;
-    ix[db] = b0 - 2 + cb;
+    int i, j, k;
+    grid_of_frame(d, n0 - 3 + cn, a0 - 2 + ca, b0 - 2 + cb, i, j, k);
     double q[5];
-    load_cell3(P, Wsrc, ix[0], ix[1], ix[2], q);
-    sW[0][cb][ca][cn] = T(q[0]);
-    sW[1][cb][ca][cn] = T(q[1 + d]);
-    sW[2][cb][ca][cn] = T(q[1 + da]);
-    sW[3][cb][ca][cn] = T(q[1 + db]);
-    sW[4][cb][ca][cn] = T(q[4]);
+    load_cell3(P, Wsrc, i, j, k, q);
+    SW(0, cb, ca, cn) = T(q[0]);
+    SW(1, cb, ca, cn) = T(sel3(d, q[1], q[2], q[3]));
+    SW(2, cb, ca, cn) = T(sel3(da, q[1], q[2], q[3]));
+    SW(3, cb, ca, cn) = T(sel3(db, q[1], q[2], q[3]));
+    SW(4, cb, ca, cn) = T(q[4]);
   }
   __syncthreads();
 
-  // ---- phase 2: normal reconstruction of every line (tangential halo 2) at the TN faces
+  // ---- 2: normal reconstruction, one line and face per thread (CA * CB * TN = 256)
   const T gam = T(P.gamma), ghi = T(P.ghi), glo = T(P.glo), eps = T(P.eps);
-  const double hh[3] = {P.dx, P.dy, P.dz};
-  const T ihn = T(1.0 / hh[d]), iha = T(1.0 / hh[da]), ihb = T(1.0 / hh[db]);
-  for (int e = tid; e < CA * CB * TN; e += 256) {
-    const int kl = e % TN, al = (e / TN) % CA, bl = e / (TN * CA);
+  const T ihn = T(1.0 / sel3(d, P.dx, P.dy, P.dz)), iha = T(1.0 / sel3(da, P.dx, P.dy, P.dz)),
+          ihb = T(1.0 / sel3(db, P.dx, P.dy, P.dz));
+  {
+    const int kl = tid % TN, al = (tid / TN) % CA, bl = tid / (TN * CA);
     T q6[6][5];
 #pragma unroll
     for (int m = 0; m < 6; ++m)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q6[m][v] = sW[v][bl][al][kl + m];
-    int ixl[3], ixr[3];
-    ixl[d] = n0 + kl - 1; ixl[da] = a0 - 2 + al; ixl[db] = b0 - 2 + bl;
-    ixr[d] = n0 + kl;     ixr[da] = ixl[da];     ixr[db] = ixl[db];
-    const int fl = (flag3_at(P, ixl[0], ixl[1], ixl[2]) >> d) & 1;
-    const int fr = (flag3_at(P, ixr[0], ixr[1], ixr[2]) >> d) & 1;
+      for (int v = 0; v < 5; ++v) q6[m][v] = SW(v, bl, al, kl + m);
+    int i, j, k;
+    grid_of_frame(d, n0 + kl - 1, a0 - 2 + al, b0 - 2 + bl, i, j, k);
+    const int fl = (flag3_at(P, i, j, k) >> d) & 1;
+    grid_of_frame(d, n0 + kl, a0 - 2 + al, b0 - 2 + bl, i, j, k);
+    const int fr = (flag3_at(P, i, j, k) >> d) & 1;
     T out[20];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -142,19 +178,19 @@ __global__ void __launch_bounds__(256) k_flux3(const ProbDev* __restrict__ probs
                     T(1.0 / 60.0);
     }
     if (fl | fr) {
-      CharMat5<T> m;
+      Char5<T> m;
       T avg[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) avg[v] = T(0.5) * (q6[2][v] + q6[3][v]);
-      char_matrices5(avg, gam, 1, m);
+      char5(avg, gam, m);
       T val[5], der[5];
       if (fl) {
-        ao_vector5(reinterpret_cast<const T(*)[5]>(&q6[0][0]), m, 0, ghi, glo, eps, val, der);
+        ao_vector5<1>(reinterpret_cast<const T(*)[5]>(&q6[0][0]), m, 0, ghi, glo, eps, val, der);
 #pragma unroll
         for (int v = 0; v < 5; ++v) { out[v] = val[v]; out[5 + v] = der[v] * ihn; }
       }
       if (fr) {
-        ao_vector5(reinterpret_cast<const T(*)[5]>(&q6[1][0]), m, 1, ghi, glo, eps, val, der);
+        ao_vector5<1>(reinterpret_cast<const T(*)[5]>(&q6[1][0]), m, 1, ghi, glo, eps, val, der);
 #pragma unroll
         for (int v = 0; v < 5; ++v) { out[10 + v] = val[v]; out[15 + v] = der[v] * ihn; }
       }
@@ -164,127 +200,86 @@ __global__ void __launch_bounds__(256) k_flux3(const ProbDev* __restrict__ probs
   }
   __syncthreads();
 
-  // ---- phase 3: Gauss point (g1, g2) of face (kl, al, bl)
+  // ---- 3: per side, sweep 1 (one result per thread: row irb, column ial, face ikl, coordinate ig1), then
+  // sweep 2 + flux at Gauss point (g1, g2) of face (kl, al, bl)
+  const int ig1 = tid & 1, ikl = (tid >> 1) & 3, ial = (tid >> 3) & 3, irb = tid >> 5;
   const int f = tid >> 2, g = tid & 3, g1 = g & 1, g2 = g >> 1;
   const int kl = f % TN, al = (f / TN) % TA, bl = f / (TN * TA);
   const int n = n0 + kl, a = a0 + al, bb = b0 + bl;
-  if (n > nn || a >= na || bb >= nb) return;  // the four lanes of a face leave together
+  const bool valid = n <= nn && a < na && bb < nb;  // the four lanes of a face agree
+  const T K = T(P.K), Kp3 = T(P.K + 3.0), iKp3 = T(1.0 / (P.K + 3.0));
+  FluxAcc3<T> acc;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (s == 1) __syncthreads();  // side 0's sweep-2 reads are done before side 1's results overwrite them
+    {
+      int i, j, k;
+      grid_of_frame(d, n0 + ikl - 1 + s, a0 + ial, b0 - 2 + irb, i, j, k);
+      const int fa = (flag3_at(P, i, j, k) >> da) & 1;
+      Char5<T> m;
+      if (fa) {
+        T own[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) own[v] = sNR[irb][ial + 2][ikl][10 * s + v];
+        char5(own, gam, m);
+      }
+      T q[5][5], val[5], der[5];
+      T* o = &sU[tid * S1];
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[r][v] = sNR[irb][ial + r][ikl][10 * s + v];
+      sweep5<2>(q, fa, m, ig1, ghi, glo, eps, val, der);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) { o[v] = val[v]; o[5 + v] = der[v] * iha; }
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[r][v] = sNR[irb][ial + r][ikl][10 * s + 5 + v];
+      sweep5<2>(q, fa, m, ig1, ghi, glo, eps, val, der);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) o[10 + v] = val[v];
+    }
+    __syncthreads();
+    if (valid) {
+      int i, j, k;
+      grid_of_frame(d, n - 1 + s, a, bb, i, j, k);
+      const int fb = (flag3_at(P, i, j, k) >> db) & 1;
+      const T* row = &sU[((bl * TA + al) * TN + kl) * 2 * S1 + g1 * S1];
+      constexpr int RS = TA * TN * 2 * S1;  // next row along db
+      T q[5][5], Wp[5], Wn[5], Wa[5], Wb[5], der[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[r][v] = row[r * RS + v];
+      Char5<T> m;
+      if (fb) char5(q[2], gam, m);  // the sweep's centre value
+      sweep5<3>(q, fb, m, g2, ghi, glo, eps, Wp, der);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Wb[v] = der[v] * ihb;
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[r][v] = row[r * RS + 5 + v];
+      sweep5<3>(q, fb, m, g2, ghi, glo, eps, Wa, der);
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[r][v] = row[r * RS + 10 + v];
+      sweep5<3>(q, fb, m, g2, ghi, glo, eps, Wn, der);
+      if (s == 0) flux3_side<0>(Wp, Wn, Wa, Wb, gam, K, Kp3, iKp3, acc);
+      else flux3_side<1>(Wp, Wn, Wa, Wb, gam, K, Kp3, iKp3, acc);
+    }
+  }
+#undef SW
+  if (!valid) return;  // no barrier below
 
+  // ---- 4: the gas-kinetic flux of the Gauss point, averaged over the face's four lanes
   FluxParams fp;
   fp.gamma = P.gamma; fp.K = P.K; fp.mu = P.mu; fp.Pr = P.Pr; fp.c1 = P.c1; fp.c2 = P.c2;
   fp.Kp2 = P.Kp2; fp.iKp2 = P.iKp2; fp.kpr = P.kpr;
   fp.dt = tsp.dt; fp.dth = tsp.dth; fp.idt = tsp.idt; fp.idt2 = tsp.idt2;
   fp.ns = P.ns; fp.want_F = (stage == 1);
-  const T K = T(P.K), Kp3 = T(P.K + 3.0), iKp3 = T(1.0 / (P.K + 3.0));
-  FluxAcc3<T> acc;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    int ix[3];
-    ix[d] = n - 1 + s;
-    ix[da] = a;
-    const int ov = 10 * s, od = 10 * s + 5;
-    // sweep 1 along da on the five db-rows, at Gauss coordinate g1: values and da-derivatives of W^s
-    T V[5][5], D[5][5], Wp[5], Wn[5], Wa[5], Wb[5];
-#pragma unroll
-    for (int r2 = 0; r2 < 5; ++r2) {
-      ix[db] = bb - 2 + r2;
-      const int fa = (flag3_at(P, ix[0], ix[1], ix[2]) >> da) & 1;
-      if (fa) {
-        CharMat5<T> m;
-        T own[5], qv[5][5], val[5], der[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) own[v] = sNR[bl + r2][al + 2][kl][ov + v];
-        char_matrices5(own, gam, 2, m);
-#pragma unroll
-        for (int r = 0; r < 5; ++r)
-#pragma unroll
-          for (int v = 0; v < 5; ++v) qv[r][v] = sNR[bl + r2][al + r][kl][ov + v];
-        ao_vector5(qv, m, 2 + g1, ghi, glo, eps, val, der);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) { V[r2][v] = val[v]; D[r2][v] = der[v] * iha; }
-      } else {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          T q[5], vv, dd;
-#pragma unroll
-          for (int r = 0; r < 5; ++r) q[r] = sNR[bl + r2][al + r][kl][ov + v];
-          gauss_linear(q, g1, vv, dd);
-          V[r2][v] = vv;
-          D[r2][v] = dd * iha;
-        }
-      }
-    }
-    // sweep 2 along db at g2 (flag of the side cell along db, characteristic state of the sweep's centre)
-    ix[db] = bb;
-    const int fb = (flag3_at(P, ix[0], ix[1], ix[2]) >> db) & 1;
-    CharMat5<T> m2;
-    if (fb) {
-      char_matrices5(V[2], gam, 3, m2);
-      T der[5], tmp[5];
-      ao_vector5(V, m2, 2 + g2, ghi, glo, eps, Wp, der);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Wb[v] = der[v] * ihb;
-      ao_vector5(D, m2, 2 + g2, ghi, glo, eps, Wa, tmp);
-    } else {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        T q[5], vv, dd;
-#pragma unroll
-        for (int r = 0; r < 5; ++r) q[r] = V[r][v];
-        gauss_linear(q, g2, vv, dd);
-        Wp[v] = vv;
-        Wb[v] = dd * ihb;
-#pragma unroll
-        for (int r = 0; r < 5; ++r) q[r] = D[r][v];
-        gauss_linear(q, g2, vv, dd);
-        Wa[v] = vv;
-      }
-    }
-    // the normal slopes W_n^s through the same two sweeps (values only)
-#pragma unroll
-    for (int r2 = 0; r2 < 5; ++r2) {
-      ix[db] = bb - 2 + r2;
-      const int fa = (flag3_at(P, ix[0], ix[1], ix[2]) >> da) & 1;
-      if (fa) {
-        CharMat5<T> m;
-        T own[5], qv[5][5], val[5], der[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) own[v] = sNR[bl + r2][al + 2][kl][ov + v];
-        char_matrices5(own, gam, 2, m);
-#pragma unroll
-        for (int r = 0; r < 5; ++r)
-#pragma unroll
-          for (int v = 0; v < 5; ++v) qv[r][v] = sNR[bl + r2][al + r][kl][od + v];
-        ao_vector5(qv, m, 2 + g1, ghi, glo, eps, val, der);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) V[r2][v] = val[v];
-      } else {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          T q[5], vv, dd;
-#pragma unroll
-          for (int r = 0; r < 5; ++r) q[r] = sNR[bl + r2][al + r][kl][od + v];
-          gauss_linear(q, g1, vv, dd);
-          V[r2][v] = vv;
-        }
-      }
-    }
-    if (fb) {
-      T der[5];
-      ao_vector5(V, m2, 2 + g2, ghi, glo, eps, Wn, der);
-    } else {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        T q[5], vv, dd;
-#pragma unroll
-        for (int r = 0; r < 5; ++r) q[r] = V[r][v];
-        gauss_linear(q, g2, vv, dd);
-        Wn[v] = vv;
-      }
-    }
-    if (s == 0) flux3_side<0>(Wp, Wn, Wa, Wb, gam, K, Kp3, iKp3, acc);
-    else flux3_side<1>(Wp, Wn, Wa, Wb, gam, K, Kp3, iKp3, acc);
-  }
   T F[5] = {0, 0, 0, 0, 0}, dF[5] = {0, 0, 0, 0, 0};
   flux3_finish(acc, fp, Kp3, iKp3, T(0.25), F, dF);
 #pragma unroll
@@ -296,20 +291,18 @@ __global__ void __launch_bounds__(256) k_flux3(const ProbDev* __restrict__ probs
   }
   if (g != 0) return;
   // grid component of each frame slot; the second stage's dF/dt goes to the F arrays (as in 2D)
-  void* Fv[3] = {P.Fx, P.Fy, P.Fz};
-  void* Gv[3] = {P.Gx, P.Gy, P.Gz};
-  T* Fo = reinterpret_cast<T*>(Fv[d]);
-  T* Go = reinterpret_cast<T*>(stage == 1 ? Gv[d] : Fv[d]);
-  int ix[3];
-  ix[d] = n; ix[da] = a; ix[db] = bb;
+  T* Fo = reinterpret_cast<T*>(d == 0 ? P.Fx : (d == 1 ? P.Fy : P.Fz));
+  T* Go = stage == 1 ? reinterpret_cast<T*>(d == 0 ? P.Gx : (d == 1 ? P.Gy : P.Gz)) : Fo;
+  int i, j, k;
+  grid_of_frame(d, n, a, bb, i, j, k);
   const int M0 = P.nx + (d == 0), M1 = P.ny + (d == 1), M2 = P.nz + (d == 2);
   const size_t plane = (size_t)M0 * M1 * M2;
-  const size_t o = ((size_t)ix[2] * M1 + ix[1]) * M0 + ix[0];
-  const int gc[5] = {0, 1 + d, 1 + da, 1 + db, 4};
+  const size_t o = ((size_t)k * M1 + j) * M0 + i;
+  const size_t oc[5] = {0, (size_t)(1 + d) * plane, (size_t)(1 + da) * plane, (size_t)(1 + db) * plane, 4 * plane};
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    if (stage == 1) Fo[gc[v] * plane + o] = F[v];
-    Go[gc[v] * plane + o] = dF[v];
+    if (stage == 1) Fo[oc[v] + o] = F[v];
+    Go[oc[v] + o] = dF[v];
   }
 }
 
