@@ -60,6 +60,14 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def kernel3_hash():
+    h = hashlib.sha256()
+    for f in ("hgks_kernels3.hip", "hgks_device3.hpp", "hgks_device.hpp", "hgks_grid.hpp"):
+        with open(os.path.join(ROOT, "paper_2304_05572_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def read_profile_table(name):
     """key value pairs of a committed profile summary (profiles/<name>), or {}."""
     path = os.path.join(ROOT, "profiles", name)
@@ -200,6 +208,16 @@ def time_3d(H, wl, n, seed, steps, warmup):
                      "kernel": "k_flux3<%s>" % ("double" if prec == H.FP64 else "float"),
                      "flagged_x": stats[0]["flagged_x"], "flagged_y": stats[0]["flagged_y"]}
         log(f"[bench] 3d {name}: {out[name]['value']:.1f} Mcell-updates/s, flux {flux_ms:.3f} ms/launch")
+    # roofline of the FP64 kernel: FP64 operations per Gauss point from the committed counter summary of the
+    # 128^3 problem (valid for its sources; the troubled fraction of other sizes differs)
+    t3 = read_profile_table("k_flux3_traffic_oct128_fp64.txt")
+    r = out["fp64"]
+    if t3.get("kernel3_hash") == kernel3_hash() and int(t3.get("n", 0)) == n and r["flux_ms_per_launch"] > 0:
+        fl = float(t3["flops_per_gauss_point"])
+        ach = fl * r["gauss_points_per_launch"] / (r["flux_ms_per_launch"] * 1e-3) / 1e12
+        r["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                         "frac": ach / PEAK_FP64_VALU, "traffic": float(t3["bytes_per_launch"]),
+                         "flops_per_gauss_point": fl, "traffic_unit": "bytes per launch"}
     return out
 
 

@@ -28,6 +28,18 @@ __device__ inline void maxw3_prims(const T w[5], T gamma, Maxw3<T>& g) {
   g.lam = T(0.5) * w[0] * drcp(p);
 }
 
+// <u^n>, n <= 6, over the half line u > 0 (half = 1) or u < 0 (half = -1)
+template <typename T>
+__device__ inline void maxw3_half_u(const Maxw3<T>& g, int half, T Mh[7]) {
+  const T s = T(0.5) * drcp(g.lam);
+  const T sl = dsqrt(g.lam);
+  const T hs = T(half);
+  Mh[0] = T(0.5) * derfc(-hs * sl * g.U);
+  Mh[1] = g.U * Mh[0] + hs * T(0.5) * dexp(-g.lam * g.U * g.U) * drcp(sl * T(1.7724538509055160273));
+#pragma unroll
+  for (int n = 0; n < 5; ++n) Mh[n + 2] = g.U * Mh[n + 1] + T(n + 1) * s * Mh[n];
+}
+
 template <typename T>
 __device__ inline void maxw3_moments(Maxw3<T>& g, T K, int half) {
   const T s = T(0.5) * drcp(g.lam);
@@ -55,10 +67,11 @@ __device__ inline void maxw3_moments(Maxw3<T>& g, T K, int half) {
   g.X2 = K * (K + 2) * s * s;
 }
 
-// <u^N v^M w^L a psi> with a = a0 + a1 u + a2 v + a3 w + a4 (u^2 + v^2 + w^2 + xi^2)/2
+// <u^N v^M w^L a psi> with a = a0 + a1 u + a2 v + a3 w + a4 (u^2 + v^2 + w^2 + xi^2)/2, the u-moments taken
+// from Mu (full or half line)
 template <int N, int M, int L, typename T>
-__device__ inline void mom3_a(const Maxw3<T>& g, const T a[5], T out[5]) {
-#define G(n, m, l) (g.Mu[n] * g.Mv[m] * g.Mw[l])
+__device__ inline void mom3_au(const Maxw3<T>& g, const T* Mu, const T a[5], T out[5]) {
+#define G(n, m, l) (Mu[n] * g.Mv[m] * g.Mw[l])
 #define SS(n, m, l) (T(0.5) * (G((n) + 2, m, l) + G(n, (m) + 2, l) + G(n, m, (l) + 2) + G(n, m, l) * g.X1))
   const T S0 = SS(N, M, L), Su = SS(N + 1, M, L), Sv = SS(N, M + 1, L), Sw = SS(N, M, L + 1);
   const T TT = T(0.25) * (G(N + 4, M, L) + G(N, M + 4, L) + G(N, M, L + 4) + G(N, M, L) * g.X2 +
@@ -76,13 +89,23 @@ __device__ inline void mom3_a(const Maxw3<T>& g, const T a[5], T out[5]) {
 #undef G
 }
 
+template <int N, int M, int L, typename T>
+__device__ inline void mom3_a(const Maxw3<T>& g, const T a[5], T out[5]) {
+  mom3_au<N, M, L>(g, g.Mu, a, out);
+}
+
+template <int N, typename T>
+__device__ inline void mom3_psiu(const Maxw3<T>& g, const T* Mu, T out[5]) {
+  out[0] = Mu[N];
+  out[1] = Mu[N + 1];
+  out[2] = Mu[N] * g.Mv[1];
+  out[3] = Mu[N] * g.Mw[1];
+  out[4] = T(0.5) * (Mu[N + 2] + Mu[N] * (g.Mv[2] + g.Mw[2] + g.X1));
+}
+
 template <int N, typename T>
 __device__ inline void mom3_psi(const Maxw3<T>& g, T out[5]) {
-  out[0] = g.Mu[N];
-  out[1] = g.Mu[N + 1];
-  out[2] = g.Mu[N] * g.Mv[1];
-  out[3] = g.Mu[N] * g.Mw[1];
-  out[4] = T(0.5) * (g.Mu[N + 2] + g.Mu[N] * (g.Mv[2] + g.Mw[2] + g.X1));
+  mom3_psiu<N>(g, g.Mu, out);
 }
 
 // a with <a psi> = b: closed-form inverse of the 5 x 5 moment matrix of g (N = K + 3 degrees of freedom
@@ -106,55 +129,63 @@ struct FluxAcc3 {
   T p_side[2];
 };
 
-// one side's contribution (S = 0: g_l over u > 0, initialises; S = 1: g_r over u < 0, adds)
+// one side's contribution (S = 0: g_l over u > 0, initialises; S = 1: g_r over u < 0, adds). The three
+// spatial slopes are taken one at a time: each adds its term of the time slope's right-hand side (full
+// moments) and its half-line moments to the accumulators before the next is solved.
 template <int S, typename T>
 __device__ inline void flux3_side(const T W[5], const T Wn[5], const T Wa[5], const T Wb[5], T gamma, T K, T Kp3,
                                   T iKp3, FluxAcc3<T>& acc) {
   Maxw3<T> g;
   maxw3_prims(W, gamma, g);
   acc.p_side[S] = T(0.5) * g.rho * drcp(g.lam);
-  const T ir = drcp(g.rho);
-  T b[5], an[5], aa[5], ab[5], A[5], t1[5], t2[5], t3[5];
+  const T ir = drcp(g.rho), rho = g.rho;
   maxw3_moments(g, K, 0);
+  T Mh[7];
+  maxw3_half_u(g, S ? -1 : 1, Mh);
+  auto put = [&](T (&dst)[5], const T x[5], bool init) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dst[c] = init ? rho * x[c] : dst[c] + rho * x[c];
+  };
+  T b[5], a[5], t[5], bA[5];
+  mom3_psiu<0>(g, Mh, t);
+  put(acc.Wc, t, S == 0);
+  // normal slope
 #pragma unroll
   for (int c = 0; c < 5; ++c) b[c] = Wn[c] * ir;
-  solve_slope3(g, Kp3, iKp3, b, an);
+  solve_slope3(g, Kp3, iKp3, b, a);
+  mom3_au<1, 0, 0>(g, g.Mu, a, bA);
+  mom3_au<0, 0, 0>(g, Mh, a, t);
+  put(acc.Wnc, t, S == 0);
+  mom3_au<2, 0, 0>(g, Mh, a, t);
+  put(acc.M5, t, S == 0);
+  // first tangential slope
 #pragma unroll
   for (int c = 0; c < 5; ++c) b[c] = Wa[c] * ir;
-  solve_slope3(g, Kp3, iKp3, b, aa);
+  solve_slope3(g, Kp3, iKp3, b, a);
+  mom3_au<0, 1, 0>(g, g.Mu, a, t);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) bA[c] += t[c];
+  mom3_au<0, 0, 0>(g, Mh, a, t);
+  put(acc.Wac, t, S == 0);
+  mom3_au<1, 1, 0>(g, Mh, a, t);
+  put(acc.M5, t, false);
+  // second tangential slope
 #pragma unroll
   for (int c = 0; c < 5; ++c) b[c] = Wb[c] * ir;
-  solve_slope3(g, Kp3, iKp3, b, ab);
-  mom3_a<1, 0, 0>(g, an, t1);
-  mom3_a<0, 1, 0>(g, aa, t2);
-  mom3_a<0, 0, 1>(g, ab, t3);
+  solve_slope3(g, Kp3, iKp3, b, a);
+  mom3_au<0, 0, 1>(g, g.Mu, a, t);
 #pragma unroll
-  for (int c = 0; c < 5; ++c) b[c] = -(t1[c] + t2[c] + t3[c]);
-  solve_slope3(g, Kp3, iKp3, b, A);
-  maxw3_moments(g, K, S ? -1 : 1);
-  const T rho = g.rho;
-  auto put = [&](T (&dst)[5], const T x[5]) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) dst[c] = (S == 0) ? rho * x[c] : dst[c] + rho * x[c];
-  };
-  mom3_psi<0>(g, t1);
-  put(acc.Wc, t1);
-  mom3_a<0, 0, 0>(g, an, t1);
-  put(acc.Wnc, t1);
-  mom3_a<0, 0, 0>(g, aa, t1);
-  put(acc.Wac, t1);
-  mom3_a<0, 0, 0>(g, ab, t1);
-  put(acc.Wbc, t1);
-  mom3_psi<1>(g, t1);
-  put(acc.M4a, t1);
-  mom3_a<1, 0, 0>(g, A, t1);
-  put(acc.M4b, t1);
-  mom3_a<2, 0, 0>(g, an, t1);
-  mom3_a<1, 1, 0>(g, aa, t2);
-  mom3_a<1, 0, 1>(g, ab, t3);
-#pragma unroll
-  for (int c = 0; c < 5; ++c) t1[c] += t2[c] + t3[c];
-  put(acc.M5, t1);
+  for (int c = 0; c < 5; ++c) bA[c] = -(bA[c] + t[c]);
+  mom3_au<0, 0, 0>(g, Mh, a, t);
+  put(acc.Wbc, t, S == 0);
+  mom3_au<1, 0, 1>(g, Mh, a, t);
+  put(acc.M5, t, false);
+  // time slope: <A psi> = -<(a u + b v + c w) psi>
+  solve_slope3(g, Kp3, iKp3, bA, a);
+  mom3_psiu<1>(g, Mh, t);
+  put(acc.M4a, t, S == 0);
+  mom3_au<1, 0, 0>(g, Mh, a, t);
+  put(acc.M4b, t, S == 0);
 }
 
 // equilibrium part, collision time and the time integrals: adds wgt * F and wgt * dF/dt
