@@ -93,6 +93,23 @@ typedef enum { HGKS_FP64 = 0, HGKS_FP32_BULK = 1 } hgks_precision;
  * one block per tile or as a persistent grid of co-resident blocks. */
 #define HGKS_NUM_LAUNCH_CONFIGS 12
 
+/* Time stepping (Sec. 2.2). stages == 0: the paper's two-stage fourth-order S2O4 (the default and the
+ * fast path). stages 1..3: a two-derivative multistage tableau, the family Sec. 2.2 places S2O4 in:
+ *   W^(i)   = W^n + sum_{j<i} (dt a[i][j] L(W^(j)) + dt^2 ah[i][j] L_t(W^(j)))
+ *   W^(n+1) = W^n + sum_i   (dt b[i]    L(W^(i)) + dt^2 bh[i]    L_t(W^(i)))
+ * where L and L_t are the negative divergence of the interface flux F and of dF/dt that the gas-kinetic
+ * flux of the stage state gives over a window of length dt (Sec. 2.2 steps (1)-(2)). Entries a[i][j],
+ * ah[i][j] with j >= i are ignored. Examples: stages 1, b = {1}, bh = {1/2} is the one-stage scheme
+ * (the flux integrated over the step, second order in time); stages 2, a[1][0] = 1/2, ah[1][0] = 1/8,
+ * b = {1, 0}, bh = {1/6, 1/3} is S2O4 again. Every problem of a handle takes the same stepper; stages
+ * >= 1 excludes prescribed-state sides, the positivity fallbacks and compensated accumulation. */
+typedef struct {
+  int32_t stages;
+  int32_t reserved;
+  double a[3][3], ah[3][3];
+  double b[3], bh[3];
+} hgks_stepper;
+
 /* One problem (Sec. 2 statement; parameters of Sec. 3). dim 1, 2 or 3. Three dimensions are the direct
  * extension the paper names: the same hybrid reconstruction along the face normal, then along the two
  * tangential directions in turn to the 2 x 2 Gauss points of each face, and the gas-kinetic flux with three
@@ -126,6 +143,7 @@ typedef struct {
   int32_t nz;                   /* dim == 3: cells along z on [z0, z1] (>= 5) and the kinds of the z-low and */
   double z0, z1;                /* z-high sides in bcz (periodic, outflow, reflect or no-slip; bc[0..3] hold  */
   int32_t bcz[2];               /* x and y). Ignored for dim 1 and 2. */
+  hgks_stepper stepper;         /* zero-initialised: S2O4 */
 } hgks_problem;
 
 typedef struct {

@@ -41,6 +41,34 @@ class BcData:
     rest: int = BC_PRESCRIBED
 
 
+class _Stepper(C.Structure):
+    _fields_ = [("stages", C.c_int32), ("pad", C.c_int32), ("a", (C.c_double * 3) * 3), ("ah", (C.c_double * 3) * 3),
+                ("b", C.c_double * 3), ("bh", C.c_double * 3)]
+
+
+@dataclasses.dataclass
+class Stepper:
+    """Two-derivative multistage tableau (Sec. 2.2's family): W^(i) = W^n + sum_{j<i} (dt a[i][j] L_j +
+    dt^2 ah[i][j] L_t,j), W^{n+1} = W^n + sum_i (dt b[i] L_i + dt^2 bh[i] L_t,i); stages 0 is the built-in
+    S2O4."""
+    stages: int = 0
+    a: tuple = ((0.0,) * 3,) * 3
+    ah: tuple = ((0.0,) * 3,) * 3
+    b: tuple = (0.0,) * 3
+    bh: tuple = (0.0,) * 3
+
+    def c_struct(self) -> _Stepper:
+        m = _Stepper()
+        m.stages = int(self.stages)
+        for i in range(3):
+            m.b[i] = float((list(self.b) + [0.0] * 3)[i])
+            m.bh[i] = float((list(self.bh) + [0.0] * 3)[i])
+            for j in range(3):
+                m.a[i][j] = float(self.a[i][j]) if i < len(self.a) and j < len(self.a[i]) else 0.0
+                m.ah[i][j] = float(self.ah[i][j]) if i < len(self.ah) and j < len(self.ah[i]) else 0.0
+        return m
+
+
 class _Problem(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
@@ -51,6 +79,7 @@ class _Problem(C.Structure):
         ("gamma_hi", C.c_double), ("gamma_lo", C.c_double), ("weno_eps", C.c_double),
         ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32), ("positivity", C.c_int32),
         ("bcd", _BcData * 4), ("nz", C.c_int32), ("z0", C.c_double), ("z1", C.c_double), ("bcz", C.c_int32 * 2),
+        ("stepper", _Stepper),
     ]
 
 
@@ -85,6 +114,7 @@ class Problem:
     z0: float = 0.0
     z1: float = 1.0
     bcz: tuple = (BC_OUTFLOW, BC_OUTFLOW)
+    stepper: object = None  # Stepper (or its fields as a dict); None: the built-in S2O4
 
     @property
     def nc(self) -> int:
@@ -105,6 +135,9 @@ class Problem:
                 s.bc = arr
             elif f.name == "bcz":
                 s.bcz = (C.c_int32 * 2)(*[int(b) for b in v])
+            elif f.name == "stepper":
+                if v is not None:
+                    s.stepper = (Stepper(**v) if isinstance(v, dict) else v).c_struct()
             elif f.name == "bcd":
                 for k, d in enumerate(list(v)[:4]):
                     if d is None:

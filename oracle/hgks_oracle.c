@@ -1101,9 +1101,12 @@ int oracle_stage_fluxes(const oracle_problem* p, const double* W, double t, doub
 
 static int step3(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken, int nthreads);
 
+static int step_ms(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken, int nthreads);
+
 int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken,
                 int nthreads) {
   oracle_init();
+  if (p->stepper.stages != 0) return step_ms(p, W, t, t_end, dt_taken, nthreads < 1 ? 1 : nthreads);
   if (p->dim == 3) return step3(p, W, t, t_end, dt_taken, nthreads < 1 ? 1 : nthreads);
   int rc = check_problem(p);
   if (rc) return rc;
@@ -2010,5 +2013,140 @@ static int step3(const oracle_problem* p, double* W, double* t, double t_end, do
 #undef FACE
   for (int d = 0; d < 3; ++d) { free(Fd[d]); free(Fh[d]); free(F[d]); free(Gn[d]); }
   free(Ws);
+  return rc;
+}
+
+
+/* ======================================================================== */
+/* 9. Two-derivative multistage steps                                        */
+/* ======================================================================== */
+/* Sec. 2.2 writes S2O4 through the spatial operator L and its time derivative L_t and places it in the
+ * multi-stage multi-derivative family; a tableau (oracle_stepper) defines a member. Each stage takes
+ * the interface fluxes F and dF/dt of its own state over a window of length dt, exactly as the first
+ * stage of S2O4 does; L = -sum_d (F_{d,hi} - F_{d,lo}) / h_d and L_t likewise from dF/dt. */
+
+static int stepper_ok(const oracle_problem* p) {
+  const oracle_stepper* m = &p->stepper;
+  if (m->stages < 1 || m->stages > 3) return 0;
+  if (p->positivity != 0) return 0;
+  for (int s = 0; s < 4; ++s)
+    if (p->bc[s] == 4) return 0;
+  for (int i = 0; i < 3; ++i) {
+    if (!isfinite(m->b[i]) || !isfinite(m->bh[i])) return 0;
+    for (int j = 0; j < 3; ++j)
+      if (!isfinite(m->a[i][j]) || !isfinite(m->ah[i][j])) return 0;
+  }
+  return 1;
+}
+
+static size_t cells_of(const oracle_problem* p) {
+  return (size_t)p->nx * (p->dim >= 2 ? p->ny : 1) * (p->dim == 3 ? p->nz : 1);
+}
+
+static int admissible_any(const oracle_problem* p, const double* W) {
+  size_t n = cells_of(p);
+  int nc = p->dim + 2;
+  for (size_t s = 0; s < n; ++s) {
+    double rho = W[s], m2 = 0.0;
+    for (int d = 0; d < p->dim; ++d) m2 += W[(size_t)(1 + d) * n + s] * W[(size_t)(1 + d) * n + s];
+    double E = W[(size_t)(nc - 1) * n + s];
+    double pr = (p->gamma - 1.0) * (E - 0.5 * m2 / rho);
+    if (!(rho > 0.0) || !(pr > 0.0) || !isfinite(E)) return 0;
+  }
+  return 1;
+}
+
+/* L(W) and L_t(W) of every cell, [nc][cells] */
+static int ms_operators(const oracle_problem* p, const double* W, double ts, double dt, double* L, double* Lt,
+                        int nthreads) {
+  int dim = p->dim, nc = dim + 2;
+  int N[3] = {p->nx, dim >= 2 ? p->ny : 1, dim == 3 ? p->nz : 1};
+  double h[3] = {(p->x1 - p->x0) / p->nx, dim >= 2 ? (p->y1 - p->y0) / p->ny : 1.0,
+                 dim == 3 ? (p->z1 - p->z0) / p->nz : 1.0};
+  double *F[3] = {NULL, NULL, NULL}, *G[3] = {NULL, NULL, NULL};
+  for (int d = 0; d < dim; ++d) {
+    size_t nf = (size_t)nc * (N[0] + (d == 0)) * (N[1] + (d == 1)) * (N[2] + (d == 2));
+    F[d] = (double*)malloc(sizeof(double) * nf);
+    G[d] = (double*)malloc(sizeof(double) * nf);
+  }
+  int rc = (dim == 3) ? oracle_stage_fluxes3(p, W, dt, F, G, nthreads)
+                      : oracle_stage_fluxes(p, W, ts, dt, F[0], G[0], F[1], G[1], nthreads);
+  if (!rc) {
+    size_t n = cells_of(p);
+#define FACE(d, c, i, j, k) ((((size_t)(c) * (N[2] + ((d) == 2)) + (k)) * (N[1] + ((d) == 1)) + (j)) * (N[0] + ((d) == 0)) + (i))
+    for (int c = 0; c < nc; ++c)
+      for (int k = 0; k < N[2]; ++k)
+        for (int j = 0; j < N[1]; ++j)
+          for (int i = 0; i < N[0]; ++i) {
+            double l = 0.0, lt = 0.0;
+            for (int d = 0; d < dim; ++d) {
+              size_t lo = FACE(d, c, i, j, k), hi = FACE(d, c, i + (d == 0), j + (d == 1), k + (d == 2));
+              l -= (F[d][hi] - F[d][lo]) / h[d];
+              lt -= (G[d][hi] - G[d][lo]) / h[d];
+            }
+            size_t o = (size_t)c * n + ((size_t)k * N[1] + j) * N[0] + i;
+            L[o] = l;
+            Lt[o] = lt;
+          }
+#undef FACE
+  }
+  for (int d = 0; d < dim; ++d) {
+    free(F[d]);
+    free(G[d]);
+  }
+  return rc;
+}
+
+static int step_ms(const oracle_problem* p, double* W, double* t, double t_end, double* dt_taken, int nthreads) {
+  int rc = (p->dim == 3) ? check_problem3(p) : check_problem(p);
+  if (rc) return rc;
+  if (!stepper_ok(p)) return ORACLE_EINVAL;
+  const oracle_stepper* m = &p->stepper;
+  if (dt_taken) *dt_taken = 0.0;
+  if (*t >= t_end) return ORACLE_OK;
+  double dt = (p->fixed_dt > 0.0) ? p->fixed_dt : oracle_cfl_dt(p, W);
+  if (!(dt > 0.0) || !isfinite(dt)) return ORACLE_EDT;
+  double tnew;
+  if (*t + dt >= t_end) { dt = t_end - *t; tnew = t_end; }
+  else tnew = *t + dt;
+  int S = m->stages;
+  size_t len = (size_t)(p->dim + 2) * cells_of(p);
+  double* L[3];
+  double* Lt[3];
+  for (int i = 0; i < S; ++i) {
+    L[i] = (double*)malloc(sizeof(double) * len);
+    Lt[i] = (double*)malloc(sizeof(double) * len);
+  }
+  double* Wi = (double*)malloc(sizeof(double) * len);
+  for (int i = 0; i < S && !rc; ++i) {
+    /* the stage state from the earlier stages' operators */
+    double ci = 0.0;
+    for (size_t o = 0; o < len; ++o) {
+      double w = W[o];
+      for (int j = 0; j < i; ++j) w += dt * m->a[i][j] * L[j][o] + dt * dt * m->ah[i][j] * Lt[j][o];
+      Wi[o] = w;
+    }
+    for (int j = 0; j < i; ++j) ci += m->a[i][j];
+    if (i > 0 && !admissible_any(p, Wi)) { rc = ORACLE_ENONPHYS; break; }
+    rc = ms_operators(p, Wi, *t + ci * dt, dt, L[i], Lt[i], nthreads);
+  }
+  if (!rc) {
+    for (size_t o = 0; o < len; ++o) {
+      double w = W[o];
+      for (int i = 0; i < S; ++i) w += dt * m->b[i] * L[i][o] + dt * dt * m->bh[i] * Lt[i][o];
+      Wi[o] = w;
+    }
+    if (!admissible_any(p, Wi)) rc = ORACLE_ENONPHYS;
+  }
+  if (!rc) {
+    memcpy(W, Wi, sizeof(double) * len);
+    *t = tnew;
+    if (dt_taken) *dt_taken = dt;
+  }
+  for (int i = 0; i < S; ++i) {
+    free(L[i]);
+    free(Lt[i]);
+  }
+  free(Wi);
   return rc;
 }

@@ -31,6 +31,18 @@ typedef struct {
   int32_t rest, pad;
 } oracle_bc_data;
 
+/* Time stepping (Sec. 2.2): stages == 0 is the paper's S2O4 as its steps (1)-(4) state it. stages 1..3
+ * take a two-derivative multistage tableau, the family Sec. 2.2 places S2O4 in:
+ *   W^(i)   = W^n + sum_{j<i} (dt a[i][j] L(W^(j)) + dt^2 ah[i][j] L_t(W^(j)))
+ *   W^(n+1) = W^n + sum_i   (dt b[i]    L(W^(i)) + dt^2 bh[i]    L_t(W^(i)))
+ * with L, L_t the negative divergence of the interface fluxes F and dF/dt of the stage state over the
+ * window [t_i, t_i + dt] (steps (1)-(2)), t_i = t_n + dt sum_j a[i][j]. */
+typedef struct {
+  int32_t stages, pad;
+  double a[3][3], ah[3][3];
+  double b[3], bh[3];
+} oracle_stepper;
+
 /* Problem statement (Sec. 2 and Sec. 3 of the paper). Field meanings follow the
  * HIP library's hgks_problem, but this is a separate declaration. */
 typedef struct {
@@ -55,6 +67,7 @@ typedef struct {
   int32_t nz;                   /* 3D (dim == 3): cells along z on [z0, z1], kinds of the z-low and z-high */
   double z0, z1;                /* sides in bcz (0..3); bc[0..3] hold the x and y sides */
   int32_t bcz[2];
+  oracle_stepper stepper;       /* stages 1..3: no prescribed sides, positivity 0 */
 } oracle_problem;
 
 enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_ENONPHYS = -4, ORACLE_EDT = -5 };

@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["hgks_kernels.hip", "hgks_kernels3.hip", "hgks_capi.cpp"]
+SRC = ["hgks_kernels.hip", "hgks_kernels3.hip", "hgks_stepper.hip", "hgks_capi.cpp"]
 LIB = os.path.join(HERE, "libhgks.so")
 ARCH = os.environ.get("HGKS_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -31,13 +31,14 @@ static thread_local hipError_t last_hip_error = hipSuccess;
 
 struct hgks {
   int nprob = 0, dim = 2, fp32 = 0, use_graph = 0, autotune = 0, compensated = 0;
+  hgks_stepper ms{};        // stages 0: S2O4; 1..3: the tableau (the same for every problem)
   int tile = 0, tuned = 0;  // tile: flux launch configuration, 0 .. kNumConfigs-1
   int pgrid[kNumConfigs];   // persistent grid per configuration (0: not yet queried)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<hgks_problem> hp;
   std::vector<ProbDev> pd;
-  std::vector<size_t> off_W, off_Ws, off_S, off_E, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_Fz, off_Gz, off_cnt;
+  std::vector<size_t> off_W, off_Ws, off_Ws2, off_S, off_E, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_Fz, off_Gz, off_cnt;
   size_t off_probs = 0, off_ts = 0, off_tab = 0, off_qpart = 0, ws_bytes = 0;
   char* ws = nullptr;
   bool own_ws = false, ready = false;
@@ -81,7 +82,35 @@ static hgks_status validate3(const hgks_problem& p) {
   return HGKS_OK;
 }
 
+// a multistage tableau: 1..3 stages, finite coefficients; not with prescribed-state sides (their stage
+// times), the positivity fallbacks (built on S2O4's stages) or compensated accumulation
+static hgks_status validate_stepper(const hgks_problem& p) {
+  const hgks_stepper& m = p.stepper;
+  if (m.stages == 0) return HGKS_OK;
+  if (m.stages < 1 || m.stages > 3) return HGKS_EINVAL;
+  for (int i = 0; i < 3; ++i) {
+    if (!std::isfinite(m.b[i]) || !std::isfinite(m.bh[i])) return HGKS_EINVAL;
+    for (int j = 0; j < 3; ++j)
+      if (!std::isfinite(m.a[i][j]) || !std::isfinite(m.ah[i][j])) return HGKS_EINVAL;
+  }
+  if (p.positivity != 0) return HGKS_EINVAL;
+  for (int s = 0; s < 4; ++s)
+    if (p.bc[s] == HGKS_BC_PRESCRIBED) return HGKS_EINVAL;
+  return HGKS_OK;
+}
+
+static bool same_stepper(const hgks_stepper& a, const hgks_stepper& b) {
+  if (a.stages != b.stages) return false;
+  for (int i = 0; i < 3; ++i) {
+    if (a.b[i] != b.b[i] || a.bh[i] != b.bh[i]) return false;
+    for (int j = 0; j < i; ++j)
+      if (a.a[i][j] != b.a[i][j] || a.ah[i][j] != b.ah[i][j]) return false;
+  }
+  return true;
+}
+
 static hgks_status validate(const hgks_problem& p) {
+  if (hgks_status s = validate_stepper(p)) return s;
   if (p.dim == 3) return validate3(p);
   if (p.dim != 1 && p.dim != 2) return HGKS_EINVAL;
   if (p.nx < 5 || (p.dim == 2 && p.ny < 5) || (p.dim == 1 && p.ny != 1)) return HGKS_EINVAL;
@@ -119,7 +148,7 @@ static void plan(hgks* h) {
   size_t o = 0;
   const size_t ts = h->fp32 ? sizeof(float) : sizeof(double);
   const int np = h->nprob;
-  h->off_W.resize(np); h->off_Ws.resize(np); h->off_S.resize(np); h->off_E.resize(np); h->off_flags.resize(np);
+  h->off_W.resize(np); h->off_Ws.resize(np); h->off_Ws2.resize(np); h->off_S.resize(np); h->off_E.resize(np); h->off_flags.resize(np);
   h->off_Fx.resize(np); h->off_Gx.resize(np); h->off_Fy.resize(np); h->off_Gy.resize(np); h->off_cnt.resize(np);
   h->off_Fz.resize(np); h->off_Gz.resize(np);
   for (int p = 0; p < np; ++p) {
@@ -128,6 +157,11 @@ static void plan(hgks* h) {
     const size_t state = nc * cells_of(q) * sizeof(double);
     h->off_W[p] = o; o = align256(o + state);
     h->off_Ws[p] = o; o = align256(o + state);
+    if (h->ms.stages == 3) {
+      h->off_Ws2[p] = o; o = align256(o + state);
+    } else {
+      h->off_Ws2[p] = 0;
+    }
     h->off_S[p] = o; o = align256(o + state);
     if (h->compensated) {
       h->off_E[p] = o; o = align256(o + state);
@@ -266,6 +300,7 @@ static hgks_status materialise(hgks* h) {
     d.Ws = reinterpret_cast<double*>(h->ws + h->off_Ws[p]);
     d.S = reinterpret_cast<double*>(h->ws + h->off_S[p]);
     d.E = h->compensated ? reinterpret_cast<double*>(h->ws + h->off_E[p]) : nullptr;
+    d.Ws2 = h->ms.stages == 3 ? reinterpret_cast<double*>(h->ws + h->off_Ws2[p]) : nullptr;
     d.flags = reinterpret_cast<uint8_t*>(h->ws + h->off_flags[p]);
     d.Fx = h->ws + h->off_Fx[p];
     d.Gx = h->ws + h->off_Gx[p];
@@ -364,6 +399,26 @@ static void collect_profile(hgks* h) {
 static void enqueue_step(hgks* h, int use_tend, bool capturing = false) {
   const LaunchCtx L = ctx(h);
   timed(h, 3, capturing, [&] { launch_dt_finalize(L, use_tend); });
+  if (h->ms.stages > 0) {  // a multistage tableau: flags, fluxes (F and dF/dt) and the update per stage
+    const hgks_stepper& m = h->ms;
+    for (int i = 0; i < m.stages; ++i) {
+      MsStage c;
+      c.i = i;
+      c.stages = m.stages;
+      c.b = m.b[i];
+      c.bh = m.bh[i];
+      c.n1 = i + 1 < m.stages ? m.a[i + 1][i] : 0.0;
+      c.nh1 = i + 1 < m.stages ? m.ah[i + 1][i] : 0.0;
+      c.n2 = (i == 0 && m.stages == 3) ? m.a[2][0] : 0.0;
+      c.nh2 = (i == 0 && m.stages == 3) ? m.ah[2][0] : 0.0;
+      timed(h, 2, capturing, [&] { launch_flags(L, i > 0, i == 0, 0); });
+      timed(h, 0, capturing, [&] { launch_flux(L, i == 0 ? 1 : 3); });
+      timed(h, 1, capturing, [&] { launch_update_ms(L, c); });
+    }
+    timed(h, 3, capturing, [&] { launch_commit(L, use_tend); });
+    if (h->recs.size() > 4096) collect_profile(h);
+    return;
+  }
   timed(h, 2, capturing, [&] { launch_flags(L, 0, 1, 0); });
   timed(h, 0, capturing, [&] { launch_flux(L, 1); });
   timed(h, 1, capturing, [&] { launch_update(L, 1); });
@@ -514,6 +569,7 @@ hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opt
     hgks_status s = validate(probs[p]);
     if (s) return s;
     if (probs[p].dim != probs[0].dim) return HGKS_EINVAL;
+    if (!same_stepper(probs[p].stepper, probs[0].stepper)) return HGKS_EINVAL;
   }
   hgks* h = new (std::nothrow) hgks;
   if (!h) return HGKS_ENOMEM;
@@ -526,7 +582,8 @@ hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opt
   h->profile = opts ? opts->profile : 0;
   h->tile = (opts && opts->tile >= 0 && opts->tile < kNumConfigs) ? opts->tile : 0;
   h->compensated = opts ? (opts->compensated != 0) : 0;
-  if (h->dim == 3 && h->compensated) {
+  h->ms = probs[0].stepper;
+  if ((h->dim == 3 || h->ms.stages > 0) && h->compensated) {
     delete h;
     return HGKS_EINVAL;
   }

@@ -42,6 +42,7 @@ struct ProbDev {
   double* S;                 // partial sum W^n - dt L^n - dt^2/6 L_t^n
   double* E;                 // compensated mode: rounding error of W^n (between steps) and of S (within a
                              // step), so that the carried state is W + E; nullptr in plain mode
+  double* Ws2;               // three-stage tableaux: partial sum of the third stage's state
   uint8_t* flags;            // [(ny+4)][(nx+4)] (2D) / [nx+4] (1D): bit 0 x-flag, bit 1 y-flag
   void* Fx;                  // x-interfaces [4][ny][nx+1]: F (stage 1) / unused (stage 2)
   void* Gx;                  // x-interfaces: dF/dt

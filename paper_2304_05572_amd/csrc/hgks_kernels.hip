@@ -4,6 +4,7 @@
 //   k_dt_finalize -> [k_flags -> k_flux(stage 1) -> k_update(stage 1)]
 //                 -> [k_flags -> k_flux(stage 2) -> k_update(stage 2, + CFL partials)] (-> k_repair)
 //                 -> k_commit
+// (a multistage tableau instead runs [k_flags -> k_flux(stage 1 or 3) -> k_update_ms] per stage).
 // Work is split into tiles; a prefix-sum table maps a flat block index to (problem, tile), so a batch
 // of uneven problems runs in the same launches as a single problem.
 #include <hip/hip_runtime.h>
@@ -364,6 +365,8 @@ __device__ inline void tangential_side(const T* sNR, int tt, int k, int s, int f
 // then each thread takes one interface through the tangential reconstruction at the two Gauss
 // points, the equilibrium state and the flux (Sec. 2.3.3 Steps 1-3, Sec. 2.1-2.2).
 // Frame: slot 1 holds the normal momentum, slot 2 the tangential one (y-interfaces swap U and V).
+// stage 1: W^n -> F, dF/dt; stage 2: W* -> dF/dt only (into the F arrays); stage 3: W* -> F, dF/dt
+// (the stages of a multistage tableau after the first).
 // ---------------------------------------------------------------------------------------------
 template <typename T, int TN, int TT, int DIM, bool PRFIX>
 __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
@@ -526,7 +529,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   fp.gamma = P.gamma; fp.K = P.K; fp.mu = P.mu; fp.Pr = P.Pr; fp.c1 = P.c1; fp.c2 = P.c2;
   fp.Kp2 = P.Kp2; fp.iKp2 = P.iKp2; fp.kpr = P.kpr;
   fp.dt = tsp.dt; fp.dth = tsp.dth; fp.idt = tsp.idt; fp.idt2 = tsp.idt2;
-  fp.ns = P.ns; fp.want_F = (stage == 1);
+  fp.ns = P.ns; fp.want_F = (stage != 2);
   T F[4] = {0, 0, 0, 0}, dF[4] = {0, 0, 0, 0};
   if (DIM == 1) {
     T Wl[4], Wxl[4], Wr[4], Wxr[4];
@@ -561,10 +564,10 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
     }
   }
 
-  // ---- write F (stage 1) and dF/dt in the grid's component order. The second stage's dF/dt goes to
+  // ---- write F (stages 1 and 3) and dF/dt in the grid's component order. The second stage's dF/dt goes to
   // the F arrays (F^n is spent by then), which keeps the first stage's dF/dt for the time-order fallback.
   T* Fo = reinterpret_cast<T*>(dir ? P.Fy : P.Fx);
-  T* Go = reinterpret_cast<T*>(stage == 1 ? (dir ? P.Gy : P.Gx) : (dir ? P.Fy : P.Fx));
+  T* Go = reinterpret_cast<T*>(stage != 2 ? (dir ? P.Gy : P.Gx) : (dir ? P.Fy : P.Fx));
   size_t o, plane;
   if (dir == 0) { plane = (size_t)P.ny * (P.nx + 1); o = (size_t)t * (P.nx + 1) + n; }
   else { plane = (size_t)(P.ny + 1) * P.nx; o = (size_t)n * P.nx + t; }
@@ -579,7 +582,7 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
       if (v == 3) gc = 2;
     }
     if (gc >= nc) continue;
-    if (stage == 1 && gp == 0) Fo[gc * plane + o] = F[v];
+    if (stage != 2 && gp == 0) Fo[gc * plane + o] = F[v];
     if (DIM == 1 || gp == 1) Go[gc * plane + o] = dF[v];
   }
 }

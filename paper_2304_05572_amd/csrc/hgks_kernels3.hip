@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   fp.gamma = P.gamma; fp.K = P.K; fp.mu = P.mu; fp.Pr = P.Pr; fp.c1 = P.c1; fp.c2 = P.c2;
   fp.Kp2 = P.Kp2; fp.iKp2 = P.iKp2; fp.kpr = P.kpr;
   fp.dt = tsp.dt; fp.dth = tsp.dth; fp.idt = tsp.idt; fp.idt2 = tsp.idt2;
-  fp.ns = P.ns; fp.want_F = (stage == 1);
+  fp.ns = P.ns; fp.want_F = (stage != 2);
   T F[5] = {0, 0, 0, 0, 0}, dF[5] = {0, 0, 0, 0, 0};
   flux3_finish(acc, fp, Kp3, iKp3, T(0.25), F, dF);
 #pragma unroll
@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   if (g != 0) return;
   // grid component of each frame slot; the second stage's dF/dt goes to the F arrays (as in 2D)
   T* Fo = reinterpret_cast<T*>(d == 0 ? P.Fx : (d == 1 ? P.Fy : P.Fz));
-  T* Go = stage == 1 ? reinterpret_cast<T*>(d == 0 ? P.Gx : (d == 1 ? P.Gy : P.Gz)) : Fo;
+  T* Go = stage != 2 ? reinterpret_cast<T*>(d == 0 ? P.Gx : (d == 1 ? P.Gy : P.Gz)) : Fo;
   int i, j, k;
   grid_of_frame(d, n, a, bb, i, j, k);
   const int M0 = P.nx + (d == 0), M1 = P.ny + (d == 1), M2 = P.nz + (d == 2);
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const size_t oc[5] = {0, (size_t)(1 + d) * plane, (size_t)(1 + da) * plane, (size_t)(1 + db) * plane, 4 * plane};
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    if (stage == 1) Fo[oc[v] + o] = F[v];
+    if (stage != 2) Fo[oc[v] + o] = F[v];
     Go[oc[v] + o] = dF[v];
   }
 }

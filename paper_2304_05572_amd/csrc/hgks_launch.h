@@ -61,6 +61,14 @@ void launch_flux(const LaunchCtx& L, int stage);
 int flux_persistent_grid(const LaunchCtx& L);  // blocks of the persistent flux launch for L's variant
 void launch_update(const LaunchCtx& L, int stage);
 void launch_repair(const LaunchCtx& L);
+// One stage of a two-derivative multistage tableau (stage i of `stages`): its own weights b, bh in the
+// new state, the coefficients a, ah of its operators in the next stage's state (n1, nh1) and in the one
+// after (n2, nh2, three-stage tableaux after the first stage only).
+struct MsStage {
+  int i, stages;
+  double b, bh, n1, nh1, n2, nh2;
+};
+void launch_update_ms(const LaunchCtx& L, const MsStage& c);
 // the 3D kernels (own source file; the launchers above dispatch to these when L.dim == 3)
 void launch_cfl3(const LaunchCtx& L);
 void launch_flags3(const LaunchCtx& L, int stage_state, int count);

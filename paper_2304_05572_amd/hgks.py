@@ -60,6 +60,33 @@ class BcData:
     rest: int = BC_PRESCRIBED
 
 
+class hgks_stepper(C.Structure):
+    _fields_ = [("stages", C.c_int32), ("reserved", C.c_int32), ("a", (C.c_double * 3) * 3),
+                ("ah", (C.c_double * 3) * 3), ("b", C.c_double * 3), ("bh", C.c_double * 3)]
+
+
+@dataclasses.dataclass
+class Stepper:
+    """Two-derivative multistage tableau (hgks_stepper): W^(i) = W^n + sum_{j<i} (dt a[i][j] L_j + dt^2
+    ah[i][j] L_t,j), W^{n+1} = W^n + sum_i (dt b[i] L_i + dt^2 bh[i] L_t,i); stages 0 is S2O4."""
+    stages: int = 0
+    a: tuple = ((0.0,) * 3,) * 3
+    ah: tuple = ((0.0,) * 3,) * 3
+    b: tuple = (0.0,) * 3
+    bh: tuple = (0.0,) * 3
+
+    def c_struct(self) -> hgks_stepper:
+        m = hgks_stepper()
+        m.stages = int(self.stages)
+        for i in range(3):
+            m.b[i] = float((list(self.b) + [0.0] * 3)[i])
+            m.bh[i] = float((list(self.bh) + [0.0] * 3)[i])
+            for j in range(3):
+                m.a[i][j] = float(self.a[i][j]) if i < len(self.a) and j < len(self.a[i]) else 0.0
+                m.ah[i][j] = float(self.ah[i][j]) if i < len(self.ah) and j < len(self.ah[i]) else 0.0
+        return m
+
+
 class hgks_problem(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
@@ -71,6 +98,7 @@ class hgks_problem(C.Structure):
         ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32), ("positivity", C.c_int32),
         ("bcd", hgks_bc_data * 4),
         ("nz", C.c_int32), ("z0", C.c_double), ("z1", C.c_double), ("bcz", C.c_int32 * 2),
+        ("stepper", hgks_stepper),
     ]
 
 
@@ -112,6 +140,7 @@ class Problem:
     z0: float = 0.0
     z1: float = 1.0
     bcz: tuple = (BC_OUTFLOW,) * 2
+    stepper: object = None  # Stepper (or its fields as a dict); None: S2O4
 
     @property
     def nc(self):
@@ -135,6 +164,9 @@ class Problem:
                 s.bc = (C.c_int32 * 4)(*[int(b) for b in (list(v) + [0] * 4)[:4]])
             elif f.name == "bcz":
                 s.bcz = (C.c_int32 * 2)(*[int(b) for b in (list(v) + [0] * 2)[:2]])
+            elif f.name == "stepper":
+                if v is not None:
+                    s.stepper = (Stepper(**v) if isinstance(v, dict) else v).c_struct()
             elif f.name == "bcd":
                 for k, d in enumerate(list(v)[:4]):
                     if isinstance(d, dict):

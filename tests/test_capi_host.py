@@ -46,6 +46,14 @@ def test_bc_data_layout_matches_header():
     assert C.sizeof(H.hgks_bc_data) == 8 * 11 + 8
 
 
+def test_stepper_layout_matches_header():
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\} hgks_stepper;", src, re.S).group(1)
+    names = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)(?:\[\d+\])*\s*[,;]", body)
+    assert [f[0] for f in H.hgks_stepper._fields_] == names
+    assert C.sizeof(H.hgks_stepper) == 8 + 8 * (9 + 9 + 3 + 3)
+
+
 def test_status_strings():
     for code in (H.OK, H.EINVAL, H.ENOMEM, H.EDEVICE, H.ENONPHYS, H.EDT):
         assert H.hgks_status_str(code) and H.hgks_status_str(code) != "unknown status"
@@ -67,6 +75,12 @@ def test_status_strings():
     dict(dim=3, nz=4), dict(dim=3, nz=8, bcz=(0, 1)), dict(dim=3, nz=8, bcz=(1, 4)), dict(dim=3, nz=8, z1=0.0),
     dict(dim=3, nz=8, eqn=1, mu=1e-3, Pr=0.72), dict(dim=3, nz=8, positivity=1),
     dict(dim=3, nz=8, bc=(4, 1, 1, 1), bcd=(H.BcData(),)),
+    # multistage tableaux: stage count, non-finite coefficients, what only S2O4 supports
+    dict(stepper=H.Stepper(4, b=(1, 0, 0))), dict(stepper=H.Stepper(-1)),
+    dict(stepper=H.Stepper(1, b=(1, 0, 0), bh=(float("nan"), 0, 0))),
+    dict(stepper=H.Stepper(2, a=((0, 0, 0), (float("inf"), 0, 0), (0, 0, 0)), b=(1, 0, 0))),
+    dict(stepper=H.Stepper(1, b=(1, 0, 0), bh=(0.5, 0, 0)), positivity=1),
+    dict(stepper=H.Stepper(1, b=(1, 0, 0), bh=(0.5, 0, 0)), bc=(4, 1, 1, 1), bcd=(H.BcData(),)),
 ])
 def test_invalid_problems_rejected_on_host(bad):
     P = H.Problem(**bad)
@@ -78,6 +92,16 @@ def test_invalid_problems_rejected_on_host(bad):
 def test_compensated_accumulation_rejected_in_3d():
     with pytest.raises(H.HgksError) as e:
         H.hgks_create([H.Problem(dim=3, nx=8, ny=8, nz=8)], compensated=1)
+    assert e.value.code == H.EINVAL
+
+
+def test_mixed_steppers_and_compensated_tableau_rejected():
+    one = H.Stepper(1, b=(1, 0, 0), bh=(0.5, 0, 0))
+    with pytest.raises(H.HgksError) as e:
+        H.hgks_create([H.Problem(), H.Problem(stepper=one)])
+    assert e.value.code == H.EINVAL
+    with pytest.raises(H.HgksError) as e:
+        H.hgks_create([H.Problem(stepper=one)], compensated=1)
     assert e.value.code == H.EINVAL
 
 

@@ -1,0 +1,98 @@
+"""Pins of the oracle's two-derivative multistage steps (Sec. 2.2 writes S2O4 through the spatial operator L
+and its time derivative L_t and places it in the multi-stage multi-derivative family). Checked against
+things other than the generic code itself: S2O4 written as a tableau reproduces the oracle's own S2O4
+(coded step by step as the paper states it); the one-stage tableau (the flux function integrated over the
+step) converges at second order in time; with tau = 0 the gas-kinetic flux and its time derivative do not
+depend on the window, so a two- or three-stage tableau built from equal one-stage sub-steps must equal
+those sub-steps taken one after another (which exercises every coefficient slot of the stage
+bookkeeping)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_05572_amd import workloads as wl
+
+NT = min(8, os.cpu_count() or 1)
+
+# Sec. 2.2: W* = W^n + dt/2 L + dt^2/8 L_t; W^{n+1} = W^n + dt L + dt^2/6 (L_t(W^n) + 2 L_t(W*))
+S2O4 = O.Stepper(2, a=((0, 0, 0), (0.5, 0, 0), (0, 0, 0)), ah=((0, 0, 0), (0.125, 0, 0), (0, 0, 0)),
+                 b=(1, 0, 0), bh=(1 / 6, 1 / 3, 0))
+# the time integral of the linear-in-time flux over one step: W^{n+1} = W^n + dt L + dt^2/2 L_t
+ONE = O.Stepper(1, b=(1, 0, 0), bh=(0.5, 0, 0))
+# two and three equal one-stage sub-steps of dt/2 and dt/3 as one tableau
+TWO_HALVES = O.Stepper(2, a=((0, 0, 0), (1 / 2, 0, 0), (0, 0, 0)), ah=((0, 0, 0), (1 / 8, 0, 0), (0, 0, 0)),
+                       b=(1 / 2, 1 / 2, 0), bh=(1 / 8, 1 / 8, 0))
+THREE_THIRDS = O.Stepper(3, a=((0, 0, 0), (1 / 3, 0, 0), (1 / 3, 1 / 3, 0)),
+                         ah=((0, 0, 0), (1 / 18, 0, 0), (1 / 18, 1 / 18, 0)),
+                         b=(1 / 3, 1 / 3, 1 / 3), bh=(1 / 18, 1 / 18, 1 / 18))
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _cases():
+    W2, _ = wl.riemann_2d(20, seed=4)
+    yield "2d", dict(nx=20, ny=20, bc=(1, 1, 1, 1)), W2
+    yield "1d", dict(dim=1, nx=60, ny=1, bc=(2, 2, 0, 0)), wl.sod_1d(60)
+    yield "ns", dict(nx=16, ny=12, bc=(3, 3, 2, 2), eqn=O.NS, mu=5e-3, Pr=0.73), wl.riemann_2d(16, seed=2, ny=12)[0]
+    yield "3d", dict(dim=3, nx=8, ny=7, nz=6, bc=(1, 1, 1, 1), bcz=(1, 1)), wl.octants_3d(8, 7, 6, seed=3)
+
+
+@pytest.mark.parametrize("case", ["2d", "1d", "ns", "3d"])
+def test_s2o4_tableau_reproduces_the_s2o4_step(case):
+    name, kw, W = next(c for c in _cases() if c[0] == case)
+    Wa, ta, dta = O.step(O.Problem(**kw), W, 0.0, nthreads=NT)
+    Wb, tb, dtb = O.step(O.Problem(**kw, stepper=S2O4), W, 0.0, nthreads=NT)
+    assert dta == dtb and ta == tb
+    assert rel(Wb, Wa) < 1e-14
+
+
+def test_one_stage_tableau_is_second_order_in_time():
+    """1D density wave, 80 cells (fixed), tau = 0, to t = 0.4 with dt = T/80, T/160, T/320 against S2O4 at
+    T/2560: the error falls by 4 per halving."""
+    n, T = 80, 0.4
+    kw = dict(dim=1, nx=n, ny=1, bc=(0, 0, 0, 0), x1=2.0, c1=0.0, c2=0.0)
+    W0 = wl.advection_1d(n)
+
+    def run(st, m):
+        W, t, _, _ = O.run(O.Problem(**kw, fixed_dt=T / m, stepper=st), W0, T, nthreads=1)
+        assert abs(t - T) < 1e-12
+        return W[0]
+
+    ref = run(S2O4, 2560)
+    e = [np.abs(run(ONE, m) - ref).max() for m in (80, 160, 320)]
+    orders = [np.log2(e[k] / e[k + 1]) for k in range(2)]
+    assert all(1.95 < q < 2.05 for q in orders), orders
+    # S2O4 at the coarsest step is far more accurate than the one-stage scheme
+    assert np.abs(run(S2O4, 80) - ref).max() < 1e-3 * e[0]
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_multistage_tableaux_equal_their_one_stage_substeps(dim):
+    if dim == 1:
+        kw = dict(dim=1, nx=40, ny=1, bc=(0, 0, 0, 0), x1=2.0, c1=0.0, c2=0.0)
+        W0 = wl.advection_1d(40)
+    else:
+        kw = dict(nx=16, ny=16, bc=(0, 0, 0, 0), x1=2.0, y1=2.0, c1=0.0, c2=0.0)
+        W0 = wl.advection_2d(16)
+    dt = 0.02
+    for st, parts in ((TWO_HALVES, 2), (THREE_THIRDS, 3)):
+        Wt, _, _ = O.step(O.Problem(**kw, fixed_dt=dt, stepper=st), W0, 0.0, nthreads=NT)
+        Ws, t = W0.copy(), 0.0
+        for _ in range(parts):
+            Ws, t, _ = O.step(O.Problem(**kw, fixed_dt=dt / parts, stepper=ONE), Ws, t, nthreads=NT)
+        assert rel(Wt, Ws) < 1e-14, parts
+
+
+@pytest.mark.parametrize("bad", [
+    dict(stepper=O.Stepper(4, b=(1, 0, 0))),
+    dict(stepper=O.Stepper(1, b=(1, 0, 0), bh=(float("nan"), 0, 0))),
+    dict(stepper=ONE, positivity=1),
+])
+def test_invalid_tableaux_rejected(bad):
+    W, _ = wl.riemann_2d(12, seed=1)
+    with pytest.raises(O.OracleError):
+        O.step(O.Problem(nx=12, ny=12, **bad), W, 0.0)
