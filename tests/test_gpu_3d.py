@@ -176,3 +176,42 @@ def test_smooth_advection_fifth_order_on_gpu():
     order = np.log(errs[0] / errs[1]) / np.log(1.5)
     say("errors", errs, "order", order)
     assert 4.5 < order < 5.6
+
+
+def test_bench_size_128cubed_windows_and_flags():
+    """The benchmark's 3D workload (128^3 eight-octant problem, seed 0, FP64, its launch configuration):
+    after three steps, the troubled-cell flags of the whole grid bit-exact, and the fourth step on three
+    30^3 windows (the point where the eight states meet, a planar discontinuity away from it, the corner
+    of the domain) against oracle steps of the windows with the same dt, compared 10 cells inside the
+    window's interior faces (the reach of two stages)."""
+    n = 128
+    kw = dict(dim=3, nx=n, ny=n, nz=n, bc=(1, 1, 1, 1), bcz=(1, 1), cfl=0.5, c1=0.01, c2=1.0)
+    W0 = wl.octants_3d(n, n, n, seed=0)
+    s = H.Solver(H.Problem(**kw), tile=0)
+    s.set_ic(0, W0)
+    s.run(np.inf, 3)
+    W3, t3 = s.get_state(0)
+    say("128^3 flags")
+    f = s.flags(0)
+    o = O.flags3(O.Problem(**kw), W3)
+    for d in range(3):
+        assert np.array_equal(f[d], o[d]), d
+    dt = s.step()[0]
+    W4, _ = s.get_state(0)
+    h, half, margin = 1.0 / n, 15, 10
+    worst = 0.0
+    for c in ((64, 64, 64), (64, 30, 98), (12, 12, 12)):
+        lo = [max(x - half, 0) for x in c]
+        hi = [min(x + half, n) for x in c]
+        sub = np.ascontiguousarray(W3[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]])
+        P = O.Problem(**dict(kw, nx=hi[0] - lo[0], ny=hi[1] - lo[1], nz=hi[2] - lo[2],
+                             x0=lo[0] * h, x1=hi[0] * h, y0=lo[1] * h, y1=hi[1] * h, z0=lo[2] * h, z1=hi[2] * h,
+                             fixed_dt=dt))
+        Wo, _, _ = O.step(P, sub, t3, nthreads=NT)
+        a = [0 if lo[k] == 0 else margin for k in range(3)]
+        b = [(hi[k] - lo[k]) - (0 if hi[k] == n else margin) for k in range(3)]
+        got = W4[:, lo[2] + a[2]:lo[2] + b[2], lo[1] + a[1]:lo[1] + b[1], lo[0] + a[0]:lo[0] + b[0]]
+        want = Wo[:, a[2]:b[2], a[1]:b[1], a[0]:b[0]]
+        worst = max(worst, rel(got, want))
+        say("window", c, rel(got, want))
+    assert worst < 1e-12
