@@ -215,3 +215,78 @@ def test_bench_size_128cubed_windows_and_flags():
         worst = max(worst, rel(got, want))
         say("window", c, rel(got, want))
     assert worst < 1e-12
+
+
+def test_minimum_size_grids_alone_and_in_a_batch():
+    """5 x 5 x 5 cells (the smallest grid the stencils allow) with each boundary kind, alone and in one
+    batch with a ragged 9 x 6 x 7 problem: steps against the oracle."""
+    cases = [
+        dict(dim=3, nx=5, ny=5, nz=5, bc=(0, 0, 0, 0), bcz=(0, 0)),
+        dict(dim=3, nx=5, ny=5, nz=5, bc=(2, 3, 1, 2), bcz=(3, 1)),
+        dict(dim=3, nx=9, ny=6, nz=7, bc=(1, 1, 2, 2), bcz=(0, 0)),
+    ]
+    states = [wl.octants_3d(k["nx"], k["ny"], k["nz"], seed=20 + i, wiggle=0.05) for i, k in enumerate(cases)]
+    kws = [dict(k, c1=0.01, c2=1.0, cfl=0.4) for k in cases]
+    s = H.Solver([H.Problem(**k) for k in kws])
+    for p, W in enumerate(states):
+        s.set_ic(p, W)
+    say("3d minimum sizes")
+    cur = [W.copy() for W in states]
+    t = [0.0] * len(cases)
+    for step in range(4):
+        dts = s.step()
+        for p, k in enumerate(kws):
+            Wo, to, dto = O.step(O.Problem(**k), cur[p], t[p], nthreads=NT)
+            assert dts[p] == dto, (p, step)
+            Wg, tg = s.get_state(p)
+            assert tg == to and rel(Wg, Wo) < 1e-12, (p, step, rel(Wg, Wo))
+            cur[p], t[p] = Wg, tg
+
+
+def test_largest_grid_640_cubed():
+    """640^3 = 2.6e8 cells (the library's limit is 2^28), periodic, FP64, one step: 64-bit offsets in every
+    kernel (each state array is 10.5 GB, each face array 10.5 GB). The state is built on the device (a
+    smooth field with a sharp layer); checked: mass, momentum and energy conserved to rounding, and three
+    30^3 windows against oracle steps with the same dt, compared 10 cells inside."""
+    import torch
+    n = 640
+    kw = dict(dim=3, nx=n, ny=n, nz=n, bc=(0, 0, 0, 0), bcz=(0, 0), cfl=0.5, c1=0.01, c2=1.0)
+    say("640^3 build state")
+    c = (torch.arange(n, device="cuda", dtype=torch.float64) + 0.5) / n
+    Z, Y, X = c.view(n, 1, 1), c.view(1, n, 1), c.view(1, 1, n)
+    W = torch.empty((5, n, n, n), dtype=torch.float64, device="cuda")
+    rho = 1.0 + 0.3 * torch.sin(2 * torch.pi * X) * torch.cos(2 * torch.pi * Y) + 0.4 * ((Z - 0.5).abs() < 0.2)
+    u, v, w = 0.2 + 0.1 * torch.sin(2 * torch.pi * Z), -0.1 + 0.0 * X, 0.15 + 0.05 * torch.cos(2 * torch.pi * Y)
+    p = 1.0 + 0.2 * torch.cos(2 * torch.pi * (X + Y))
+    W[0] = rho
+    W[1] = rho * u
+    W[2] = rho * v
+    W[3] = rho * w
+    W[4] = p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)
+    del rho, u, v, w, p
+    torch.cuda.synchronize()
+    tot0 = W.sum(dim=(1, 2, 3)).cpu().numpy()
+    say("640^3 step")
+    s = H.Solver(H.Problem(**kw), tile=0)
+    s.set_ic(0, W)
+    dt = s.step()[0]
+    W1 = torch.empty_like(W)
+    s.get_state(0, W1)
+    torch.cuda.synchronize()
+    tot1 = W1.sum(dim=(1, 2, 3)).cpu().numpy()
+    say("totals", tot0, tot1)
+    assert np.all(np.abs(tot1 - tot0) <= 1e-11 * np.abs(tot0).max())
+    h, half, margin = 1.0 / n, 15, 10
+    worst = 0.0
+    for cen in ((320, 320, 320), (100, 500, 384), (560, 70, 200)):
+        lo = [x - half for x in cen]
+        sub = W[:, lo[2]:lo[2] + 30, lo[1]:lo[1] + 30, lo[0]:lo[0] + 30].cpu().numpy().copy()
+        P = O.Problem(**dict(kw, nx=30, ny=30, nz=30, bc=(1, 1, 1, 1), bcz=(1, 1), x0=lo[0] * h, x1=(lo[0] + 30) * h,
+                             y0=lo[1] * h, y1=(lo[1] + 30) * h, z0=lo[2] * h, z1=(lo[2] + 30) * h, fixed_dt=dt))
+        Wo, _, _ = O.step(P, sub, 0.0, nthreads=NT)
+        got = W1[:, lo[2] + margin:lo[2] + 30 - margin, lo[1] + margin:lo[1] + 30 - margin,
+                 lo[0] + margin:lo[0] + 30 - margin].cpu().numpy()
+        want = Wo[:, margin:30 - margin, margin:30 - margin, margin:30 - margin]
+        worst = max(worst, rel(got, want))
+        say("window", cen, rel(got, want))
+    assert worst < 1e-12
