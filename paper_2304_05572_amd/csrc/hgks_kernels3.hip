@@ -113,6 +113,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   constexpr int S1 = 15;   // per sweep-1 result: value, da-derivative, value of the normal slope
   constexpr int NW = 5 * CB * CA * CN, NS1 = CB * TA * TN * 2 * S1;
   __shared__ T sNR[CB][CA][TN][NRS];
+  __shared__ uint8_t sFl[CB][CA][CN];  // flags of the staged cells (0 outside the extended range)
   __shared__ T sU[NW > NS1 ? NW : NS1];  // cells (phases 1-2), then one side's sweep-1 results (phase 3)
 #define SW(v, cb, ca, cn) sU[(((v) * CB + (cb)) * CA + (ca)) * CN + (cn)]
   const int b = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -135,13 +136,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const int n0 = (lt % tn) * TN, a0 = ((lt / tn) % ta) * TA, b0 = (lt / (tn * ta)) * TB;
   const double* __restrict__ Wsrc = (stage == 1) ? P.W : P.Ws;
 
-  // ---- 1: cells
+  // ---- 1: cells and their flags. Consecutive threads take consecutive x (the normal for x-faces, the
+  // second tangential axis for y-faces, the first for z-faces), so that the loads coalesce.
   for (int e = tid; e < CN * CA * CB; e += 256) {
-    const int cn = e % CN, ca = (e / CN) % CA, cb = e / (CN * CA);
+    int cn, ca, cb;
+    if (d == 0) { cn = e % CN; ca = (e / CN) % CA; cb = e / (CN * CA); }
+    else if (d == 1) { cb = e % CB; cn = (e / CB) % CN; ca = e / (CB * CN); }
+    else { ca = e % CA; cb = (e / CA) % CB; cn = e / (CA * CB); }
     int i, j, k;
     grid_of_frame(d, n0 - 3 + cn, a0 - 2 + ca, b0 - 2 + cb, i, j, k);
     double q[5];
     load_cell3(P, Wsrc, i, j, k, q);
+    sFl[cb][ca][cn] = flag3_at(P, i, j, k);
     SW(0, cb, ca, cn) = T(q[0]);
     SW(1, cb, ca, cn) = T(sel3(d, q[1], q[2], q[3]));
     SW(2, cb, ca, cn) = T(sel3(da, q[1], q[2], q[3]));
@@ -161,11 +167,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     for (int m = 0; m < 6; ++m)
 #pragma unroll
       for (int v = 0; v < 5; ++v) q6[m][v] = SW(v, bl, al, kl + m);
-    int i, j, k;
-    grid_of_frame(d, n0 + kl - 1, a0 - 2 + al, b0 - 2 + bl, i, j, k);
-    const int fl = (flag3_at(P, i, j, k) >> d) & 1;
-    grid_of_frame(d, n0 + kl, a0 - 2 + al, b0 - 2 + bl, i, j, k);
-    const int fr = (flag3_at(P, i, j, k) >> d) & 1;
+    const int fl = (sFl[bl][al][kl + 2] >> d) & 1, fr = (sFl[bl][al][kl + 3] >> d) & 1;
     T out[20];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -218,9 +220,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   for (int s = 0; s < 2; ++s) {
     if (s == 1) __syncthreads();  // side 0's sweep-2 reads are done before side 1's results overwrite them
     {
-      int i, j, k;
-      grid_of_frame(d, n0 + ikl - 1 + s, a0 + ial, b0 - 2 + irb, i, j, k);
-      const int fa = (flag3_at(P, i, j, k) >> da) & 1;
+      const int fa = (sFl[irb][ial + 2][ikl + 2 + s] >> da) & 1;  // cell (n0 + ikl - 1 + s, a0 + ial, b0 - 2 + irb)
       Char5<T> m;
       if (fa) {
         T own[5];
@@ -247,9 +247,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
     __syncthreads();
     if (valid) {
-      int i, j, k;
-      grid_of_frame(d, n - 1 + s, a, bb, i, j, k);
-      const int fb = (flag3_at(P, i, j, k) >> db) & 1;
+      const int fb = (sFl[bl + 2][al + 2][kl + 2 + s] >> db) & 1;  // cell (n - 1 + s, a, bb)
       const T* row = &sU[((bl * TA + al) * TN + kl) * 2 * S1 + g1 * S1];
       constexpr int RS = TA * TN * 2 * S1;  // next row along db
       T q[5][5], Wp[5], Wn[5], Wa[5], Wb[5], der[5];
