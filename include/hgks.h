@@ -128,7 +128,10 @@ typedef struct {
   int32_t recon;                /* hgks_recon */
   double gamma_hi, gamma_lo, weno_eps;  /* WENO-AO linear weights and epsilon (0.85, 0.85, 1e-8) */
   int32_t zeta1_mode;           /* Step-1 threshold: 0 -> 5*h on the normalised quadratic, 1 -> 5*h^3 */
-  int32_t tangential_flag_mode; /* 0: tangential step uses the perpendicular-direction cell flag */
+  int32_t tangential_flag_mode; /* flag of the tangential reconstruction (Sec. 2.3.3 Step 2): 0 the side
+                                   cell's flag along the interface (default); 1 (2D only) the hybrid
+                                   indicator (Steps 1-4) on the line values along the interface. All problems
+                                   of a handle take the same mode. */
   int32_t positivity;           /* 0: the scheme as the paper states it. 1: two first-order fallbacks.
                                    A reconstructed state with rho <= 0 or p <= 0 (or not finite) drops to
                                    first order in space: a normal interface value takes its cell's average

@@ -255,6 +255,7 @@ typedef struct {
   int ns;
   double ghi, glo, eps;
   int recon, zeta1_mode, positivity;
+  int tfm;  /* tangential flag: 0 the side cell's flag, 1 the indicator on the line values */
 } params;
 
 /* q5[r][c]: the side's five cells (offsets -2..2), xi: evaluation point. Unflagged: component-wise
@@ -651,6 +652,7 @@ static void make_params(const oracle_problem* p, params* pp) {
   pp->recon = p->recon;
   pp->zeta1_mode = p->zeta1_mode;
   pp->positivity = p->positivity;
+  pp->tfm = p->tangential_flag_mode;
 }
 
 static int check_problem(const oracle_problem* p) {
@@ -659,6 +661,7 @@ static int check_problem(const oracle_problem* p) {
   if (!(p->gamma > 1.0) || !(p->x1 > p->x0) || (p->dim == 2 && !(p->y1 > p->y0))) return ORACLE_EINVAL;
   if (p->eqn == 1 && !(p->Pr > 0.0 && p->mu >= 0.0)) return ORACLE_EINVAL;
   if (p->positivity != 0 && p->positivity != 1) return ORACLE_EINVAL;
+  if (p->tangential_flag_mode != 0 && !(p->dim == 2 && p->tangential_flag_mode == 1)) return ORACLE_EINVAL;
   int nb = p->dim == 2 ? 4 : 2;
   for (int s = 0; s < nb; ++s) {
     if (p->bc[s] < 0 || p->bc[s] > 4) return ORACLE_EINVAL;
@@ -875,8 +878,11 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
   uint8_t* Fn = (uint8_t*)malloc((size_t)pn * pt);
   uint8_t* Ft = (uint8_t*)malloc((size_t)pn * pt);
   frame_flags(f, pp, Fn, f->dim == 2 ? Ft : NULL);
-  int nrows = (f->dim == 2) ? nt + 4 : 1; /* rows -2..nt+1 carry line values in 2D */
-  int r0 = (f->dim == 2) ? -2 : 0;
+  /* rows -2..nt+1 carry line values in 2D; -3..nt+2 when the tangential flag is the indicator on the line
+   * values (its widening needs the indicator one row beyond the interface's own rows) */
+  int ext = (f->dim == 2) ? (pp->tfm ? 3 : 2) : 0;
+  int nrows = (f->dim == 2) ? nt + 2 * ext : 1;
+  int r0 = -ext;
   size_t lsz = (size_t)nrows * (nn + 1);
   /* line values: [kind][c][row][k], kind 0: W^l, 1: W_x^l, 2: W^r, 3: W_x^r */
   double* LV = (double*)malloc(sizeof(double) * 4 * nc * lsz);
@@ -909,6 +915,27 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
       }
     }
   }
+  /* Sec. 2.3.3 Step 2 reading A: the tangential reconstruction's flag is the hybrid method's indicator
+   * (Steps 1-3) on the line values W^s along the interface, widened over the neighbouring rows (Step 4);
+   * Tl[s][row + 1][k] for rows -1..nt */
+  uint8_t* Tl = NULL;
+  if (f->dim == 2 && pp->tfm) {
+    Tl = (uint8_t*)malloc((size_t)2 * (nt + 2) * (nn + 1));
+    for (int sd = 0; sd < 2; ++sd)
+      for (int row = -1; row <= nt; ++row)
+        for (int k = 0; k <= nn; ++k) {
+          int T = 0;
+          double q[5], xb, xh;
+          int st;
+          for (int c = 0; c < nc; ++c) {
+            for (int r = 0; r < 5; ++r) q[r] = LVAT(2 * sd, c, row - 2 + r, k);
+            T |= troubled_component(q, f->ht, pp->zeta1_mode, &xb, &xh, &st);
+          }
+          if (pp->recon == 1) T = 1;
+          if (pp->recon == 2) T = 0;
+          Tl[((size_t)sd * (nt + 2) + (row + 1)) * (nn + 1) + k] = (uint8_t)T;
+        }
+  }
   const double eta = 1.0 / (2.0 * sqrt(3.0)); /* two-point Gauss-Legendre on [-1/2, 1/2] */
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
   for (int j = 0; j < nt; ++j) {
@@ -930,7 +957,12 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
         int ftf[2];
         double R[2][16], L[2][16];
         for (int s = 0; s < 2; ++s) {
-          ftf[s] = Ft[(size_t)(j + tp) * pn + (k - 1 + s + NG)];
+          if (Tl) {
+            const uint8_t* t = Tl + (size_t)s * (nt + 2) * (nn + 1);
+            ftf[s] = t[(size_t)j * (nn + 1) + k] | t[(size_t)(j + 1) * (nn + 1) + k] | t[(size_t)(j + 2) * (nn + 1) + k];
+          } else {
+            ftf[s] = Ft[(size_t)(j + tp) * pn + (k - 1 + s + NG)];
+          }
           if (ftf[s]) {
             double own[MAXC];
             for (int c = 0; c < nc; ++c) own[c] = LVAT(2 * s, c, j, k);
@@ -971,6 +1003,7 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
   }
 #undef LVAT
   free(LV);
+  free(Tl);
   free(Fn);
   free(Ft);
 }
@@ -1864,7 +1897,7 @@ static int check_problem3(const oracle_problem* p) {
   if (p->nx < 5 || p->ny < 5 || p->nz < 5) return ORACLE_EINVAL;
   if (!(p->gamma > 1.0) || !(p->x1 > p->x0) || !(p->y1 > p->y0) || !(p->z1 > p->z0)) return ORACLE_EINVAL;
   if (p->eqn == 1 && !(p->Pr == 1.0 && p->mu >= 0.0)) return ORACLE_EINVAL;
-  if (p->positivity != 0) return ORACLE_EINVAL;
+  if (p->positivity != 0 || p->tangential_flag_mode != 0) return ORACLE_EINVAL;
   int k[6] = {p->bc[0], p->bc[1], p->bc[2], p->bc[3], p->bcz[0], p->bcz[1]};
   for (int s = 0; s < 6; ++s)
     if (k[s] < 0 || k[s] > 3) return ORACLE_EINVAL;

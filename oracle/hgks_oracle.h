@@ -57,7 +57,8 @@ typedef struct {
   int32_t recon;                /* 0 hybrid, 1 always WENO5-AO, 2 always linear */
   double gamma_hi, gamma_lo, weno_eps;  /* WENO-AO linear-weight parameters and epsilon */
   int32_t zeta1_mode;           /* 0: Step-1 threshold 5*h on the normalised quadratic, 1: 5*h^3 */
-  int32_t tangential_flag_mode; /* only 0 (perpendicular cell flag) is implemented */
+  int32_t tangential_flag_mode; /* 2D: 0 the side cell's flag along the interface, 1 the hybrid indicator
+                                   on the line values along the interface (widened over rows) */
   int32_t positivity;           /* 0: the scheme as the paper states it. 1: first-order fallbacks: a
                                    reconstructed interface or Gauss-point state with rho <= 0 or p <= 0 is
                                    replaced by the state of the cell (or centre segment) it belongs to, with

@@ -118,7 +118,8 @@ static hgks_status validate(const hgks_problem& p) {
   if (!(p.cfl > 0.0) && !(p.fixed_dt > 0.0)) return HGKS_EINVAL;
   if (p.eqn != HGKS_EULER && p.eqn != HGKS_NS) return HGKS_EINVAL;
   if (p.eqn == HGKS_NS && !(p.Pr > 0.0 && p.mu >= 0.0)) return HGKS_EINVAL;
-  if (p.c1 < 0.0 || p.c2 < 0.0 || p.recon < 0 || p.recon > 2 || p.tangential_flag_mode != 0) return HGKS_EINVAL;
+  if (p.c1 < 0.0 || p.c2 < 0.0 || p.recon < 0 || p.recon > 2) return HGKS_EINVAL;
+  if (p.tangential_flag_mode != 0 && !(p.dim == 2 && p.tangential_flag_mode == 1)) return HGKS_EINVAL;
   if (p.positivity != 0 && p.positivity != 1) return HGKS_EINVAL;
   if (!(p.gamma_hi > 0.0 && p.gamma_hi < 1.0) || !(p.gamma_lo > 0.0 && p.gamma_lo < 1.0) || !(p.weno_eps > 0.0))
     return HGKS_EINVAL;
@@ -235,6 +236,7 @@ static LaunchCtx ctx(hgks* h) {
   for (auto& q : h->hp) L.prfix |= (q.eqn == HGKS_NS && q.Pr != 1.0);
   L.positivity = 0;
   for (auto& q : h->hp) L.positivity |= q.positivity;
+  L.tfm = h->hp[0].tangential_flag_mode;
   L.cell_blocks = h->tab_cell[h->nprob];
   L.ext_blocks = h->tab_ext[h->nprob];
   L.flux_blocks = h->tab_flux[shape][h->nprob];
@@ -437,6 +439,7 @@ static std::string tune_key(hgks* h) {
   for (auto& q : h->hp) cells += (size_t)q.nx * q.ny;
   k += "_c" + std::to_string(cells) + "_x" + std::to_string(h->hp[0].nx) + "_y" + std::to_string(h->hp[0].ny);
   k += "_r" + std::to_string(h->hp[0].recon) + "_e" + std::to_string(h->hp[0].eqn);
+  if (h->hp[0].tangential_flag_mode) k += "_t" + std::to_string(h->hp[0].tangential_flag_mode);
   return k;
 }
 
@@ -570,6 +573,7 @@ hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opt
     if (s) return s;
     if (probs[p].dim != probs[0].dim) return HGKS_EINVAL;
     if (!same_stepper(probs[p].stepper, probs[0].stepper)) return HGKS_EINVAL;
+    if (probs[p].tangential_flag_mode != probs[0].tangential_flag_mode) return HGKS_EINVAL;
   }
   hgks* h = new (std::nothrow) hgks;
   if (!h) return HGKS_ENOMEM;

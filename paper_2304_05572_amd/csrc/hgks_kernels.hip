@@ -368,17 +368,20 @@ __device__ inline void tangential_side(const T* sNR, int tt, int k, int s, int f
 // stage 1: W^n -> F, dF/dt; stage 2: W* -> dF/dt only (into the F arrays); stage 3: W* -> F, dF/dt
 // (the stages of a multistage tableau after the first).
 // ---------------------------------------------------------------------------------------------
-template <typename T, int TN, int TT, int DIM, bool PRFIX>
+template <typename T, int TN, int TT, int DIM, bool PRFIX, int TFM>
 __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
                                  const int* __restrict__ off, int nprob, int stage, int b) {
-  constexpr int R = (DIM == 2) ? TT + 4 : 1;  // rows with halo
-  constexpr int RO = (DIM == 2) ? 2 : 0;      // halo rows below
+  // rows with halo: two on each side, three when the tangential flag is the indicator on the line values
+  // (its widening reaches one row further)
+  constexpr int RO = (DIM == 2) ? 2 + TFM : 0;  // halo rows below
+  constexpr int R = (DIM == 2) ? TT + 2 * RO : 1;
   constexpr int C = TN + 5;                   // cells along the normal: -3 .. TN+1
   constexpr int NTH = flux_threads(TN, TT, DIM);  // 2D: two threads (Gauss points) per interface
   __shared__ T sW[4][R][C];
   __shared__ uint8_t sF[R][TN + 1];
   constexpr int NRW = nr_row<T, TN>();
   __shared__ T sNR[R * NRW];
+  __shared__ uint8_t sTL[TFM ? TT + 2 : 1][TN];  // line-value indicator of rows t0-1 .. t0+TT (bit s: side s)
 
   const int p = find_prob(off, nprob, b);
   const ProbDev& P = probs[p];
@@ -514,6 +517,32 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   }
   __syncthreads();
 
+  // ---- phase 2b (tangential_flag_mode 1): the hybrid indicator (Steps 1-3) on the line values along the
+  // interface, each side and row; phase 3 widens it over the neighbouring rows (Step 4)
+  if (DIM == 2 && TFM) {
+    const double hts = dir ? P.dx : P.dy;
+    const double thr = (P.zeta1_mode == 0) ? 5.0 * hts : 5.0 * hts * hts * hts;
+    for (int e = tid; e < (TT + 2) * TN; e += NTH) {
+      const int jj = e / TN, kk = e % TN;  // row t0 - 1 + jj: line values of rows jj .. jj + 4 of sNR
+      int tl = 0;
+      if (P.recon == 1) {
+        tl = 3;
+      } else if (P.recon == 0) {
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            double q[5];
+#pragma unroll
+            for (int r = 0; r < 5; ++r) q[r] = double(sNR[(jj + r) * NRW + kk * kNRS + 8 * sd + c]);
+            tl |= troubled5(q[0], q[1], q[2], q[3], q[4], thr) << sd;
+          }
+      }
+      sTL[jj][kk] = (uint8_t)tl;
+    }
+    __syncthreads();
+  }
+
   // ---- phase 3: tangential reconstruction at the Gauss points, equilibrium state and GKS flux. In 2D
   // lanes 2m and 2m+1 take the two Gauss points of interface m (they read the same LDS rows, which the
   // hardware broadcasts) and add their halves of F and dF/dt with one lane exchange; both lanes of a
@@ -546,13 +575,15 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
     FluxAcc<T> acc;
     T Ws[4], Wxs[4], Wys[4];
     // tangential reconstruction of one side at this Gauss point, then its share of the flux
-    tangential_side<T, TN, R>(sNR, tt, k, 0, (sF[tt + 2][k] >> 1) & 1, gp, gam, ghi, glo, eps, iht, P.positivity, Ws,
-                              Wxs, Wys);
+    // the side's flag along the interface: its cell's flag, or the widened line-value indicator
+    const int tl = TFM ? (sTL[TFM ? tt : 0][k] | sTL[TFM ? tt + 1 : 0][k] | sTL[TFM ? tt + 2 : 0][k]) : 0;
+    const int ft0 = TFM ? (tl & 1) : ((sF[tt + RO][k] >> 1) & 1);
+    const int ft1 = TFM ? ((tl >> 1) & 1) : ((sF[tt + RO][k + 1] >> 1) & 1);
+    tangential_side<T, TN, R>(sNR, tt + RO - 2, k, 0, ft0, gp, gam, ghi, glo, eps, iht, P.positivity, Ws, Wxs, Wys);
     __builtin_amdgcn_sched_barrier(0);
     flux_side<0, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
     __builtin_amdgcn_sched_barrier(0);
-    tangential_side<T, TN, R>(sNR, tt, k, 1, (sF[tt + 2][k + 1] >> 1) & 1, gp, gam, ghi, glo, eps, iht, P.positivity,
-                              Ws, Wxs, Wys);
+    tangential_side<T, TN, R>(sNR, tt + RO - 2, k, 1, ft1, gp, gam, ghi, glo, eps, iht, P.positivity, Ws, Wxs, Wys);
     __builtin_amdgcn_sched_barrier(0);
     flux_side<1, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
     __builtin_amdgcn_sched_barrier(0);
@@ -588,11 +619,11 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
 }
 
 // One block per tile; tiles are renumbered so that each XCD works on a contiguous range.
-template <typename T, int TN, int TT, int DIM, bool PRFIX, int WPE>
+template <typename T, int TN, int TT, int DIM, bool PRFIX, int TFM, int WPE>
 __global__ void __launch_bounds__(flux_threads(TN, TT, DIM)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_flux(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts, const int* __restrict__ off, int nprob,
        int stage) {
-  flux_tile<T, TN, TT, DIM, PRFIX>(probs, ts, off, nprob, stage, xcd_swizzle(blockIdx.x, gridDim.x));
+  flux_tile<T, TN, TT, DIM, PRFIX, TFM>(probs, ts, off, nprob, stage, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 // Persistent form: a grid of co-resident blocks (a multiple of 8) walks the tile list of every problem
@@ -600,7 +631,7 @@ k_flux(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts, const 
 // same contiguous tile range as above and deals it to its blocks cyclically, which spreads the costlier
 // tiles along a shock over many blocks. Every block leaves the loop after at most ceil(range / blocks)
 // tiles.
-template <typename T, int TN, int TT, int DIM, bool PRFIX, int WPE>
+template <typename T, int TN, int TT, int DIM, bool PRFIX, int TFM, int WPE>
 __global__ void __launch_bounds__(flux_threads(TN, TT, DIM)) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_flux_persistent(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts, const int* __restrict__ off,
                   int nprob, int stage, int ntiles) {
@@ -608,7 +639,7 @@ k_flux_persistent(const ProbDev* __restrict__ probs, const TimeDev* __restrict__
   const int q = ntiles >> 3, r = ntiles & 7;
   const int begin = x * q + (x < r ? x : r), end = begin + q + (x < r ? 1 : 0);
   for (int b = begin + li; b < end; b += nloc) {
-    flux_tile<T, TN, TT, DIM, PRFIX>(probs, ts, off, nprob, stage, b);
+    flux_tile<T, TN, TT, DIM, PRFIX, TFM>(probs, ts, off, nprob, stage, b);
     __syncthreads();  // the tile's LDS is dead before the next tile is staged
   }
 }
@@ -815,27 +846,28 @@ static int resident_grid(const void* fn, int threads, int ntiles) {
 }
 
 // stage 0 asks for the persistent grid size of the variant instead of launching (written to *grid)
-template <typename T, int TN, int TT, int DIM, bool PR, int WPE>
+template <typename T, int TN, int TT, int DIM, bool PR, int TFM, int WPE>
 static void flux_launch(const LaunchCtx& L, int stage, int* grid) {
   constexpr int TNd = (DIM == 1) ? TN * TT : TN, TTd = (DIM == 1) ? 1 : TT;
   constexpr int NTH = flux_threads(TNd, TTd, DIM);
   if (stage == 0) {
-    *grid = resident_grid(reinterpret_cast<const void*>(k_flux_persistent<T, TNd, TTd, DIM, PR, WPE>), NTH,
+    *grid = resident_grid(reinterpret_cast<const void*>(k_flux_persistent<T, TNd, TTd, DIM, PR, TFM, WPE>), NTH,
                           L.flux_blocks);
     return;
   }
   if (!L.persistent)
-    hipLaunchKernelGGL((k_flux<T, TNd, TTd, DIM, PR, WPE>), dim3(L.flux_blocks), dim3(NTH), 0, L.stream,
+    hipLaunchKernelGGL((k_flux<T, TNd, TTd, DIM, PR, TFM, WPE>), dim3(L.flux_blocks), dim3(NTH), 0, L.stream,
                        L.probs, L.ts, L.off_flux, L.nprob, stage);
   else
-    hipLaunchKernelGGL((k_flux_persistent<T, TNd, TTd, DIM, PR, WPE>), dim3(L.persistent_grid), dim3(NTH), 0,
+    hipLaunchKernelGGL((k_flux_persistent<T, TNd, TTd, DIM, PR, TFM, WPE>), dim3(L.persistent_grid), dim3(NTH), 0,
                        L.stream, L.probs, L.ts, L.off_flux, L.nprob, stage, L.flux_blocks);
 }
 
 template <typename T, int TN, int TT, bool PR, int WPE>
 static void flux_variant_pr(const LaunchCtx& L, int stage, int* grid) {
-  if (L.dim == 1) flux_launch<T, TN, TT, 1, PR, WPE>(L, stage, grid);
-  else flux_launch<T, TN, TT, 2, PR, WPE>(L, stage, grid);
+  if (L.dim == 1) flux_launch<T, TN, TT, 1, PR, 0, WPE>(L, stage, grid);
+  else if (L.tfm) flux_launch<T, TN, TT, 2, PR, 1, WPE>(L, stage, grid);
+  else flux_launch<T, TN, TT, 2, PR, 0, WPE>(L, stage, grid);
 }
 
 // the Prandtl-number correction is compiled in only for launches that need it (NS with Pr != 1)

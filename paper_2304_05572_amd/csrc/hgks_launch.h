@@ -30,6 +30,7 @@ struct LaunchCtx {
   int persistent_grid;
   int prfix;             // 1 if any problem is Navier-Stokes with Pr != 1
   int positivity;        // 1 if any problem asks for the first-order fallbacks
+  int tfm;               // tangential flag: 0 the side cell's flag, 1 the indicator on the line values (2D)
   int cell_blocks, ext_blocks, flux_blocks;  // flux_blocks: tiles of all problems
 };
 

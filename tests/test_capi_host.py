@@ -62,7 +62,8 @@ def test_status_strings():
 @pytest.mark.parametrize("bad", [
     dict(nx=4), dict(dim=3), dict(gamma=1.0), dict(bc=(0, 1, 1, 1)), dict(dim=1, ny=3),
     dict(eqn=1, Pr=0.0), dict(recon=5), dict(cfl=0.0), dict(x1=0.0), dict(gamma_hi=1.0),
-    dict(tangential_flag_mode=1), dict(positivity=2),
+    dict(tangential_flag_mode=2), dict(dim=1, ny=1, tangential_flag_mode=1), dict(positivity=2),
+    dict(dim=3, nz=8, tangential_flag_mode=1),
     # prescribed-state sides: no data (rest 0), a periodic rest, NaN split, non-physical states
     dict(bc=(4, 1, 1, 1)), dict(bc=(4, 1, 1, 1), bcd=(H.BcData(rest=0),)),
     dict(bc=(0, 4, 1, 1), bcd=(None, H.BcData())),
@@ -102,6 +103,12 @@ def test_mixed_steppers_and_compensated_tableau_rejected():
     assert e.value.code == H.EINVAL
     with pytest.raises(H.HgksError) as e:
         H.hgks_create([H.Problem(stepper=one)], compensated=1)
+    assert e.value.code == H.EINVAL
+
+
+def test_mixed_tangential_flag_modes_rejected():
+    with pytest.raises(H.HgksError) as e:
+        H.hgks_create([H.Problem(), H.Problem(tangential_flag_mode=1)])
     assert e.value.code == H.EINVAL
 
 
