@@ -458,7 +458,7 @@ def main():
             tr = float(traffic[key])
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_VALU, "traffic": tr,
-                "kernel": ("k_flux_persistent" if r["tile"][4] else "k_flux") + "<double, %d, %d, 2, false, %d>"
+                "kernel": ("k_flux_persistent" if r["tile"][4] else "k_flux") + "<double, %d, %d, 2, false, 0, %d>"
                           % (r["tile"][0], r["tile"][1], r["tile"][2]) + " (fused reconstruction + GKS flux)",
                 "ms_per_launch": r["flux_ms"],
                 "flops_per_launch": fl * gps, "flops_per_gauss_point": fl, "gauss_points_per_launch": gps,
