@@ -147,6 +147,12 @@ typedef struct {
   double z0, z1;                /* z-high sides in bcz (periodic, outflow, reflect or no-slip; bc[0..3] hold  */
   int32_t bcz[2];               /* x and y). Ignored for dim 1 and 2. */
   hgks_stepper stepper;         /* zero-initialised: S2O4 */
+  int32_t char_state_mode;      /* 2D: state whose characteristic variables the tangential WENO-AO uses:
+                                   0 the reconstructing side's own line value of the centre segment
+                                   (default), 1 the mean of both sides' (Sec. 2.3.1's "averaged
+                                   conservative variables from both sides" applied along the interface) */
+  int32_t viscous_dt_mode;      /* Navier-Stokes time step (Sec. 3): 0 h^2 / (4 nu) with nu = mu / rho
+                                   (default), 1 the printed nu = mu / p */
 } hgks_problem;
 
 typedef struct {

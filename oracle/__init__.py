@@ -79,7 +79,7 @@ class _Problem(C.Structure):
         ("gamma_hi", C.c_double), ("gamma_lo", C.c_double), ("weno_eps", C.c_double),
         ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32), ("positivity", C.c_int32),
         ("bcd", _BcData * 4), ("nz", C.c_int32), ("z0", C.c_double), ("z1", C.c_double), ("bcz", C.c_int32 * 2),
-        ("stepper", _Stepper),
+        ("stepper", _Stepper), ("char_state_mode", C.c_int32), ("viscous_dt_mode", C.c_int32),
     ]
 
 
@@ -115,6 +115,8 @@ class Problem:
     z1: float = 1.0
     bcz: tuple = (BC_OUTFLOW, BC_OUTFLOW)
     stepper: object = None  # Stepper (or its fields as a dict); None: the built-in S2O4
+    char_state_mode: int = 0  # 2D: tangential characteristic state, 0 own side, 1 mean of both sides
+    viscous_dt_mode: int = 0  # NS time step: 0 nu = mu / rho, 1 nu = mu / p
 
     @property
     def nc(self) -> int:

@@ -256,6 +256,7 @@ typedef struct {
   double ghi, glo, eps;
   int recon, zeta1_mode, positivity;
   int tfm;  /* tangential flag: 0 the side cell's flag, 1 the indicator on the line values */
+  int csm;  /* tangential characteristic state: 0 own side, 1 mean of both sides */
 } params;
 
 /* q5[r][c]: the side's five cells (offsets -2..2), xi: evaluation point. Unflagged: component-wise
@@ -653,6 +654,7 @@ static void make_params(const oracle_problem* p, params* pp) {
   pp->zeta1_mode = p->zeta1_mode;
   pp->positivity = p->positivity;
   pp->tfm = p->tangential_flag_mode;
+  pp->csm = p->char_state_mode;
 }
 
 static int check_problem(const oracle_problem* p) {
@@ -662,6 +664,8 @@ static int check_problem(const oracle_problem* p) {
   if (p->eqn == 1 && !(p->Pr > 0.0 && p->mu >= 0.0)) return ORACLE_EINVAL;
   if (p->positivity != 0 && p->positivity != 1) return ORACLE_EINVAL;
   if (p->tangential_flag_mode != 0 && !(p->dim == 2 && p->tangential_flag_mode == 1)) return ORACLE_EINVAL;
+  if (p->char_state_mode != 0 && !(p->dim == 2 && p->char_state_mode == 1)) return ORACLE_EINVAL;
+  if (p->viscous_dt_mode != 0 && p->viscous_dt_mode != 1) return ORACLE_EINVAL;
   int nb = p->dim == 2 ? 4 : 2;
   for (int s = 0; s < nb; ++s) {
     if (p->bc[s] < 0 || p->bc[s] > 4) return ORACLE_EINVAL;
@@ -965,7 +969,8 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
           }
           if (ftf[s]) {
             double own[MAXC];
-            for (int c = 0; c < nc; ++c) own[c] = LVAT(2 * s, c, j, k);
+            for (int c = 0; c < nc; ++c)
+              own[c] = pp->csm ? 0.5 * (LVAT(0, c, j, k) + LVAT(2, c, j, k)) : LVAT(2 * s, c, j, k);
             char_R(f->dim, 2, own, pp->gamma, R[s]);
             mat_inverse(nc, R[s], L[s]);
           }
@@ -1093,7 +1098,7 @@ double oracle_cfl_dt(const oracle_problem* p, const double* W) {
     double sp = sqrt(U * U + V * V) + c;
     double q = h / sp;
     if (p->eqn == 1) {
-      double qv = (h * h) / (4.0 * (p->mu / rho));
+      double qv = (h * h) / (4.0 * (p->mu / (p->viscous_dt_mode ? pr : rho)));
       q = fmin(q, qv);
     }
     qmin = fmin(qmin, q);
@@ -1887,7 +1892,7 @@ double oracle_cfl_dt3(const oracle_problem* p, const double* W) {
     double pr = (p->gamma - 1.0) * (W[4 * nc + s] - 0.5 * rho * (U * U + V * V + Z * Z));
     double c = sqrt(p->gamma * pr / rho);
     double q = h / (sqrt(U * U + V * V + Z * Z) + c);
-    if (p->eqn == 1) q = fmin(q, (h * h) / (4.0 * (p->mu / rho)));
+    if (p->eqn == 1) q = fmin(q, (h * h) / (4.0 * (p->mu / (p->viscous_dt_mode ? pr : rho))));
     qmin = fmin(qmin, q);
   }
   return p->cfl * qmin;
@@ -1897,7 +1902,8 @@ static int check_problem3(const oracle_problem* p) {
   if (p->nx < 5 || p->ny < 5 || p->nz < 5) return ORACLE_EINVAL;
   if (!(p->gamma > 1.0) || !(p->x1 > p->x0) || !(p->y1 > p->y0) || !(p->z1 > p->z0)) return ORACLE_EINVAL;
   if (p->eqn == 1 && !(p->Pr == 1.0 && p->mu >= 0.0)) return ORACLE_EINVAL;
-  if (p->positivity != 0 || p->tangential_flag_mode != 0) return ORACLE_EINVAL;
+  if (p->positivity != 0 || p->tangential_flag_mode != 0 || p->char_state_mode != 0) return ORACLE_EINVAL;
+  if (p->viscous_dt_mode != 0 && p->viscous_dt_mode != 1) return ORACLE_EINVAL;
   int k[6] = {p->bc[0], p->bc[1], p->bc[2], p->bc[3], p->bcz[0], p->bcz[1]};
   for (int s = 0; s < 6; ++s)
     if (k[s] < 0 || k[s] > 3) return ORACLE_EINVAL;

@@ -69,6 +69,9 @@ typedef struct {
   double z0, z1;                /* sides in bcz (0..3); bc[0..3] hold the x and y sides */
   int32_t bcz[2];
   oracle_stepper stepper;       /* stages 1..3: no prescribed sides, positivity 0 */
+  int32_t char_state_mode;      /* 2D: tangential characteristic state: 0 the side's own centre line value,
+                                   1 the mean of both sides' */
+  int32_t viscous_dt_mode;      /* NS time step: 0 nu = mu / rho, 1 nu = mu / p as printed */
 } oracle_problem;
 
 enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_ENONPHYS = -4, ORACLE_EDT = -5 };

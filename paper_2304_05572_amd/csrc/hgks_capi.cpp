@@ -70,7 +70,8 @@ static hgks_status validate3(const hgks_problem& p) {
   if (p.eqn != HGKS_EULER && p.eqn != HGKS_NS) return HGKS_EINVAL;
   if (p.eqn == HGKS_NS && !(p.Pr == 1.0 && p.mu >= 0.0)) return HGKS_EINVAL;  // no Prandtl correction in 3D
   if (p.c1 < 0.0 || p.c2 < 0.0 || p.recon < 0 || p.recon > 2 || p.tangential_flag_mode != 0) return HGKS_EINVAL;
-  if (p.positivity != 0) return HGKS_EINVAL;
+  if (p.positivity != 0 || p.char_state_mode != 0) return HGKS_EINVAL;
+  if (p.viscous_dt_mode != 0 && p.viscous_dt_mode != 1) return HGKS_EINVAL;
   if (!(p.gamma_hi > 0.0 && p.gamma_hi < 1.0) || !(p.gamma_lo > 0.0 && p.gamma_lo < 1.0) || !(p.weno_eps > 0.0))
     return HGKS_EINVAL;
   const int k[6] = {p.bc[0], p.bc[1], p.bc[2], p.bc[3], p.bcz[0], p.bcz[1]};
@@ -120,6 +121,8 @@ static hgks_status validate(const hgks_problem& p) {
   if (p.eqn == HGKS_NS && !(p.Pr > 0.0 && p.mu >= 0.0)) return HGKS_EINVAL;
   if (p.c1 < 0.0 || p.c2 < 0.0 || p.recon < 0 || p.recon > 2) return HGKS_EINVAL;
   if (p.tangential_flag_mode != 0 && !(p.dim == 2 && p.tangential_flag_mode == 1)) return HGKS_EINVAL;
+  if (p.char_state_mode != 0 && !(p.dim == 2 && p.char_state_mode == 1)) return HGKS_EINVAL;
+  if (p.viscous_dt_mode != 0 && p.viscous_dt_mode != 1) return HGKS_EINVAL;
   if (p.positivity != 0 && p.positivity != 1) return HGKS_EINVAL;
   if (!(p.gamma_hi > 0.0 && p.gamma_hi < 1.0) || !(p.gamma_lo > 0.0 && p.gamma_lo < 1.0) || !(p.weno_eps > 0.0))
     return HGKS_EINVAL;
@@ -276,6 +279,7 @@ static hgks_status materialise(hgks* h) {
       B.rest = q.bcd[s].rest;
     }
     d.recon = q.recon; d.zeta1_mode = q.zeta1_mode; d.positivity = q.positivity;
+    d.csm = q.char_state_mode; d.vdt = q.viscous_dt_mode;
     d.x0 = q.x0; d.y0 = q.dim >= 2 ? q.y0 : 0.0;
     d.nz = q.dim == 3 ? q.nz : 1;
     d.bcz[0] = q.dim == 3 ? q.bcz[0] : 0;

@@ -29,6 +29,8 @@ struct ProbDev {
   int recon, zeta1_mode;
   int positivity;            // 1: non-physical reconstructed states drop to first order
   int prescribed;            // 1 if any side is a prescribed-state side (bc == 4)
+  int csm;                   // tangential characteristic state: 0 own side, 1 mean of both sides (2D)
+  int vdt;                   // Navier-Stokes time step: 0 nu = mu / rho, 1 nu = mu / p
   double x0, y0;             // lower-left corner (ghost centres of prescribed sides)
   double dx, dy, h;          // cell sizes; h = min(dx, dy) for the CFL step
   double gamma, K, mu, Pr, c1, c2;  // K: internal dof of the 2D model (1D problems embed into it)

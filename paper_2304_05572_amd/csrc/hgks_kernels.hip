@@ -29,7 +29,7 @@ __device__ inline double cfl_quantity(const ProbDev& P, double rho, double mu_, 
   const double sp = sqrt(U * U + V * V) + c;
   double q = P.h / sp;
   if (P.ns) {
-    const double qv = (P.h * P.h) / (4.0 * (P.mu / rho));
+    const double qv = (P.h * P.h) / (4.0 * (P.mu / (P.vdt ? pr : rho)));
     q = fmin(q, qv);
   }
   return q;
@@ -301,17 +301,20 @@ constexpr int flux_threads(int tn, int tt, int dim) { return (dim == 2 ? 2 : 1) 
 // Tangential reconstruction (Sec. 2.3.3, Step 2) of side s of interface column k at Gauss point gp from
 // the line averages of rows tt..tt+4 (value line W^s and normal-slope line W^s_x): values at the Gauss
 // point, tangential slope of W^s, value of W^s_x. Linear quartic per component, or WENO-AO in the
-// tangential characteristic variables about the side's own centre-segment state when flagged.
+// tangential characteristic variables about the side's own centre-segment state (csm = 0) or the mean of
+// both sides' (csm = 1) when flagged.
 template <typename T, int TN, int R>
 __device__ inline void tangential_side(const T* sNR, int tt, int k, int s, int ft, int gp, T gam, T ghi,
-                                       T glo, T eps, T iht, int pos, T Ws[4], T Wxs[4], T Wys[4]) {
+                                       T glo, T eps, T iht, int pos, int csm, T Ws[4], T Wxs[4], T Wys[4]) {
   constexpr int NRW = nr_row<T, TN>();
   const int ov = 8 * s, od = 8 * s + 4;
   if (ft) {
     CharMat<T> m;
     T own[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) own[v] = sNR[(tt + 2) * NRW + k * kNRS + ov + v];
+    for (int v = 0; v < 4; ++v)
+      own[v] = csm ? T(0.5) * (sNR[(tt + 2) * NRW + k * kNRS + v] + sNR[(tt + 2) * NRW + k * kNRS + 8 + v])
+                   : sNR[(tt + 2) * NRW + k * kNRS + ov + v];
     char_matrices(own, gam, 2, m);
     T qv[5][4], qd[5][4], val[4], der[4];
 #pragma unroll
@@ -579,11 +582,13 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
     const int tl = TFM ? (sTL[TFM ? tt : 0][k] | sTL[TFM ? tt + 1 : 0][k] | sTL[TFM ? tt + 2 : 0][k]) : 0;
     const int ft0 = TFM ? (tl & 1) : ((sF[tt + RO][k] >> 1) & 1);
     const int ft1 = TFM ? ((tl >> 1) & 1) : ((sF[tt + RO][k + 1] >> 1) & 1);
-    tangential_side<T, TN, R>(sNR, tt + RO - 2, k, 0, ft0, gp, gam, ghi, glo, eps, iht, P.positivity, Ws, Wxs, Wys);
+    tangential_side<T, TN, R>(sNR, tt + RO - 2, k, 0, ft0, gp, gam, ghi, glo, eps, iht, P.positivity, P.csm, Ws, Wxs,
+                              Wys);
     __builtin_amdgcn_sched_barrier(0);
     flux_side<0, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
     __builtin_amdgcn_sched_barrier(0);
-    tangential_side<T, TN, R>(sNR, tt + RO - 2, k, 1, ft1, gp, gam, ghi, glo, eps, iht, P.positivity, Ws, Wxs, Wys);
+    tangential_side<T, TN, R>(sNR, tt + RO - 2, k, 1, ft1, gp, gam, ghi, glo, eps, iht, P.positivity, P.csm, Ws, Wxs,
+                              Wys);
     __builtin_amdgcn_sched_barrier(0);
     flux_side<1, PRFIX>(Ws, Wxs, Wys, gam, K, Kp2, iKp2, acc);
     __builtin_amdgcn_sched_barrier(0);

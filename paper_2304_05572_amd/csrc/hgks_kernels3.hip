@@ -325,7 +325,7 @@ __device__ inline double cfl_quantity3(const ProbDev& P, double rho, double mx, 
   const double pr = (P.gamma - 1.0) * (E - 0.5 * rho * (U * U + V * V + Z * Z));
   const double c = sqrt(P.gamma * pr / rho);
   double q = P.h / (sqrt(U * U + V * V + Z * Z) + c);
-  if (P.ns) q = fmin(q, (P.h * P.h) / (4.0 * (P.mu / rho)));
+  if (P.ns) q = fmin(q, (P.h * P.h) / (4.0 * (P.mu / (P.vdt ? pr : rho))));
   return q;
 }
 

@@ -22,7 +22,7 @@ __device__ inline double cfl_quantity_any(const ProbDev& P, const double* w) {
   const double pr = (P.gamma - 1.0) * (w[nc - 1] - 0.5 * rho * q2);
   const double c = sqrt(P.gamma * pr / rho);
   double q = P.h / (sqrt(q2) + c);
-  if (P.ns) q = fmin(q, (P.h * P.h) / (4.0 * (P.mu / rho)));
+  if (P.ns) q = fmin(q, (P.h * P.h) / (4.0 * (P.mu / (P.vdt ? pr : rho))));
   return q;
 }
 

@@ -98,7 +98,7 @@ class hgks_problem(C.Structure):
         ("zeta1_mode", C.c_int32), ("tangential_flag_mode", C.c_int32), ("positivity", C.c_int32),
         ("bcd", hgks_bc_data * 4),
         ("nz", C.c_int32), ("z0", C.c_double), ("z1", C.c_double), ("bcz", C.c_int32 * 2),
-        ("stepper", hgks_stepper),
+        ("stepper", hgks_stepper), ("char_state_mode", C.c_int32), ("viscous_dt_mode", C.c_int32),
     ]
 
 
@@ -141,6 +141,8 @@ class Problem:
     z1: float = 1.0
     bcz: tuple = (BC_OUTFLOW,) * 2
     stepper: object = None  # Stepper (or its fields as a dict); None: S2O4
+    char_state_mode: int = 0  # 2D: tangential characteristic state, 0 own side, 1 mean of both sides
+    viscous_dt_mode: int = 0  # NS time step: 0 nu = mu / rho, 1 the printed nu = mu / p
 
     @property
     def nc(self):

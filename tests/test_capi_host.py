@@ -64,6 +64,8 @@ def test_status_strings():
     dict(eqn=1, Pr=0.0), dict(recon=5), dict(cfl=0.0), dict(x1=0.0), dict(gamma_hi=1.0),
     dict(tangential_flag_mode=2), dict(dim=1, ny=1, tangential_flag_mode=1), dict(positivity=2),
     dict(dim=3, nz=8, tangential_flag_mode=1),
+    dict(char_state_mode=2), dict(dim=1, ny=1, char_state_mode=1), dict(dim=3, nz=8, char_state_mode=1),
+    dict(viscous_dt_mode=2), dict(dim=3, nz=8, viscous_dt_mode=-1),
     # prescribed-state sides: no data (rest 0), a periodic rest, NaN split, non-physical states
     dict(bc=(4, 1, 1, 1)), dict(bc=(4, 1, 1, 1), bcd=(H.BcData(rest=0),)),
     dict(bc=(0, 4, 1, 1), bcd=(None, H.BcData())),
