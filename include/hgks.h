@@ -132,12 +132,15 @@ typedef struct {
                                    cell's flag along the interface (default); 1 (2D only) the hybrid
                                    indicator (Steps 1-4) on the line values along the interface. All problems
                                    of a handle take the same mode. */
-  int32_t positivity;           /* 0: the scheme as the paper states it. 1: two first-order fallbacks.
+  int32_t positivity;           /* 0: the scheme as the paper states it. 1: three first-order fallbacks.
                                    A reconstructed state with rho <= 0 or p <= 0 (or not finite) drops to
                                    first order in space: a normal interface value takes its cell's average
                                    with zero normal slope, a Gauss-point value the interface's
-                                   centre-segment line values with zero tangential slope. And every face of
-                                   a cell that the S2O4 update leaves non-physical takes the one-stage flux
+                                   centre-segment line values with zero tangential slope. Every face of a
+                                   cell whose first-stage state W* is non-physical takes, for W*, the
+                                   gas-kinetic flux of the two cell averages (no slopes) over [0, dt/2].
+                                   And every face of a cell that the S2O4 update leaves non-physical takes
+                                   the one-stage flux
                                    F^n + dt/2 dF^n/dt of the first stage (first order lower in time, still
                                    conservative); a cell still non-physical then is reported. The paper
                                    gives no positivity treatment; its double Mach reflection and blast wave

@@ -1202,6 +1202,48 @@ int oracle_step(const oracle_problem* p, double* W, double* t, double t_end, dou
         size_t o = (size_t)c * ncell + (size_t)j * nx + i;
         Ws[o] = W[o] - (a + b);
       }
+  if (pp.positivity && nonphysical(p, Ws)) {
+    /* first-order fallback of the first stage: every face of a cell whose intermediate state is
+     * non-physical takes the gas-kinetic flux of the two cell averages (constant states, no slopes) over
+     * [0, dt/2] in place of the reconstructed one, for both of its cells; then update again */
+    uint8_t* bad = (uint8_t*)calloc(ncell, 1);
+    for (size_t s = 0; s < ncell; ++s) bad[s] = !admissible_cell(p, Ws, s);
+    const double z[MAXC] = {0};
+    for (int dir = 0; dir < dim; ++dir) {
+      frame f;
+      build_frame(p, W, *t, dir, &f);
+      for (int row = 0; row < f.nt; ++row)
+        for (int k = 0; k <= f.nn; ++k) {
+          /* the face's cells in grid indices: (k-1, row), (k, row) along x; (row, k-1), (row, k) along y */
+          int b0 = 0, b1 = 0;
+          if (k >= 1) b0 = bad[dir ? (size_t)(k - 1) * nx + row : (size_t)row * nx + (k - 1)];
+          if (k < f.nn) b1 = bad[dir ? (size_t)k * nx + row : (size_t)row * nx + k];
+          if (!(b0 | b1)) continue;
+          double Wl[MAXC], Wr[MAXC], Fdg[MAXC], Fhg[MAXC];
+          for (int c = 0; c < nc; ++c) {
+            Wl[c] = *fr_at(&f, c, row, k - 1);
+            Wr[c] = *fr_at(&f, c, row, k);
+          }
+          gp_flux(&pp, Wl, z, z, Wr, z, z, dt, Fdg, Fhg, NULL);
+          for (int c = 0; c < nc; ++c) {
+            int cs = (dir && c == 1) ? 2 : (dir && c == 2) ? 1 : c; /* frame slot -> grid component */
+            if (dir == 0) Fxh[((size_t)cs * ny + row) * (nx + 1) + k] = Fhg[c];
+            else Fyh[((size_t)cs * (ny + 1) + k) * nx + row] = Fhg[c];
+          }
+        }
+      free(f.P);
+    }
+    free(bad);
+    for (int c = 0; c < nc; ++c)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          double a = (Fxh[((size_t)c * ny + j) * (nx + 1) + i + 1] - Fxh[((size_t)c * ny + j) * (nx + 1) + i]) / dx;
+          double b = 0.0;
+          if (dim == 2) b = (Fyh[((size_t)c * (ny + 1) + j + 1) * nx + i] - Fyh[((size_t)c * (ny + 1) + j) * nx + i]) / dy;
+          size_t o = (size_t)c * ncell + (size_t)j * nx + i;
+          Ws[o] = W[o] - (a + b);
+        }
+  }
   if (nonphysical(p, Ws)) rc = ORACLE_ENONPHYS;
   if (!rc) {
     /* stage 2 at t* = t_n + dt/2: only the time derivative of the flux is needed */

@@ -62,8 +62,10 @@ typedef struct {
   int32_t positivity;           /* 0: the scheme as the paper states it. 1: first-order fallbacks: a
                                    reconstructed interface or Gauss-point state with rho <= 0 or p <= 0 is
                                    replaced by the state of the cell (or centre segment) it belongs to, with
-                                   zero slopes; and the faces of a cell that the S2O4 update leaves
-                                   non-physical take the one-stage flux F^n + dt/2 dF^n/dt */
+                                   zero slopes; the faces of a cell whose first-stage state W* is
+                                   non-physical take, for W*, the flux of the two cell averages with zero
+                                   slopes over [0, dt/2]; and the faces of a cell that the S2O4 update
+                                   leaves non-physical take the one-stage flux F^n + dt/2 dF^n/dt */
   oracle_bc_data bcd[4];        /* per side, read where bc[side] == 4 */
   int32_t nz;                   /* 3D (dim == 3): cells along z on [z0, z1], kinds of the z-low and z-high */
   double z0, z1;                /* sides in bcz (0..3); bc[0..3] hold the x and y sides */

@@ -428,6 +428,7 @@ static void enqueue_step(hgks* h, int use_tend, bool capturing = false) {
   timed(h, 2, capturing, [&] { launch_flags(L, 0, 1, 0); });
   timed(h, 0, capturing, [&] { launch_flux(L, 1); });
   timed(h, 1, capturing, [&] { launch_update(L, 1); });
+  if (L.positivity) timed(h, 1, capturing, [&] { launch_repair1(L); });
   timed(h, 2, capturing, [&] { launch_flags(L, 1, 0, 0); });
   timed(h, 0, capturing, [&] { launch_flux(L, 2); });
   timed(h, 1, capturing, [&] { launch_update(L, 2); });

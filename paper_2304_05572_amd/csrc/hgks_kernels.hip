@@ -729,7 +729,7 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
     const double ke = 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / rho;
     const double pr = (P.gamma - 1.0) * (wn[3] - ke);
     bad = !(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf());
-    if (bad && stage == 2 && P.positivity)  // left to k_repair: mark the cell (flag bit 2)
+    if (bad && P.positivity)  // left to k_repair1 / k_repair: mark the cell (flag bit 2)
       P.flags[(P.dim == 2 ? (size_t)(j + 2) * (P.nx + 4) : 0) + (i + 2)] |= 4;
     else if (bad)
       atomicOr(&tsp.status, 1);
@@ -739,6 +739,106 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
     q = block_min(q);
     if (threadIdx.x == 0) qpart[blockIdx.x] = q;
   }
+}
+
+// Gas-kinetic flux of two constant states (frame components, no slopes) over [0, dt/2] of the current
+// step: dt/2 F + dt^2/8 dF/dt with F, dF/dt from the flux function (Sec. 2.1-2.2), in FP64.
+template <bool PRFIX>
+__device__ inline void constant_state_half_flux(const ProbDev& P, const TimeDev& tsp, const double Wl[4],
+                                                const double Wr[4], double out[4]) {
+  FluxParams fp;
+  fp.gamma = P.gamma; fp.K = P.K; fp.mu = P.mu; fp.Pr = P.Pr; fp.c1 = P.c1; fp.c2 = P.c2;
+  fp.Kp2 = P.Kp2; fp.iKp2 = P.iKp2; fp.kpr = P.kpr;
+  fp.dt = tsp.dt; fp.dth = tsp.dth; fp.idt = tsp.idt; fp.idt2 = tsp.idt2;
+  fp.ns = P.ns; fp.want_F = true;
+  const double z[4] = {0, 0, 0, 0};
+  FluxAcc<double> acc;
+  flux_side<0, PRFIX>(Wl, z, z, P.gamma, P.K, P.Kp2, P.iKp2, acc);
+  flux_side<1, PRFIX>(Wr, z, z, P.gamma, P.K, P.Kp2, P.iKp2, acc);
+  double F[4] = {0, 0, 0, 0}, dF[4] = {0, 0, 0, 0};
+  flux_finish<PRFIX>(acc, fp, 1.0, F, dF);
+  const double dt = tsp.dt;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[v] = dt * (0.5 * F[v] + 0.125 * dt * dF[v]);
+}
+
+// First-order fallback of the first stage (problems with positivity = 1): every face next to a cell whose
+// intermediate state W* came out non-physical (flag bit 2, set by k_update in stage 1) takes the
+// gas-kinetic flux of the two cell averages (constant states, no slopes) over [0, dt/2] in place of the
+// reconstructed dt/2 F + dt^2/8 dF/dt; both cells of such a face see the same flux (conservative). Cells
+// still non-physical set the problem's status.
+template <typename T>
+__global__ void __launch_bounds__(256) k_repair1(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
+                                                 const int* __restrict__ off, int nprob) {
+  const int p = find_prob(off, nprob, blockIdx.x);
+  const ProbDev& P = probs[p];
+  TimeDev& tsp = ts[p];
+  if (!tsp.active || !P.positivity) return;
+  const size_t ncell = (size_t)P.nx * P.ny;
+  const size_t cell = (size_t)(blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
+  if (cell >= ncell) return;
+  const int i = (int)(cell % P.nx), j = (int)(cell / P.nx);
+  const int two = P.dim == 2;
+  const size_t ex = (size_t)P.nx + 4;
+  auto marked = [&](int a, int b) -> int {
+    if (a < 0 || a >= P.nx || b < 0 || b >= P.ny) return 0;
+    return (P.flags[(two ? (size_t)(b + 2) * ex : 0) + (a + 2)] >> 2) & 1;
+  };
+  const int m0 = marked(i, j);
+  const int mf[4] = {m0 | marked(i - 1, j), m0 | marked(i + 1, j), two ? (m0 | marked(i, j - 1)) : 0,
+                     two ? (m0 | marked(i, j + 1)) : 0};  // faces x-low, x-high, y-low, y-high
+  if (!(mf[0] | mf[1] | mf[2] | mf[3])) return;
+  const int nc = P.dim + 2;
+  const double dt = tsp.dt, tb = tsp.t;
+  const T* Fx = reinterpret_cast<const T*>(P.Fx);
+  const T* Gx = reinterpret_cast<const T*>(P.Gx);
+  const T* Fy = reinterpret_cast<const T*>(P.Fy);
+  const T* Gy = reinterpret_cast<const T*>(P.Gy);
+  const size_t px = (size_t)P.ny * (P.nx + 1), py = (size_t)(P.ny + 1) * P.nx;
+  const size_t ox = (size_t)j * (P.nx + 1) + i, oy = (size_t)j * P.nx + i;
+  const bool prfix = P.ns && P.Pr != 1.0;
+  double dW[4] = {0, 0, 0, 0};  // change of W*, frame slots of the grid components
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    if (!mf[f]) continue;
+    const int ydir = f >= 2, high = f & 1;
+    double a[4], b[4], fo[4];
+    if (!ydir) {  // cells i - 1 + high and i + high
+      load_cell(P, P.W, i - 1 + high, j, tb, a);
+      load_cell(P, P.W, i + high, j, tb, b);
+    } else {      // frame of a y-face: the tangential and normal momenta swap
+      load_cell(P, P.W, i, j - 1 + high, tb, a);
+      load_cell(P, P.W, i, j + high, tb, b);
+      double t0 = a[1]; a[1] = a[2]; a[2] = t0;
+      t0 = b[1]; b[1] = b[2]; b[2] = t0;
+    }
+    if (prfix) constant_state_half_flux<true>(P, tsp, a, b, fo);
+    else constant_state_half_flux<false>(P, tsp, a, b, fo);
+    if (ydir) { const double t0 = fo[1]; fo[1] = fo[2]; fo[2] = t0; }
+    const double ih = ydir ? 1.0 / P.dy : 1.0 / P.dx;
+    const double sg = high ? -1.0 : 1.0;  // W* = W - (F_high - F_low) / h
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c >= nc) break;
+      const int slot = (c == nc - 1) ? 3 : c;  // grid component -> frame slot (1D has no slot 2)
+      const size_t o = ydir ? c * py + oy + (high ? P.nx : 0) : c * px + ox + high;
+      const double cur = ydir ? dt * (0.5 * double(Fy[o]) + 0.125 * dt * double(Gy[o]))
+                              : dt * (0.5 * double(Fx[o]) + 0.125 * dt * double(Gx[o]));
+      dW[slot] += sg * (fo[slot] - cur) * ih;
+    }
+  }
+  double wn[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= nc) break;
+    const int slot = (c == nc - 1) ? 3 : c;
+    const double w = P.Ws[c * ncell + cell] + dW[slot];
+    P.Ws[c * ncell + cell] = w;
+    wn[slot] = w;
+  }
+  const double rho = wn[0];
+  const double pr = (P.gamma - 1.0) * (wn[3] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / rho);
+  if (!(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf())) atomicOr(&tsp.status, 1);
 }
 
 // Time-order fallback after the second stage (problems with positivity = 1): every face next to a cell
@@ -913,6 +1013,15 @@ int flux_persistent_grid(const LaunchCtx& L) {
   if (L.fp32) launch_flux_t<float>(L, 0, &g);
   else launch_flux_t<double>(L, 0, &g);
   return g;
+}
+
+void launch_repair1(const LaunchCtx& L) {
+  if (L.fp32)
+    hipLaunchKernelGGL(k_repair1<float>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
+                       L.nprob);
+  else
+    hipLaunchKernelGGL(k_repair1<double>, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell,
+                       L.nprob);
 }
 
 void launch_repair(const LaunchCtx& L) {

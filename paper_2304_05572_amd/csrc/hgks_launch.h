@@ -62,6 +62,7 @@ void launch_flux(const LaunchCtx& L, int stage);
 int flux_persistent_grid(const LaunchCtx& L);  // blocks of the persistent flux launch for L's variant
 void launch_update(const LaunchCtx& L, int stage);
 void launch_repair(const LaunchCtx& L);
+void launch_repair1(const LaunchCtx& L);  // first-stage fallback (problems with positivity = 1)
 // One stage of a two-derivative multistage tableau (stage i of `stages`): its own weights b, bh in the
 // new state, the coefficients a, ah of its operators in the next stage's state (n1, nh1) and in the one
 // after (n2, nh2, three-stage tableaux after the first stage only).

@@ -434,3 +434,25 @@ def test_viscous_shock_tube_runs():
     assert ns == 150 and t > 0.3
     assert W[0].min() > 0
     assert W[0].sum() == pytest.approx(W0[0].sum(), rel=1e-4)  # no-slip ghost walls: truncation-level
+
+
+def test_first_stage_fallback_rescues_a_non_physical_intermediate_state():
+    """Strong jumps at CFL 0.8 with c1 = 0: the high-order first-stage state W* = W - div F(dt/2) has
+    non-physical cells. With positivity = 1 the faces of those cells take the flux of the constant cell
+    averages over [0, dt/2] and the step completes with a physical state; without, it is reported."""
+    from _stage1_case import stage1_case
+    W, kw = stage1_case()
+    P = O.Problem(**kw)
+    dt = O.cfl_dt(P, W)
+    Fx, Gx, Fy, Gy = O.stage_fluxes(P, W, dt, nthreads=NT)
+    Fxh, Fyh = Fx * dt / 2 + Gx * dt * dt / 8, Fy * dt / 2 + Gy * dt * dt / 8
+    ny, nx = W.shape[1:]
+    Ws = W - ((Fxh[:, :, 1:] - Fxh[:, :, :-1]) * nx + (Fyh[:, 1:, :] - Fyh[:, :-1, :]) * ny)
+    r, _, _, p = wl.cons_to_prim(Ws)
+    assert ((r <= 0) | (p <= 0) | ~np.isfinite(p)).any()
+    Wn, t, dt2 = O.step(P, W, 0.0, nthreads=NT)
+    r, _, _, p = wl.cons_to_prim(Wn)
+    assert dt2 == dt and r.min() > 0 and p.min() > 0
+    with pytest.raises(O.OracleError) as e:
+        O.step(O.Problem(**dict(kw, positivity=0)), W, 0.0, nthreads=NT)
+    assert e.value.code == O.ENONPHYS
