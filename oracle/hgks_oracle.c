@@ -549,6 +549,20 @@ static void gp_flux(const params* pp, const double* Wl, const double* Wxl, const
   /* equilibrium g0 at the interface */
   maxw g0;
   maxw_from_W(pp, Wc, 0, &g0);
+  /* interface vacuum: two physical sides (positive, finite pressures; a non-physical side leaves NaN
+   * moments and is reported as such) whose half-space integrals leave no equilibrium (density zero or
+   * temperature not positive and finite) give a face without flux. Two states separating at many
+   * thermal speeds reach this where the integrals underflow; every term carries a factor of those
+   * vanishing integrals, so zero is their limit. */
+  {
+    const double psl = gs[0].rho / (2.0 * gs[0].lam), psr = gs[1].rho / (2.0 * gs[1].lam);
+    if (psl > 0.0 && psl < INFINITY && psr > 0.0 && psr < INFINITY && g0.rho == g0.rho &&
+        !(g0.rho > 0.0 && g0.lam > 0.0 && g0.lam < INFINITY)) {
+      for (int al = 0; al < nc; ++al) Fd[al] = Fh[al] = 0.0;
+      if (tau_out) *tau_out = 0.0;
+      return;
+    }
+  }
   double a0[MAXC], b0[MAXC], A0[MAXC];
   for (int al = 0; al < nc; ++al) b[al] = Wxc[al] / g0.rho;
   solve_slope(pp, &g0, b, a0);
@@ -1569,6 +1583,12 @@ static void gp_flux3(const params* pp, const double* Wl, const double* Wnl, cons
   }
   maxw3 g0;
   maxw3_from_W(pp->K, pp->gamma, Wc, 0, &g0);
+  /* interface vacuum: no flux (the rule of two dimensions) */
+  if (pside[0] > 0.0 && pside[0] < INFINITY && pside[1] > 0.0 && pside[1] < INFINITY && g0.rho == g0.rho &&
+      !(g0.rho > 0.0 && g0.lam > 0.0 && g0.lam < INFINITY)) {
+    for (int c = 0; c < NC3; ++c) Fd[c] = Fh[c] = 0.0;
+    return;
+  }
   double a0[NC3], b0[NC3], c0[NC3], A0[NC3];
   for (int c = 0; c < NC3; ++c) b[c] = Wnc[c] / g0.rho;
   solve_slope3(&g0, b, a0);

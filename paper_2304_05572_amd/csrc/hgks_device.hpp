@@ -609,6 +609,16 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
   // equilibrium g0 at the interface
   Maxw<T> g0;
   maxw_prims(acc.Wc, gamma, g0);
+  // interface vacuum: two physical sides (positive, finite pressures; a non-physical side leaves NaN
+  // moments and is reported) whose half-space integrals leave no equilibrium (density zero or temperature
+  // not positive and finite, where two states separate at many thermal speeds and the integrals
+  // underflow): the face carries no flux
+  {
+    const T inf = T(__builtin_inf()), pl = acc.p_side[0], pr = acc.p_side[1];
+    if (pl > T(0) && pl < inf && pr > T(0) && pr < inf && g0.rho == g0.rho &&
+        !(g0.rho > T(0) && g0.lam > T(0) && g0.lam < inf))
+      return;
+  }
 
   // collision time (Sec. 3) and the time-integral combinations (FP64):
   // F = (4 F(dt/2) - F(dt)) / dt, dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2, term by term

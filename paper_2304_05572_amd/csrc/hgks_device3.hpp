@@ -195,6 +195,13 @@ __device__ inline void flux3_finish(FluxAcc3<T>& acc, const FluxParams& fp, T Kp
   const T gamma = T(fp.gamma), K = T(fp.K);
   Maxw3<T> g0;
   maxw3_prims(acc.Wc, gamma, g0);
+  // interface vacuum (two physical sides, no equilibrium): the face carries no flux
+  {
+    const T inf = T(__builtin_inf()), pl = acc.p_side[0], pr = acc.p_side[1];
+    if (pl > T(0) && pl < inf && pr > T(0) && pr < inf && g0.rho == g0.rho &&
+        !(g0.rho > T(0) && g0.lam > T(0) && g0.lam < inf))
+      return;
+  }
   double cf[5], cd[5], tau;
   {
     const double pl = double(acc.p_side[0]), pr = double(acc.p_side[1]);

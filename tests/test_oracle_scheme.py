@@ -456,3 +456,48 @@ def test_first_stage_fallback_rescues_a_non_physical_intermediate_state():
     with pytest.raises(O.OracleError) as e:
         O.step(O.Problem(**dict(kw, positivity=0)), W, 0.0, nthreads=NT)
     assert e.value.code == O.ENONPHYS
+
+
+def _separating(u, p=1e-4, dim=1):
+    """Two equal cold states (rho 1, pressure p) moving apart at speed u each, as frame vectors."""
+    if dim == 1:
+        return np.array([1.0, -u, 0.5 * u * u + p / 0.4]), np.array([1.0, u, 0.5 * u * u + p / 0.4])
+    return (np.array([1.0, -u, 0.0, 0.5 * u * u + p / 0.4]), np.array([1.0, u, 0.0, 0.5 * u * u + p / 0.4]))
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_interface_vacuum_carries_no_flux(dim):
+    """Two cold states separating at many thermal speeds (lambda = 5000): the half-space integrals that
+    form the interface equilibrium shrink like erfc(sqrt(lambda) u) and underflow for sqrt(lambda) u > 27,
+    where the face carries exactly no flux; just before that, the flux is finite and of the size of those
+    integrals; by symmetry the mass and energy fluxes vanish at every speed."""
+    P = O.Problem(dim=dim, nx=8, ny=1 if dim == 1 else 8, c1=0.0, c2=1.0)
+    z = np.zeros(dim + 2)
+    dt = 1e-3
+    for u in (0.05, 0.2, 0.3, 0.35):  # sqrt(lambda) u = 3.5 ... 24.7: an equilibrium exists
+        Wl, Wr = _separating(u, dim=dim)
+        Fd, Fh, _ = O.gp_flux(P, Wl, z, z, Wr, z, z, dt)
+        assert np.isfinite(Fd).all() and np.isfinite(Fh).all()
+        bound = math.erfc(math.sqrt(5000.0) * u)  # half-space density of either side
+        assert abs(Fd[0]) <= 1e-12 * dt and abs(Fd[-1]) <= 1e-12 * dt
+        assert 0 < abs(Fd[1]) <= 10 * bound * dt, (u, Fd)
+    for u in (0.5, 2.0, 10.0):  # sqrt(lambda) u >= 35: underflow, no equilibrium
+        Wl, Wr = _separating(u, dim=dim)
+        Fd, Fh, tau = O.gp_flux(P, Wl, z, z, Wr, z, z, dt)
+        assert not Fd.any() and not Fh.any()
+
+
+def test_interface_vacuum_step_stays_physical():
+    """A 1D state of two cold halves separating at Mach ~60 (the centre face has no equilibrium): the
+    step keeps every cell physical, conserves mass and leaves the centre face without flux (the two
+    cells beside it lose exactly what their outer faces carry away)."""
+    n = 40
+    Wl, Wr = _separating(2.0)
+    W = np.where(np.arange(n) < n // 2, Wl[:, None], Wr[:, None])
+    P = O.Problem(dim=1, nx=n, ny=1, bc=(0, 0, 0, 0), c1=0.0, c2=1.0, fixed_dt=2e-4)
+    W1, _, dt = O.step(P, W, 0.0)
+    rho, _, _, p = wl.cons_to_prim(W1[:, None, :])
+    assert rho.min() > 0 and p.min() > 0
+    assert abs(W1[0].sum() - W[0].sum()) < 1e-12 * n
+    Fx, Gx, _, _ = O.stage_fluxes(P, W, dt)
+    assert not Fx[:, n // 2].any() and not Gx[:, n // 2].any()
