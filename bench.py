@@ -258,8 +258,7 @@ def tile_sweep(args):
 PAPER_CASES = {
     "rp_config1": dict(n=(500, 500), t_end=0.2, cfl=0.5, paper_s=(706.471, 6100.513)),
     "rp_config6": dict(n=(500, 500), t_end=0.6, cfl=0.95, paper_s=(5546.881, 9628.309)),
-    # run at CFL 0.5: at the paper's 0.8 this reading breaks down before t = 0.1 (see the workload)
-    "double_mach": dict(n=(960, 240), t_end=0.2, cfl=0.5, paper_s=(5334.322, 13596.93)),
+    "double_mach": dict(n=(960, 240), t_end=0.2, cfl=0.8, paper_s=(5334.322, 13596.93)),
 }
 
 

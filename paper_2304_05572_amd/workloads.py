@@ -189,8 +189,8 @@ def double_mach(nx: int = 960, ny: int = 240, walls: bool = True, cfl: float = 0
     walls=False the bottom also follows the exact moving shock: the exact solution is then the
     translating oblique shock itself. The scheme as the paper states it produces a non-physical Gauss-point
     state at the wall corner in the first step, so the problem enables the first-order fallbacks. cfl: the
-    paper's 0.8 by default; with these fallbacks the 960 x 240 run reaches t = 0.2 at 0.5 (the value the
-    paper gives for the classic WENO5 GKS in this case) and breaks down near t = 0.03-0.07 at 0.8."""
+    paper's 0.8 by default; with these fallbacks the 960 x 240 run reaches t = 0.2 at 0.8 and at 0.5 (the
+    value the paper gives for the classic WENO5 GKS in this case)."""
     post, pre = _cons_tuple(DMR_POST), _cons_tuple(DMR_PRE)
     xc = 4.0 * (np.arange(nx) + 0.5) / nx
     yc = (np.arange(ny) + 0.5) / ny
