@@ -458,6 +458,23 @@ def test_first_stage_fallback_rescues_a_non_physical_intermediate_state():
     assert e.value.code == O.ENONPHYS
 
 
+def test_first_stage_fallback_rescues_a_1d_intermediate_state():
+    """The same in 1D: one cell of W* non-physical, rescued by the fallback, reported without."""
+    from _stage1_case import stage1_case_1d
+    W, kw = stage1_case_1d()
+    P = O.Problem(**kw)
+    dt = O.cfl_dt(P, W)
+    Fx, Gx, _, _ = O.stage_fluxes(P, W, dt)
+    Fh = Fx * dt / 2 + Gx * dt * dt / 8
+    Ws = W - (Fh[:, 1:] - Fh[:, :-1]) * kw["nx"]
+    p = 0.4 * (Ws[2] - 0.5 * Ws[1] ** 2 / Ws[0])
+    assert ((Ws[0] <= 0) | (p <= 0)).sum() == 1
+    Wn, _, dt2 = O.step(P, W, 0.0)
+    assert dt2 == dt and Wn[0].min() > 0 and (0.4 * (Wn[2] - 0.5 * Wn[1] ** 2 / Wn[0])).min() > 0
+    with pytest.raises(O.OracleError):
+        O.step(O.Problem(**dict(kw, positivity=0)), W, 0.0)
+
+
 def _separating(u, p=1e-4, dim=1):
     """Two equal cold states (rho 1, pressure p) moving apart at speed u each, as frame vectors."""
     if dim == 1:
