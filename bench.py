@@ -45,7 +45,7 @@ PEAK_HBM = 8000.0  # GB/s
 # counter counts active lanes, so this is the algorithmic count of the hybrid scheme to well under 1%
 # (linear path everywhere, WENO5-AO on troubled sides; profiles/k_flux_rp1024_recon_modes.txt). Measured
 # on the 16 x 8 tile; the 8 x 8 tile, which the autotuner picks about as often, executes 0.6% more.
-FLOPS_PER_GP_FP64 = 2531.2
+FLOPS_PER_GP_FP64 = 2530.2
 
 
 def log(*a):
