@@ -21,7 +21,10 @@
  *     copies in and out and never keeps a caller pointer, except the workspace bound by
  *     hgks_bind_workspace, which it borrows until hgks_destroy and never frees.
  *   - Every call returns an hgks_status. Device-side failures (a non-physical state) are sticky:
- *     they are reported by the next hgks_step / hgks_run / hgks_get_state of that handle.
+ *     they are reported by the next hgks_step / hgks_run / hgks_get_state of that handle. A problem
+ *     whose step produces a non-physical state stops there: its state and time stay those of its last
+ *     good step (hgks_get_state returns them with HGKS_ENONPHYS), and hgks_get_stats names the stage
+ *     and cell where it happened. hgks_set_ic clears the failure.
  *   - A handle is not thread-safe; calls on one handle must not overlap. It lives on the HIP device
  *     current at hgks_create; every later call must be made with that device current.
  *   - Streams: all work of a handle is issued on one stream (opts.hip_stream, or a non-blocking stream
@@ -225,8 +228,12 @@ hgks_status hgks_debug_stage_fluxes3(hgks_t* h, int32_t prob, double dt, double*
 hgks_status hgks_debug_stage_fluxes(hgks_t* h, int32_t prob, double dt, double* Fx, double* Gx,
                                     double* Fy, double* Gy);
 
-/* Statistics of problem `prob`: out[0] steps taken, out[1] cells, out[2] time, out[3] last dt,
- * out[4] fraction of cells flagged in x at the last flag evaluation, out[5] the same in y. */
+/* Statistics of problem `prob` (10 entries): out[0] steps taken, out[1] cells, out[2] time, out[3] last dt,
+ * out[4] fraction of cells flagged in x at the last flag evaluation, out[5] the same in y, out[6] in z
+ * (3D; 0 otherwise), out[7] the stage (1, 2, or the stage of a multistage tableau) of the first
+ * non-physical state since hgks_set_ic (0: none), out[8] its cell index (x fastest; the lowest of that
+ * stage's non-physical cells; -1: none), out[9] wall seconds the handle has spent in hgks_step and
+ * hgks_run (issue to completion, all problems together). Synchronises the stream. */
 hgks_status hgks_get_stats(const hgks_t* h, int32_t prob, double* out);
 
 /* Kernel timings gathered since the handle was created (opts.profile > 0), from HIP events recorded

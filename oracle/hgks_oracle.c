@@ -550,13 +550,15 @@ static void gp_flux(const params* pp, const double* Wl, const double* Wxl, const
   maxw g0;
   maxw_from_W(pp, Wc, 0, &g0);
   /* interface vacuum: two physical sides (positive, finite pressures; a non-physical side leaves NaN
-   * moments and is reported as such) whose half-space integrals leave no equilibrium (density zero or
-   * temperature not positive and finite) give a face without flux. Two states separating at many
-   * thermal speeds reach this where the integrals underflow; every term carries a factor of those
-   * vanishing integrals, so zero is their limit. */
+   * moments and is reported as such) whose half-space integrals leave an interface density below the
+   * unit roundoff of the smaller side density and no equilibrium (temperature not positive and finite)
+   * give a face without flux. Two states separating at many thermal speeds reach this where the
+   * integrals underflow; every term carries a factor of those vanishing integrals, so zero is their
+   * limit. An interface density above that bound without an equilibrium is left to give NaN. */
   {
     const double psl = gs[0].rho / (2.0 * gs[0].lam), psr = gs[1].rho / (2.0 * gs[1].lam);
-    if (psl > 0.0 && psl < INFINITY && psr > 0.0 && psr < INFINITY && g0.rho == g0.rho &&
+    const double rmin = fmin(gs[0].rho, gs[1].rho);
+    if (psl > 0.0 && psl < INFINITY && psr > 0.0 && psr < INFINITY && g0.rho <= 0x1p-53 * rmin &&
         !(g0.rho > 0.0 && g0.lam > 0.0 && g0.lam < INFINITY)) {
       for (int al = 0; al < nc; ++al) Fd[al] = Fh[al] = 0.0;
       if (tau_out) *tau_out = 0.0;
@@ -880,11 +882,20 @@ static void frame_flags(const frame* f, const params* pp, uint8_t* Fn, uint8_t* 
 }
 
 /* Whether a reconstructed state (frame components: rho, normal and tangential momentum, energy; no
- * tangential slot in 1D) has positive density and pressure. */
-static int admissible(const double* w, int nc, double gamma) {
+ * tangential slot in 1D) is physical: positive density, and a pressure above the rounding error of the
+ * arithmetic that produced it. The state combines five stencil values q5 whose largest |energy| is emax;
+ * its pressure then carries an absolute rounding error of a few units in the last place of emax, so a
+ * pressure within 64 units of the unit roundoff (2^-53) times emax of zero is not taken as positive. */
+static double stencil_emax(const double q5[5][MAXC], int nc) {
+  double e = 0.0;
+  for (int r = 0; r < 5; ++r) e = fmax(e, fabs(q5[r][nc - 1]));
+  return e;
+}
+
+static int admissible(const double* w, int nc, double gamma, double emax) {
   double mt = (nc == 4) ? w[2] : 0.0;
   double pr = (gamma - 1.0) * (w[nc - 1] - 0.5 * (w[1] * w[1] + mt * mt) / w[0]);
-  return w[0] > 0.0 && pr > 0.0 && isfinite(pr);
+  return w[0] > 0.0 && pr > 64.0 * 0x1p-53 * emax && isfinite(pr);
 }
 
 /* Time-integrated fluxes F(dt), F(dt/2) at every interface of the frame (normal-direction
@@ -921,7 +932,7 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
         for (int r = 0; r < 5; ++r)
           for (int c = 0; c < nc; ++c) q5[r][c] = *fr_at(f, c, row, cell - 2 + r);
         recon_side(pp, q5, s == 0 ? 0.5 : -0.5, s == 0 ? fl : fr, R, L, val, der);
-        if (pp->positivity && !admissible(val, nc, pp->gamma))
+        if (pp->positivity && !admissible(val, nc, pp->gamma, stencil_emax(q5, nc)))
           for (int c = 0; c < nc; ++c) { /* first order: the cell's own average, no slope */
             val[c] = q5[2][c];
             der[c] = 0.0;
@@ -997,7 +1008,7 @@ static void frame_fluxes(const frame* f, const params* pp, double dt, double* Fd
               for (int c = 0; c < nc; ++c) q5[r][c] = LVAT(2 * s, c, j - 2 + r, k);
             recon_side(pp, q5, xi, ftf[s], R[s], L[s], val, der);
             /* first order along the interface: the centre segment's line values, no tangential slope */
-            int low = pp->positivity && !admissible(val, nc, pp->gamma);
+            int low = pp->positivity && !admissible(val, nc, pp->gamma, stencil_emax(q5, nc));
             for (int c = 0; c < nc; ++c) {
               Ws[s][c] = low ? q5[2][c] : val[c];
               Wys[s][c] = low ? 0.0 : der[c] / f->ht;
@@ -1539,11 +1550,12 @@ static void gp_flux3(const params* pp, const double* Wl, const double* Wnl, cons
   double Wc[NC3] = {0}, Wnc[NC3] = {0}, Wac[NC3] = {0}, Wbc[NC3] = {0};
   double M4a[NC3] = {0}, M4b[NC3] = {0}, M5[NC3] = {0};
   double t1[NC3], t2[NC3], t3[NC3], b[NC3];
-  double pside[2];
+  double pside[2], rside[2];
   for (int s = 0; s < 2; ++s) {
     maxw3 g;
     maxw3_from_W(pp->K, pp->gamma, Ws[s], s == 0 ? +1 : -1, &g); /* g_l over u > 0, g_r over u < 0 */
     pside[s] = g.rho / (2.0 * g.lam);
+    rside[s] = g.rho;
     double an[NC3], aa[NC3], ab[NC3], A[NC3];
     for (int c = 0; c < NC3; ++c) b[c] = Dn[s][c] / g.rho;
     solve_slope3(&g, b, an);
@@ -1584,8 +1596,8 @@ static void gp_flux3(const params* pp, const double* Wl, const double* Wnl, cons
   maxw3 g0;
   maxw3_from_W(pp->K, pp->gamma, Wc, 0, &g0);
   /* interface vacuum: no flux (the rule of two dimensions) */
-  if (pside[0] > 0.0 && pside[0] < INFINITY && pside[1] > 0.0 && pside[1] < INFINITY && g0.rho == g0.rho &&
-      !(g0.rho > 0.0 && g0.lam > 0.0 && g0.lam < INFINITY)) {
+  if (pside[0] > 0.0 && pside[0] < INFINITY && pside[1] > 0.0 && pside[1] < INFINITY &&
+      g0.rho <= 0x1p-53 * fmin(rside[0], rside[1]) && !(g0.rho > 0.0 && g0.lam > 0.0 && g0.lam < INFINITY)) {
     for (int c = 0; c < NC3; ++c) Fd[c] = Fh[c] = 0.0;
     return;
   }

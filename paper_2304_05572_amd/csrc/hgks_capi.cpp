@@ -38,7 +38,8 @@ struct hgks {
   bool own_stream = false;
   std::vector<hgks_problem> hp;
   std::vector<ProbDev> pd;
-  std::vector<size_t> off_W, off_Ws, off_Ws2, off_S, off_E, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_Fz, off_Gz, off_cnt;
+  std::vector<size_t> off_W, off_Ws, off_Ws2, off_S, off_E, off_E2, off_flags, off_Fx, off_Gx, off_Fy, off_Gy, off_Fz,
+      off_Gz, off_cnt;
   size_t off_probs = 0, off_ts = 0, off_tab = 0, off_qpart = 0, ws_bytes = 0;
   char* ws = nullptr;
   bool own_ws = false, ready = false;
@@ -46,7 +47,8 @@ struct hgks {
   std::vector<char> ic_set;
   hipGraphExec_t graph = nullptr;
   int graph_tile = -1, graph_tend = -1;
-  std::vector<double> last_frac_x, last_frac_y;
+  std::vector<double> last_frac_x, last_frac_y, last_frac_z;
+  double secs = 0.0;  // wall seconds spent in hgks_step / hgks_run (issue to completion)
   // optional per-launch HIP-event timing
   int profile = 0;
   struct Rec {
@@ -152,7 +154,8 @@ static void plan(hgks* h) {
   size_t o = 0;
   const size_t ts = h->fp32 ? sizeof(float) : sizeof(double);
   const int np = h->nprob;
-  h->off_W.resize(np); h->off_Ws.resize(np); h->off_Ws2.resize(np); h->off_S.resize(np); h->off_E.resize(np); h->off_flags.resize(np);
+  h->off_W.resize(np); h->off_Ws.resize(np); h->off_Ws2.resize(np); h->off_S.resize(np); h->off_E.resize(np);
+  h->off_E2.resize(np); h->off_flags.resize(np);
   h->off_Fx.resize(np); h->off_Gx.resize(np); h->off_Fy.resize(np); h->off_Gy.resize(np); h->off_cnt.resize(np);
   h->off_Fz.resize(np); h->off_Gz.resize(np);
   for (int p = 0; p < np; ++p) {
@@ -169,8 +172,9 @@ static void plan(hgks* h) {
     h->off_S[p] = o; o = align256(o + state);
     if (h->compensated) {
       h->off_E[p] = o; o = align256(o + state);
+      h->off_E2[p] = o; o = align256(o + state);
     } else {
-      h->off_E[p] = 0;
+      h->off_E[p] = h->off_E2[p] = 0;
     }
     h->off_flags[p] = o; o = align256(o + (nx + 4) * (q.dim >= 2 ? ny + 4 : 1) * (q.dim == 3 ? nz + 4 : 1));
     h->off_Fx[p] = o; o = align256(o + nc * nz * ny * (nx + 1) * ts);
@@ -187,7 +191,7 @@ static void plan(hgks* h) {
     } else {
       h->off_Fz[p] = h->off_Gz[p] = 0;
     }
-    h->off_cnt[p] = o; o = align256(o + 2 * sizeof(int));
+    h->off_cnt[p] = o; o = align256(o + 3 * sizeof(int));
   }
   h->off_probs = o; o = align256(o + np * sizeof(ProbDev));
   h->off_ts = o; o = align256(o + np * sizeof(TimeDev));
@@ -306,6 +310,7 @@ static hgks_status materialise(hgks* h) {
     d.Ws = reinterpret_cast<double*>(h->ws + h->off_Ws[p]);
     d.S = reinterpret_cast<double*>(h->ws + h->off_S[p]);
     d.E = h->compensated ? reinterpret_cast<double*>(h->ws + h->off_E[p]) : nullptr;
+    d.E2 = h->compensated ? reinterpret_cast<double*>(h->ws + h->off_E2[p]) : nullptr;
     d.Ws2 = h->ms.stages == 3 ? reinterpret_cast<double*>(h->ws + h->off_Ws2[p]) : nullptr;
     d.flags = reinterpret_cast<uint8_t*>(h->ws + h->off_flags[p]);
     d.Fx = h->ws + h->off_Fx[p];
@@ -322,6 +327,7 @@ static hgks_status materialise(hgks* h) {
   for (auto& s : ts) {
     std::memset(&s, 0, sizeof s);
     s.t_end = INFINITY;
+    s.bad = ~0ull;
   }
   HIPOK(hipMemcpyAsync(h->ws + h->off_ts, ts.data(), h->nprob * sizeof(TimeDev), hipMemcpyHostToDevice, h->stream));
   std::vector<int> tabs((size_t)(2 + kNumTiles) * (h->nprob + 1));
@@ -347,6 +353,11 @@ static hgks_status write_ts(hgks* h, const std::vector<TimeDev>& ts) {
   HIPOK(hipStreamSynchronize(h->stream));
   return HGKS_OK;
 }
+
+// Offsets of the buffers that hold the current state W^n (and, compensated, its low part E) of problem p:
+// every committed step swaps the two state buffers (and the two low-part buffers).
+static size_t cur_W(const hgks* h, const TimeDev& s, int p) { return s.cur ? h->off_Ws[p] : h->off_W[p]; }
+static size_t cur_E(const hgks* h, const TimeDev& s, int p) { return s.cur ? h->off_E2[p] : h->off_E[p]; }
 
 // Restores a saved device time state when a debug entry point returns, on every path (the debug calls
 // temporarily change the active flags and dt of the handle's problems).
@@ -613,6 +624,7 @@ hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opt
   h->ic_set.assign(nprob, 0);
   h->last_frac_x.assign(nprob, 0.0);
   h->last_frac_y.assign(nprob, 0.0);
+  h->last_frac_z.assign(nprob, 0.0);
   plan(h);
   *out = h;
   return HGKS_OK;
@@ -636,17 +648,18 @@ hgks_status hgks_set_ic(hgks_t* h, int32_t prob, const double* W, int32_t on_dev
   if (s) return s;
   const hgks_problem& q = h->hp[prob];
   const size_t bytes = (size_t)(q.dim + 2) * cells_of(q) * sizeof(double);
-  HIPOK(hipMemcpyAsync(h->ws + h->off_W[prob], W, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                       h->stream));
-  if (h->compensated) HIPOK(hipMemsetAsync(h->ws + h->off_E[prob], 0, bytes, h->stream));
   std::vector<TimeDev> ts;
   s = read_ts(h, ts);
   if (s) return s;
+  HIPOK(hipMemcpyAsync(h->ws + cur_W(h, ts[prob], prob), W, bytes,
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+  if (h->compensated) HIPOK(hipMemsetAsync(h->ws + cur_E(h, ts[prob], prob), 0, bytes, h->stream));
   ts[prob].t = t0;
   ts[prob].t_new = t0;
   ts[prob].t_end = INFINITY;
   ts[prob].active = 1;
   ts[prob].status = 0;
+  ts[prob].bad = ~0ull;
   ts[prob].steps = 0;
   set_time_step(ts[prob], 0.0);
   s = write_ts(h, ts);
@@ -679,9 +692,11 @@ hgks_status hgks_step(hgks_t* h, double* dt_taken) {
   }
   s = write_ts(h, ts);
   if (s) return s;
+  const auto t0 = std::chrono::steady_clock::now();
   s = issue_steps(h, 0, 1);
   if (s) return s;
   s = read_ts(h, ts);
+  h->secs += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (s) return s;
   if (dt_taken)
     for (int p = 0; p < h->nprob; ++p) dt_taken[p] = ts[p].dt;
@@ -707,6 +722,12 @@ hgks_status hgks_run(hgks_t* h, const double* t_end, int64_t max_steps, int64_t*
   s = write_ts(h, ts);
   if (s) return s;
   int64_t issued = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+  struct Clock {  // wall time of the loop, on every path out of it
+    hgks* h;
+    std::chrono::steady_clock::time_point t0;
+    ~Clock() { h->secs += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+  } timer{h, t0};
   while (issued < max_steps) {
     bool any = false;
     for (auto& x : ts) any |= (x.active != 0);
@@ -730,11 +751,12 @@ hgks_status hgks_get_state(const hgks_t* hc, int32_t prob, double* W, int32_t on
   if (!h || !W || prob < 0 || prob >= h->nprob || !h->ready) return HGKS_EINVAL;
   const hgks_problem& q = h->hp[prob];
   const size_t bytes = (size_t)(q.dim + 2) * cells_of(q) * sizeof(double);
-  HIPOK(hipMemcpyAsync(W, h->ws + h->off_W[prob], bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                       h->stream));
   std::vector<TimeDev> ts;
   hgks_status s = read_ts(h, ts);
   if (s) return s;
+  HIPOK(hipMemcpyAsync(W, h->ws + cur_W(h, ts[prob], prob), bytes,
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  HIPOK(hipStreamSynchronize(h->stream));
   if (t) *t = ts[prob].t;
   return status_from(ts);
 }
@@ -744,8 +766,11 @@ hgks_status hgks_get_state_lo(const hgks_t* hc, int32_t prob, double* E, int32_t
   if (!h || !E || prob < 0 || prob >= h->nprob || !h->ready) return HGKS_EINVAL;
   const hgks_problem& q = h->hp[prob];
   const size_t bytes = (size_t)(q.dim + 2) * cells_of(q) * sizeof(double);
+  std::vector<TimeDev> ts;
+  hgks_status s = read_ts(h, ts);
+  if (s) return s;
   if (h->compensated)
-    HIPOK(hipMemcpyAsync(E, h->ws + h->off_E[prob], bytes,
+    HIPOK(hipMemcpyAsync(E, h->ws + cur_E(h, ts[prob], prob), bytes,
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
   else if (on_device)
     HIPOK(hipMemsetAsync(E, 0, bytes, h->stream));
@@ -772,7 +797,7 @@ static hgks_status debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy
   const size_t ex = q.nx + 4, ey = q.dim >= 2 ? q.ny + 4 : 1, ez = q.dim == 3 ? q.nz + 4 : 1;
   std::vector<uint8_t> buf(ex * ey * ez);
   HIPOK(hipMemcpyAsync(buf.data(), h->ws + h->off_flags[prob], buf.size(), hipMemcpyDeviceToHost, h->stream));
-  int cnt[2];
+  int cnt[3];
   HIPOK(hipMemcpyAsync(cnt, h->ws + h->off_cnt[prob], sizeof cnt, hipMemcpyDeviceToHost, h->stream));
   s = guard.restore();  // synchronises the stream: buf and cnt are complete
   if (s) return s;
@@ -789,6 +814,7 @@ static hgks_status debug_flags(hgks_t* h, int32_t prob, uint8_t* fx, uint8_t* fy
   const double cells = (double)cells_of(q);
   h->last_frac_x[prob] = cnt[0] / cells;
   h->last_frac_y[prob] = cnt[1] / cells;
+  h->last_frac_z[prob] = cnt[2] / cells;
   return HGKS_OK;
 }
 
@@ -870,16 +896,22 @@ hgks_status hgks_get_stats(const hgks_t* hc, int32_t prob, double* out) {
   std::vector<TimeDev> ts;
   hgks_status s = read_ts(h, ts);
   if (s) return s;
-  int cnt[2];
-  HIPOK(hipMemcpy(cnt, h->ws + h->off_cnt[prob], sizeof cnt, hipMemcpyDeviceToHost));
+  int cnt[3];
+  HIPOK(hipMemcpyAsync(cnt, h->ws + h->off_cnt[prob], sizeof cnt, hipMemcpyDeviceToHost, h->stream));
+  HIPOK(hipStreamSynchronize(h->stream));
   const hgks_problem& q = h->hp[prob];
   const double cells = (double)cells_of(q);
-  out[0] = (double)ts[prob].steps;
+  const TimeDev& st = ts[prob];
+  out[0] = (double)st.steps;
   out[1] = cells;
-  out[2] = ts[prob].t;
-  out[3] = ts[prob].dt;
+  out[2] = st.t;
+  out[3] = st.dt;
   out[4] = cnt[0] / cells;
   out[5] = cnt[1] / cells;
+  out[6] = cnt[2] / cells;
+  out[7] = st.bad == ~0ull ? 0.0 : (double)(st.bad >> 32);
+  out[8] = st.bad == ~0ull ? -1.0 : (double)(st.bad & 0xffffffffull);
+  out[9] = h->secs;
   return HGKS_OK;
 }
 

@@ -40,10 +40,12 @@ struct ProbDev {
   double cfl, fixed_dt;
   double ghi, glo, eps;
   double* W;                 // state W^n        [nc][ny][nx]
-  double* Ws;                // stage state W*   [nc][ny][nx]
+  double* Ws;                // stage state W*, then the new state W^{n+1} until the step is committed (the
+                             // commit swaps W and Ws when the step produced no non-physical state)
   double* S;                 // partial sum W^n - dt L^n - dt^2/6 L_t^n
-  double* E;                 // compensated mode: rounding error of W^n (between steps) and of S (within a
-                             // step), so that the carried state is W + E; nullptr in plain mode
+  double* E;                 // compensated mode: rounding error of W^n, so that the carried state is W + E;
+                             // nullptr in plain mode
+  double* E2;                // compensated mode: rounding error of S, then of W^{n+1} (within a step)
   double* Ws2;               // three-stage tableaux: partial sum of the third stage's state
   uint8_t* flags;            // [(ny+4)][(nx+4)] (2D) / [nx+4] (1D): bit 0 x-flag, bit 1 y-flag
   void* Fx;                  // x-interfaces [4][ny][nx+1]: F (stage 1) / unused (stage 2)
@@ -52,7 +54,7 @@ struct ProbDev {
   void* Gy;
   void* Fz;                  // 3D: z-interfaces [5][nz+1][ny][nx]
   void* Gz;
-  int* flag_count;           // [2] troubled cells counted at the last flag evaluation
+  int* flag_count;           // [3] troubled cells per direction counted at the last flag evaluation
   BcDev bcd[4];              // read where bc[side] == 4
 };
 
@@ -60,9 +62,21 @@ struct TimeDev {
   double dt, t, t_new, t_end;
   double dth, idt, idt2;     // dt / 2, 1 / dt, 4 / dt^2 of the current step
   int active;                // 1 while t < t_end
-  int status;                // sticky: 1 when a non-physical state appeared
+  int status;                // sticky: 1 when a non-physical state appeared (the problem then stops with
+                             // the state of its last good step), 2 when dt came out <= 0 or not finite
   long long steps;
+  int cur;                   // 0: W^n is in the problem's first state buffer, 1: in its second (each
+                             // committed step swaps them)
+  int pad;
+  unsigned long long bad;    // first non-physical state: (stage << 32) | cell index, the lowest stage and
+                             // then the lowest cell; ~0 while none
 };
+
+// Records a non-physical state of stage `stage` in cell `cell`: the sticky status and the first such cell.
+__device__ inline void report_nonphysical(TimeDev& s, int stage, size_t cell) {
+  atomicOr(&s.status, 1);
+  atomicMin(&s.bad, ((unsigned long long)stage << 32) | (unsigned long long)cell);
+}
 
 // Derived time-step quantities of the step (set wherever dt is set).
 __host__ __device__ inline void set_time_step(TimeDev& s, double dt) {
@@ -208,6 +222,9 @@ __device__ inline int troubled5(double Qm2, double Qm1, double Q0, double Qp1, d
 // ---------------------------------------------------------------------------------------------
 // Precision helpers
 // ---------------------------------------------------------------------------------------------
+template <typename T> __device__ constexpr T unit_roundoff() {
+  return sizeof(T) == 8 ? T(1.1102230246251565e-16) : T(5.9604644775390625e-8);  // 2^-53, 2^-24
+}
 template <typename T> __device__ inline T dsqrt(T x);
 template <> __device__ inline double dsqrt<double>(double x) { return sqrt(x); }
 template <> __device__ inline float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
@@ -538,6 +555,7 @@ struct FluxAcc {
   T M4a[4], M4b[4], M5[4];   // rho <u psi>_h, rho <u A psi>_h, rho <u (a u + b v) psi>_h summed over sides
   T N4b[4], N5[4];           // the same with one power of u less (Prandtl correction only)
   T p_side[2];
+  T rho_min;                 // smaller of the two sides' densities (interface-vacuum test)
 };
 
 // side S = 0: g_l integrated over u > 0 (the first side: its moments initialise the accumulators);
@@ -549,6 +567,7 @@ __device__ inline void flux_side(const T W[4], const T Wx[4], const T Wy[4], T g
   Maxw<T> g;
   maxw_prims(W, gamma, g);
   acc.p_side[s] = T(0.5) * g.rho * drcp(g.lam);
+  acc.rho_min = (S == 0) ? g.rho : fmin(acc.rho_min, g.rho);
   const T ir = drcp(g.rho);
   T b[4], ax[4], ay[4], A[4], t1[4], t2[4];
   // full-line moments: slopes and the compatibility condition <a1 u + a2 v + A> = 0
@@ -610,12 +629,13 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
   Maxw<T> g0;
   maxw_prims(acc.Wc, gamma, g0);
   // interface vacuum: two physical sides (positive, finite pressures; a non-physical side leaves NaN
-  // moments and is reported) whose half-space integrals leave no equilibrium (density zero or temperature
-  // not positive and finite, where two states separate at many thermal speeds and the integrals
-  // underflow): the face carries no flux
+  // moments and is reported) whose half-space integrals leave a density below the unit roundoff of the
+  // smaller side density and no equilibrium (temperature not positive and finite), where two states
+  // separate at many thermal speeds and the integrals underflow: the face carries no flux. An interface
+  // density above that bound with no equilibrium is left to produce NaN and be reported.
   {
     const T inf = T(__builtin_inf()), pl = acc.p_side[0], pr = acc.p_side[1];
-    if (pl > T(0) && pl < inf && pr > T(0) && pr < inf && g0.rho == g0.rho &&
+    if (pl > T(0) && pl < inf && pr > T(0) && pr < inf && g0.rho <= unit_roundoff<T>() * acc.rho_min &&
         !(g0.rho > T(0) && g0.lam > T(0) && g0.lam < inf))
       return;
   }

@@ -127,6 +127,7 @@ struct FluxAcc3 {
   T Wc[5], Wnc[5], Wac[5], Wbc[5];  // equilibrium state and its normal / tangential slopes
   T M4a[5], M4b[5], M5[5];          // rho <u psi>_h, rho <u A psi>_h, rho <u (a u + b v + c w) psi>_h
   T p_side[2];
+  T rho_min;                 // smaller of the two sides' densities (interface-vacuum test)
 };
 
 // one side's contribution (S = 0: g_l over u > 0, initialises; S = 1: g_r over u < 0, adds). The three
@@ -138,6 +139,7 @@ __device__ inline void flux3_side(const T W[5], const T Wn[5], const T Wa[5], co
   Maxw3<T> g;
   maxw3_prims(W, gamma, g);
   acc.p_side[S] = T(0.5) * g.rho * drcp(g.lam);
+  acc.rho_min = (S == 0) ? g.rho : fmin(acc.rho_min, g.rho);
   const T ir = drcp(g.rho), rho = g.rho;
   maxw3_moments(g, K, 0);
   T Mh[7];
@@ -195,10 +197,11 @@ __device__ inline void flux3_finish(FluxAcc3<T>& acc, const FluxParams& fp, T Kp
   const T gamma = T(fp.gamma), K = T(fp.K);
   Maxw3<T> g0;
   maxw3_prims(acc.Wc, gamma, g0);
-  // interface vacuum (two physical sides, no equilibrium): the face carries no flux
+  // interface vacuum (two physical sides, an interface density below the unit roundoff of the smaller side
+  // density, no equilibrium): the face carries no flux
   {
     const T inf = T(__builtin_inf()), pl = acc.p_side[0], pr = acc.p_side[1];
-    if (pl > T(0) && pl < inf && pr > T(0) && pr < inf && g0.rho == g0.rho &&
+    if (pl > T(0) && pl < inf && pr > T(0) && pr < inf && g0.rho <= unit_roundoff<T>() * acc.rho_min &&
         !(g0.rho > T(0) && g0.lam > T(0) && g0.lam < inf))
       return;
   }

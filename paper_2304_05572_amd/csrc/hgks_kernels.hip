@@ -77,6 +77,7 @@ __global__ void __launch_bounds__(256) k_dt_finalize(const ProbDev* __restrict__
   const ProbDev& P = probs[p];
   P.flag_count[0] = 0;             // troubled cells are counted afresh by the step's first flag pass
   P.flag_count[1] = 0;
+  P.flag_count[2] = 0;
   if (!s.active) {
     set_time_step(s, 0.0);
     return;
@@ -97,11 +98,27 @@ __global__ void __launch_bounds__(256) k_dt_finalize(const ProbDev* __restrict__
   set_time_step(s, dt);
 }
 
-__global__ void k_commit(TimeDev* __restrict__ ts, int nprob, int use_tend) {
+// End of a step: a problem whose step produced a non-physical state stops with W^n (its new state, in the
+// second buffer, is dropped); the others take the new state by swapping the two buffers and advance t.
+__global__ void k_commit(ProbDev* __restrict__ probs, TimeDev* __restrict__ ts, int nprob, int use_tend) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprob) return;
   TimeDev& s = ts[p];
   if (!s.active) return;
+  if (s.status & 1) {
+    s.active = 0;
+    return;
+  }
+  ProbDev& P = probs[p];
+  double* w = P.W;
+  P.W = P.Ws;
+  P.Ws = w;
+  if (P.E) {
+    double* e = P.E;
+    P.E = P.E2;
+    P.E2 = e;
+  }
+  s.cur ^= 1;
   s.t = s.t_new;
   s.steps += 1;
   if (use_tend && s.t >= s.t_end) s.active = 0;
@@ -277,15 +294,27 @@ __global__ void k_clear_counts(const ProbDev* __restrict__ probs, int nprob) {
   if (p < nprob) {
     probs[p].flag_count[0] = 0;
     probs[p].flag_count[1] = 0;
+    probs[p].flag_count[2] = 0;
   }
 }
 
 // Whether a reconstructed state (rho, normal momentum, tangential momentum, energy) has positive
-// density and pressure.
+// density and a pressure above the rounding error of the arithmetic that produced it: the state is a
+// combination of values whose energies reach emax, so its energy, and with it the pressure, carries an
+// absolute rounding error of a few units of emax in the last place of T. A pressure within 64 such units
+// of zero has no reliable sign (or digits): taken as not physical. In FP64 the margin is 7e-15 emax; in
+// FP32 4e-6 emax, where the half-space moments of a state that cold would be ruled by rounding.
 template <typename T>
-__device__ inline bool admissible(const T* w, T gam) {
+__device__ inline bool admissible(const T* w, T gam, T emax) {
+  constexpr T tol = T(64) * unit_roundoff<T>();
   const T pr = (gam - T(1)) * (w[3] - T(0.5) * (w[1] * w[1] + w[2] * w[2]) / w[0]);
-  return w[0] > T(0) && pr > T(0) && isfinite(pr);
+  return w[0] > T(0) && pr > tol * emax && isfinite(pr);
+}
+
+// Largest |energy| of the five stencil values q[r][3] (frame slot 3 holds the energy).
+template <typename T>
+__device__ inline T stencil_emax(const T q0, const T q1, const T q2, const T q3, const T q4) {
+  return fmax(fmax(fmax(fabs(q0), fabs(q1)), fmax(fabs(q2), fabs(q3))), fabs(q4));
 }
 
 // Stride (in values) of one interface entry of the normal-reconstruction rows in LDS, and of one row
@@ -346,7 +375,11 @@ __device__ inline void tangential_side(const T* sNR, int tt, int k, int s, int f
       Wxs[v] = vx;
     }
   }
-  if (pos && !admissible(Ws, gam)) {  // first order along the interface: the centre segment's line values
+  if (pos && !admissible(Ws, gam,
+                         stencil_emax(sNR[(tt + 0) * NRW + k * kNRS + ov + 3], sNR[(tt + 1) * NRW + k * kNRS + ov + 3],
+                                      sNR[(tt + 2) * NRW + k * kNRS + ov + 3], sNR[(tt + 3) * NRW + k * kNRS + ov + 3],
+                                      sNR[(tt + 4) * NRW + k * kNRS + ov + 3]))) {
+    // first order along the interface: the centre segment's line values
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       Ws[v] = sNR[(tt + 2) * NRW + k * kNRS + ov + v];
@@ -506,11 +539,11 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
       }
     }
     if (P.positivity) {  // first order where a side's value is not a physical state
-      if (!admissible(out, gam)) {
+      if (!admissible(out, gam, stencil_emax(q6[0][3], q6[1][3], q6[2][3], q6[3][3], q6[4][3]))) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) { out[v] = q6[2][v]; out[4 + v] = T(0); }
       }
-      if (!admissible(out + 8, gam)) {
+      if (!admissible(out + 8, gam, stencil_emax(q6[1][3], q6[2][3], q6[3][3], q6[4][3], q6[5][3]))) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) { out[8 + v] = q6[3][v]; out[12 + v] = T(0); }
       }
@@ -708,7 +741,7 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
         if (P.E) {
           const double e = P.E[c * ncell + cell];
           ws = w - (d1 - e);
-          P.E[c * ncell + cell] = comp_add(w, -d2, e, s);
+          P.E2[c * ncell + cell] = comp_add(w, -d2, e, s);
         } else {
           ws = w - d1;
           s = w - d2;
@@ -719,9 +752,9 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
       } else {
         const double d3 = dt * dt / 3.0 * (gx + gy);
         double wnew;
-        if (P.E) P.E[c * ncell + cell] = comp_add(P.S[c * ncell + cell], -d3, P.E[c * ncell + cell], wnew);
+        if (P.E) P.E2[c * ncell + cell] = comp_add(P.S[c * ncell + cell], -d3, P.E2[c * ncell + cell], wnew);
         else wnew = P.S[c * ncell + cell] - d3;
-        P.W[c * ncell + cell] = wnew;
+        P.Ws[c * ncell + cell] = wnew;  // W* is spent: the new state waits there for the commit
         wn[c == nc - 1 ? 3 : c] = wnew;
       }
     }
@@ -732,7 +765,7 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
     if (bad && P.positivity)  // left to k_repair1 / k_repair: mark the cell (flag bit 2)
       P.flags[(P.dim == 2 ? (size_t)(j + 2) * (P.nx + 4) : 0) + (i + 2)] |= 4;
     else if (bad)
-      atomicOr(&tsp.status, 1);
+      report_nonphysical(tsp, stage, cell);
     if (stage == 2) q = cfl_quantity(P, wn[0], wn[1], wn[2], wn[3]);
   }
   if (stage == 2) {
@@ -838,7 +871,7 @@ __global__ void __launch_bounds__(256) k_repair1(const ProbDev* __restrict__ pro
   }
   const double rho = wn[0];
   const double pr = (P.gamma - 1.0) * (wn[3] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / rho);
-  if (!(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf())) atomicOr(&tsp.status, 1);
+  if (!(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf())) report_nonphysical(tsp, 1, cell);
 }
 
 // Time-order fallback after the second stage (problems with positivity = 1): every face next to a cell
@@ -881,7 +914,7 @@ __global__ void __launch_bounds__(256) k_repair(const ProbDev* __restrict__ prob
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       if (c >= nc) break;
-      double w = P.W[c * ncell + cell];
+      double w = P.Ws[c * ncell + cell];  // the new state, before the commit
       if (mxl | mxr | myl | myr) {
         double d = 0.0;
         if (mxr) d += (double(Gnx[c * px + ox + 1]) - double(Gsx[c * px + ox + 1])) * idx;
@@ -889,13 +922,13 @@ __global__ void __launch_bounds__(256) k_repair(const ProbDev* __restrict__ prob
         if (myr) d += (double(Gny[c * py + oy + P.nx]) - double(Gsy[c * py + oy + P.nx])) * idy;
         if (myl) d -= (double(Gny[c * py + oy]) - double(Gsy[c * py + oy])) * idy;
         w -= c3 * d;
-        P.W[c * ncell + cell] = w;
+        P.Ws[c * ncell + cell] = w;
       }
       wn[c == nc - 1 ? 3 : c] = w;
     }
     const double rho = wn[0];
     const double pr = (P.gamma - 1.0) * (wn[3] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / rho);
-    if (!(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf())) atomicOr(&tsp.status, 1);
+    if (!(rho > 0.0) || !(pr > 0.0) || !(wn[3] < __builtin_inf())) report_nonphysical(tsp, 2, cell);
     q = cfl_quantity(P, wn[0], wn[1], wn[2], wn[3]);
   }
   q = block_min(q);
@@ -921,7 +954,8 @@ void launch_dt_finalize(const LaunchCtx& L, int use_tend) {
 }
 
 void launch_commit(const LaunchCtx& L, int use_tend) {
-  hipLaunchKernelGGL(k_commit, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, L.ts, L.nprob, use_tend);
+  hipLaunchKernelGGL(k_commit, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, const_cast<ProbDev*>(L.probs), L.ts,
+                     L.nprob, use_tend);
 }
 
 void launch_flags(const LaunchCtx& L, int stage_state, int count, int clear) {

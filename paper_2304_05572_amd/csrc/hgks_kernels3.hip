@@ -53,9 +53,11 @@ __global__ void __launch_bounds__(256) k_flags3(const ProbDev* __restrict__ prob
   if (count) {
     const unsigned long long bx = __ballot(interior && (fl & 1));
     const unsigned long long by = __ballot(interior && (fl & 2));
+    const unsigned long long bz = __ballot(interior && (fl & 4));
     if ((threadIdx.x & 63) == 0) {
       if (bx) atomicAdd(&P.flag_count[0], __popcll(bx));
       if (by) atomicAdd(&P.flag_count[1], __popcll(by));
+      if (bz) atomicAdd(&P.flag_count[2], __popcll(bz));
     }
   }
 }
@@ -388,13 +390,13 @@ __global__ void __launch_bounds__(256) k_update3(const ProbDev* __restrict__ pro
         wn[c] = ws;
       } else {
         const double wnew = P.S[c * ncell + cell] - dt * dt / 3.0 * gs;
-        P.W[c * ncell + cell] = wnew;
+        P.Ws[c * ncell + cell] = wnew;  // W* is spent: the new state waits there for the commit
         wn[c] = wnew;
       }
     }
     const double rho = wn[0];
     const double pr = (P.gamma - 1.0) * (wn[4] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2] + wn[3] * wn[3]) / rho);
-    if (!(rho > 0.0) || !(pr > 0.0) || !(wn[4] < __builtin_inf())) atomicOr(&tsp.status, 1);
+    if (!(rho > 0.0) || !(pr > 0.0) || !(wn[4] < __builtin_inf())) report_nonphysical(tsp, stage, cell);
     if (stage == 2) q = cfl_quantity3(P, wn[0], wn[1], wn[2], wn[3], wn[4]);
   }
   if (stage == 2) {

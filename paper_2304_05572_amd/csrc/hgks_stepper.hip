@@ -3,8 +3,9 @@
 // update of a tableau, for problems of any dimension. L and L_t of a cell are the negative divergence of
 // the interface fluxes F and dF/dt that the flux kernel wrote for the stage state.
 //
-// Buffers: W holds W^n until the last stage writes W^{n+1}; S accumulates W^n + sum_i (dt b_i L_i +
-// dt^2 bh_i L_t,i); W* is the next stage's state; W2 the partial sum of the third stage's state.
+// Buffers: W holds W^n; S accumulates W^n + sum_i (dt b_i L_i + dt^2 bh_i L_t,i); W* is the next stage's
+// state, and the last stage writes W^{n+1} there for the commit to swap in; W2 the partial sum of the
+// third stage's state.
 #include <hip/hip_runtime.h>
 
 #include "hgks_device.hpp"
@@ -73,7 +74,7 @@ __global__ void __launch_bounds__(256) k_update_ms(const ProbDev* __restrict__ p
           P.Ws[s] = wnew;
           if (cs.stages == 3) P.Ws2[s] = w + (dt * cs.n2 * l + dt2 * cs.nh2 * lt);
         } else {
-          P.W[s] = wnew;
+          P.Ws[s] = wnew;  // the new state waits in the stage buffer for the commit
         }
       } else if (!last) {  // the second stage of three
         P.S[s] = P.S[s] + own;
@@ -81,7 +82,7 @@ __global__ void __launch_bounds__(256) k_update_ms(const ProbDev* __restrict__ p
         P.Ws[s] = wnew;
       } else {
         wnew = P.S[s] + own;
-        P.W[s] = wnew;
+        P.Ws[s] = wnew;  // the last stage's state is spent: the new state waits there for the commit
       }
       wn[c] = wnew;
     }
@@ -89,7 +90,7 @@ __global__ void __launch_bounds__(256) k_update_ms(const ProbDev* __restrict__ p
     double m2 = 0.0;
     for (int d = 0; d < dim; ++d) m2 += wn[1 + d] * wn[1 + d];
     const double pr = (P.gamma - 1.0) * (wn[nc - 1] - 0.5 * m2 / wn[0]);
-    if (!(wn[0] > 0.0) || !(pr > 0.0) || !(wn[nc - 1] < __builtin_inf())) atomicOr(&tsp.status, 1);
+    if (!(wn[0] > 0.0) || !(pr > 0.0) || !(wn[nc - 1] < __builtin_inf())) report_nonphysical(tsp, cs.i + 1, cell);
     if (last) q = cfl_quantity_any(P, wn);
   }
   if (last) {

@@ -323,8 +323,11 @@ def hgks_debug_stage_fluxes3(h, prob: int, dt: float, Fx, Gx, Fy, Gy, Fz, Gz):
     _check(lib().hgks_debug_stage_fluxes3(h, int(prob), float(dt), *ptrs), "hgks_debug_stage_fluxes3")
 
 
+STATS_ENTRIES = 10
+
+
 def hgks_get_stats(h, prob: int):
-    out = np.zeros(6)
+    out = np.zeros(STATS_ENTRIES)
     _check(lib().hgks_get_stats(h, int(prob), out.ctypes.data_as(C.c_void_p)), "hgks_get_stats")
     return out
 
@@ -434,8 +437,11 @@ class Solver:
         return Fx, Gx, Fy, Gy
 
     def stats(self, prob: int = 0):
+        """Counters of problem `prob`; bad_stage / bad_cell name the first non-physical state (stage 0 and
+        cell -1 while there is none); seconds is the handle's wall time in step / run."""
         s = hgks_get_stats(self.h, prob)
-        return dict(steps=int(s[0]), cells=int(s[1]), t=s[2], dt=s[3], flagged_x=s[4], flagged_y=s[5])
+        return dict(steps=int(s[0]), cells=int(s[1]), t=s[2], dt=s[3], flagged_x=s[4], flagged_y=s[5],
+                    flagged_z=s[6], bad_stage=int(s[7]), bad_cell=int(s[8]), seconds=s[9])
 
     def tile(self):
         return hgks_get_tile(self.h)
