@@ -249,6 +249,24 @@ hgks_status hgks_get_profile(hgks_t* h, double* out /* 8 entries */);
  * tile, or not launched yet). */
 hgks_status hgks_get_tile(const hgks_t* h, int32_t* out /* 5 entries */);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): one step of hgks_step for a single 1D or 2D problem (S2O4, Euler or
+ * Navier-Stokes, FP64 or FP32-bulk, the library's default launch configuration) without a handle.
+ * W: device pointer to the problem's cell averages ([nc][ny][nx] FP64, as hgks_set_ic takes them) at time
+ * t, advanced in place by one step of the problem's own CFL (or fixed) time step; *dt_taken (may be NULL)
+ * receives that step. The step's buffers (stage states, fluxes, flags, tables) live in a fixed device
+ * array of HGKS_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the process
+ * ends; the call allocates nothing (no hipMalloc, no host heap) and overwrites that array, so calls that
+ * overlap on one GPU (other threads, other streams) race and must be serialised by the caller. Needs
+ * 2 * nc * cells * 8 bytes of state plus 4 * nc * (cells + ny or nx) * sizeof(bulk type) of fluxes plus
+ * about (nx + 4) (ny + 4) bytes: 2D FP64 up to about 345 000 cells (589^2), FP32-bulk about 518 000 (720^2).
+ * Larger problems, 3D problems and multistage tableaux return HGKS_ENOMEM / HGKS_EINVAL before any device
+ * work. A step that produces a non-physical state returns HGKS_ENONPHYS and leaves W unchanged.
+ * hip_stream: borrowed hipStream_t (NULL: the null stream); W must be ready on it. Synchronises it. */
+#define HGKS_NOALLOC_SCRATCH_BYTES (64u << 20)
+hgks_status hgks_step_noalloc(const hgks_problem* prob, int32_t precision, double* W, double t, double* dt_taken,
+                              void* hip_stream);
+
 void hgks_destroy(hgks_t* h);
 const char* hgks_status_str(hgks_status s);
 

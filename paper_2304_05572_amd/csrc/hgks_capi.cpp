@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -254,6 +255,49 @@ static LaunchCtx ctx(hgks* h) {
   return L;
 }
 
+// Device copy of a problem's parameters (buffer pointers are set by the caller).
+static void fill_problem(const hgks_problem& q, ProbDev& d) {
+  std::memset(&d, 0, sizeof d);
+  d.dim = q.dim; d.nx = q.nx; d.ny = q.ny; d.ns = (q.eqn == HGKS_NS);
+  for (int s = 0; s < 4; ++s) {
+    d.bc[s] = q.bc[s];
+    if (q.bc[s] != HGKS_BC_PRESCRIBED || (q.dim == 1 && s >= 2)) continue;
+    d.prescribed = 1;
+    BcDev& B = d.bcd[s];
+    for (int c = 0; c < 4; ++c) {
+      B.a[c] = q.bcd[s].a[c];
+      B.b[c] = q.bcd[s].b[c];
+    }
+    if (q.dim == 1) B.a[2] = B.b[2] = 0.0;
+    B.s0 = q.bcd[s].s0; B.sn = q.bcd[s].sn; B.st = q.bcd[s].st;
+    B.rest = q.bcd[s].rest;
+  }
+  d.recon = q.recon; d.zeta1_mode = q.zeta1_mode; d.positivity = q.positivity;
+  d.csm = q.char_state_mode; d.vdt = q.viscous_dt_mode;
+  d.x0 = q.x0; d.y0 = q.dim >= 2 ? q.y0 : 0.0;
+  d.nz = q.dim == 3 ? q.nz : 1;
+  d.bcz[0] = q.dim == 3 ? q.bcz[0] : 0;
+  d.bcz[1] = q.dim == 3 ? q.bcz[1] : 0;
+  d.dz = q.dim == 3 ? (q.z1 - q.z0) / q.nz : 1.0;
+  d.ihz = 1.0 / d.dz;
+  d.dx = (q.x1 - q.x0) / q.nx;
+  d.dy = q.dim >= 2 ? (q.y1 - q.y0) / q.ny : 1.0;
+  d.h = q.dim == 2 ? std::min(d.dx, d.dy) : q.dim == 3 ? std::min(std::min(d.dx, d.dy), d.dz) : d.dx;
+  d.gamma = q.gamma;
+  // internal degrees of freedom of the 2D model (K + 2 = 2/(gamma-1)); a 1D problem runs as the 2D
+  // model with V = 0, which has the same u-moments as the 1D model with K + 1 = 2/(gamma-1)
+  d.K = (4.0 - 2.0 * q.gamma) / (q.gamma - 1.0);
+  if (q.dim == 3) d.K = (5.0 - 3.0 * q.gamma) / (q.gamma - 1.0);  // K + 3 = 2/(gamma-1) with three velocities
+  d.mu = q.mu; d.Pr = q.Pr; d.c1 = q.c1; d.c2 = q.c2;
+  d.Kp2 = d.K + 2.0;
+  d.iKp2 = 1.0 / d.Kp2;
+  d.kpr = 1.0 / q.Pr - 1.0;
+  d.ihx = 1.0 / d.dx;
+  d.ihy = 1.0 / d.dy;
+  d.cfl = q.cfl; d.fixed_dt = q.fixed_dt;
+  d.ghi = q.gamma_hi; d.glo = q.gamma_lo; d.eps = q.weno_eps;
+}
+
 static hgks_status materialise(hgks* h) {
   if (h->ready) return HGKS_OK;
   if (!h->ws) {
@@ -267,45 +311,7 @@ static hgks_status materialise(hgks* h) {
   for (int p = 0; p < h->nprob; ++p) {
     const hgks_problem& q = h->hp[p];
     ProbDev& d = h->pd[p];
-    std::memset(&d, 0, sizeof d);
-    d.dim = q.dim; d.nx = q.nx; d.ny = q.ny; d.ns = (q.eqn == HGKS_NS);
-    for (int s = 0; s < 4; ++s) {
-      d.bc[s] = q.bc[s];
-      if (q.bc[s] != HGKS_BC_PRESCRIBED || (q.dim == 1 && s >= 2)) continue;
-      d.prescribed = 1;
-      BcDev& B = d.bcd[s];
-      for (int c = 0; c < 4; ++c) {
-        B.a[c] = q.bcd[s].a[c];
-        B.b[c] = q.bcd[s].b[c];
-      }
-      if (q.dim == 1) B.a[2] = B.b[2] = 0.0;
-      B.s0 = q.bcd[s].s0; B.sn = q.bcd[s].sn; B.st = q.bcd[s].st;
-      B.rest = q.bcd[s].rest;
-    }
-    d.recon = q.recon; d.zeta1_mode = q.zeta1_mode; d.positivity = q.positivity;
-    d.csm = q.char_state_mode; d.vdt = q.viscous_dt_mode;
-    d.x0 = q.x0; d.y0 = q.dim >= 2 ? q.y0 : 0.0;
-    d.nz = q.dim == 3 ? q.nz : 1;
-    d.bcz[0] = q.dim == 3 ? q.bcz[0] : 0;
-    d.bcz[1] = q.dim == 3 ? q.bcz[1] : 0;
-    d.dz = q.dim == 3 ? (q.z1 - q.z0) / q.nz : 1.0;
-    d.ihz = 1.0 / d.dz;
-    d.dx = (q.x1 - q.x0) / q.nx;
-    d.dy = q.dim >= 2 ? (q.y1 - q.y0) / q.ny : 1.0;
-    d.h = q.dim == 2 ? std::min(d.dx, d.dy) : q.dim == 3 ? std::min(std::min(d.dx, d.dy), d.dz) : d.dx;
-    d.gamma = q.gamma;
-    // internal degrees of freedom of the 2D model (K + 2 = 2/(gamma-1)); a 1D problem runs as the 2D
-    // model with V = 0, which has the same u-moments as the 1D model with K + 1 = 2/(gamma-1)
-    d.K = (4.0 - 2.0 * q.gamma) / (q.gamma - 1.0);
-    if (q.dim == 3) d.K = (5.0 - 3.0 * q.gamma) / (q.gamma - 1.0);  // K + 3 = 2/(gamma-1) with three velocities
-    d.mu = q.mu; d.Pr = q.Pr; d.c1 = q.c1; d.c2 = q.c2;
-    d.Kp2 = d.K + 2.0;
-    d.iKp2 = 1.0 / d.Kp2;
-    d.kpr = 1.0 / q.Pr - 1.0;
-    d.ihx = 1.0 / d.dx;
-    d.ihy = 1.0 / d.dy;
-    d.cfl = q.cfl; d.fixed_dt = q.fixed_dt;
-    d.ghi = q.gamma_hi; d.glo = q.gamma_lo; d.eps = q.weno_eps;
+    fill_problem(q, d);
     d.W = reinterpret_cast<double*>(h->ws + h->off_W[p]);
     d.Ws = reinterpret_cast<double*>(h->ws + h->off_Ws[p]);
     d.S = reinterpret_cast<double*>(h->ws + h->off_S[p]);
@@ -412,6 +418,21 @@ static void collect_profile(hgks* h) {
   h->recs.clear();
 }
 
+// The two stages of an S2O4 step (Sec. 2.2), each launch passed to wrap(kind, launch) (kinds: 0 flux,
+// 1 update, 2 flags): flags, reconstruction + flux and update per stage, the first-order fallbacks where
+// a problem asks for them.
+template <typename Wrap>
+static void s2o4_stages(const LaunchCtx& L, Wrap wrap) {
+  wrap(2, [&] { launch_flags(L, 0, 1, 0); });
+  wrap(0, [&] { launch_flux(L, 1); });
+  wrap(1, [&] { launch_update(L, 1); });
+  if (L.positivity) wrap(1, [&] { launch_repair1(L); });
+  wrap(2, [&] { launch_flags(L, 1, 0, 0); });
+  wrap(0, [&] { launch_flux(L, 2); });
+  wrap(1, [&] { launch_update(L, 2); });
+  if (L.positivity) wrap(1, [&] { launch_repair(L); });
+}
+
 // The launches of one S2O4 step (everything stays on the device: dt, t and the CFL minimum).
 static void enqueue_step(hgks* h, int use_tend, bool capturing = false) {
   const LaunchCtx L = ctx(h);
@@ -436,14 +457,7 @@ static void enqueue_step(hgks* h, int use_tend, bool capturing = false) {
     if (h->recs.size() > 4096) collect_profile(h);
     return;
   }
-  timed(h, 2, capturing, [&] { launch_flags(L, 0, 1, 0); });
-  timed(h, 0, capturing, [&] { launch_flux(L, 1); });
-  timed(h, 1, capturing, [&] { launch_update(L, 1); });
-  if (L.positivity) timed(h, 1, capturing, [&] { launch_repair1(L); });
-  timed(h, 2, capturing, [&] { launch_flags(L, 1, 0, 0); });
-  timed(h, 0, capturing, [&] { launch_flux(L, 2); });
-  timed(h, 1, capturing, [&] { launch_update(L, 2); });
-  if (L.positivity) timed(h, 1, capturing, [&] { launch_repair(L); });
+  s2o4_stages(L, [&](int kind, auto fn) { timed(h, kind, capturing, fn); });
   timed(h, 3, capturing, [&] { launch_commit(L, use_tend); });
   if (h->recs.size() > 4096) collect_profile(h);
 }
@@ -579,7 +593,143 @@ static hgks_status issue_steps(hgks* h, int use_tend, int64_t nsteps) {
   return HGKS_OK;
 }
 
+// ---------------------------------------------------------------------------------------------
+// One step without allocation: every buffer of the step lives in a fixed device array of
+// HGKS_NOALLOC_SCRATCH_BYTES. Each device the library runs on holds its own copy of the array (from
+// the code object's load until the process ends); host code reaches it only through the address
+// hipGetSymbolAddress gives for the device current at the first call there.
+// ---------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[HGKS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[kMaxDevices];  // the array's device address, per device
+
+static hgks_status scratch_address(void** out) {
+  int dev = -1;
+  HIPOK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return HGKS_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPOK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return HGKS_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HGKS_OK;
+}
+
+// Byte offsets of the step's buffers inside the scratch array for problem q (total in `bytes`).
+struct NoallocPlan {
+  size_t probs, ts, tab, qpart, Ws, S, flags, cnt, Fx, Gx, Fy, Gy, bytes;
+  int cell_blocks, ext_blocks, flux_blocks;
+};
+
+static NoallocPlan plan_noalloc(const hgks_problem& q, int fp32) {
+  NoallocPlan n;
+  const size_t ts = fp32 ? sizeof(float) : sizeof(double);
+  const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny, cells = nx * ny;
+  const size_t state = nc * cells * sizeof(double);
+  n.cell_blocks = (int)((cells + 255) / 256);
+  n.ext_blocks = q.dim == 2 ? (int)(((nx + 4 + 31) / 32) * ((ny + 4 + 15) / 16)) : (int)((nx + 4 + 255) / 256);
+  n.flux_blocks = flux_tiles(q.dim, q.nx, q.ny, 0);
+  size_t o = 0;
+  n.probs = o; o = align256(o + sizeof(ProbDev));
+  n.ts = o; o = align256(o + sizeof(TimeDev));
+  n.tab = o; o = align256(o + 6 * sizeof(int));
+  n.qpart = o; o = align256(o + (size_t)n.cell_blocks * sizeof(double));
+  n.Ws = o; o = align256(o + state);
+  n.S = o; o = align256(o + state);
+  n.flags = o; o = align256(o + (nx + 4) * (q.dim == 2 ? ny + 4 : 1));
+  n.cnt = o; o = align256(o + 3 * sizeof(int));
+  n.Fx = o; o = align256(o + nc * ny * (nx + 1) * ts);
+  n.Gx = o; o = align256(o + nc * ny * (nx + 1) * ts);
+  n.Fy = n.Gy = 0;
+  if (q.dim == 2) {
+    n.Fy = o; o = align256(o + nc * (ny + 1) * nx * ts);
+    n.Gy = o; o = align256(o + nc * (ny + 1) * nx * ts);
+  }
+  n.bytes = o;
+  return n;
+}
+
 extern "C" {
+
+hgks_status hgks_step_noalloc(const hgks_problem* prob, int32_t precision, double* W, double t, double* dt_taken,
+                              void* hip_stream) {
+  if (!prob || !W || !std::isfinite(t) || (precision != HGKS_FP64 && precision != HGKS_FP32_BULK))
+    return HGKS_EINVAL;
+  const hgks_problem& q = *prob;
+  if (hgks_status s = validate(q)) return s;
+  if (q.dim == 3 || q.stepper.stages != 0) return HGKS_EINVAL;
+  const NoallocPlan n = plan_noalloc(q, precision == HGKS_FP32_BULK);
+  if (n.bytes > (size_t)HGKS_NOALLOC_SCRATCH_BYTES) return HGKS_ENOMEM;
+  void* base = nullptr;
+  if (hgks_status s = scratch_address(&base)) return s;
+  char* sc = static_cast<char*>(base);
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+
+  ProbDev d;
+  fill_problem(q, d);
+  d.W = W;  // the caller's state; the step's second state buffer is in the scratch array
+  d.Ws = reinterpret_cast<double*>(sc + n.Ws);
+  d.S = reinterpret_cast<double*>(sc + n.S);
+  d.E = d.E2 = d.Ws2 = nullptr;
+  d.flags = reinterpret_cast<uint8_t*>(sc + n.flags);
+  d.Fx = sc + n.Fx;
+  d.Gx = sc + n.Gx;
+  d.Fy = q.dim == 2 ? sc + n.Fy : nullptr;
+  d.Gy = q.dim == 2 ? sc + n.Gy : nullptr;
+  d.Fz = d.Gz = nullptr;
+  d.flag_count = reinterpret_cast<int*>(sc + n.cnt);
+  TimeDev ts;
+  std::memset(&ts, 0, sizeof ts);
+  ts.t = ts.t_new = t;
+  ts.t_end = INFINITY;
+  ts.active = 1;
+  ts.bad = ~0ull;
+  const int tabs[6] = {0, n.cell_blocks, 0, n.ext_blocks, 0, n.flux_blocks};
+  // every table the kernels read is written here; every other buffer is written by the step before it is
+  // read (flags, fluxes, S, the second state, the CFL block minima; the dt finalisation clears the counts)
+  HIPOK(hipMemcpyAsync(sc + n.probs, &d, sizeof d, hipMemcpyHostToDevice, stream));
+  HIPOK(hipMemcpyAsync(sc + n.ts, &ts, sizeof ts, hipMemcpyHostToDevice, stream));
+  HIPOK(hipMemcpyAsync(sc + n.tab, tabs, sizeof tabs, hipMemcpyHostToDevice, stream));
+
+  LaunchCtx L;
+  L.stream = stream;
+  L.probs = reinterpret_cast<const ProbDev*>(sc + n.probs);
+  L.ts = reinterpret_cast<TimeDev*>(sc + n.ts);
+  L.off_cell = reinterpret_cast<const int*>(sc + n.tab);
+  L.off_ext = reinterpret_cast<const int*>(sc + n.tab) + 2;
+  L.off_flux = reinterpret_cast<const int*>(sc + n.tab) + 4;
+  L.qpart = reinterpret_cast<double*>(sc + n.qpart);
+  L.nprob = 1;
+  L.dim = q.dim;
+  L.fp32 = precision == HGKS_FP32_BULK;
+  L.tile = 0;
+  L.persistent = 0;
+  L.persistent_grid = 0;
+  L.prfix = q.eqn == HGKS_NS && q.Pr != 1.0;
+  L.positivity = q.positivity;
+  L.tfm = q.tangential_flag_mode;
+  L.cell_blocks = n.cell_blocks;
+  L.ext_blocks = n.ext_blocks;
+  L.flux_blocks = n.flux_blocks;
+  launch_cfl(L);
+  launch_dt_finalize(L, 0);
+  s2o4_stages(L, [](int, auto fn) { fn(); });
+  launch_commit(L, 0);
+  launch_state_home(L);
+  HIPOK(hipGetLastError());
+  TimeDev out;
+  HIPOK(hipMemcpyAsync(&out, sc + n.ts, sizeof out, hipMemcpyDeviceToHost, stream));
+  HIPOK(hipStreamSynchronize(stream));
+  if (dt_taken) *dt_taken = out.dt;
+  if (out.status & 1) return HGKS_ENONPHYS;
+  if (out.status & 2) return HGKS_EDT;
+  return HGKS_OK;
+}
 
 hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opts* opts, hgks_t** out) {
   if (!probs || nprob < 1 || !out) return HGKS_EINVAL;

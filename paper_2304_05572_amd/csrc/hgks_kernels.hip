@@ -124,6 +124,21 @@ __global__ void k_commit(ProbDev* __restrict__ probs, TimeDev* __restrict__ ts, 
   if (use_tend && s.t >= s.t_end) s.active = 0;
 }
 
+// After the commit a problem's current state sits in its second buffer when the step was clean: copy it
+// into the first (the caller-owned state of the entry point that allocates nothing). Problems whose step
+// stopped keep the first buffer as it was.
+__global__ void __launch_bounds__(256) k_state_home(const ProbDev* __restrict__ probs, const TimeDev* __restrict__ ts,
+                                                    const int* __restrict__ off, int nprob) {
+  const int p = find_prob(off, nprob, blockIdx.x);
+  const ProbDev& P = probs[p];
+  if (!ts[p].cur) return;
+  const size_t ncell = (size_t)P.nx * P.ny;
+  const size_t cell = (size_t)(blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
+  if (cell >= ncell) return;
+  const int nc = P.dim + 2;
+  for (int c = 0; c < nc; ++c) P.Ws[c * ncell + cell] = P.W[c * ncell + cell];
+}
+
 // ---------------------------------------------------------------------------------------------
 // Troubled-cell flags (Sec. 2.3.1 Steps 1-4) of every cell of the extended range [-2, n+1]:
 // T of the cell and both neighbours, OR over the four conserved components, per direction.
@@ -956,6 +971,10 @@ void launch_dt_finalize(const LaunchCtx& L, int use_tend) {
 void launch_commit(const LaunchCtx& L, int use_tend) {
   hipLaunchKernelGGL(k_commit, dim3(nblk(L.nprob, 64)), dim3(64), 0, L.stream, const_cast<ProbDev*>(L.probs), L.ts,
                      L.nprob, use_tend);
+}
+
+void launch_state_home(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_state_home, dim3(L.cell_blocks), dim3(256), 0, L.stream, L.probs, L.ts, L.off_cell, L.nprob);
 }
 
 void launch_flags(const LaunchCtx& L, int stage_state, int count, int clear) {

@@ -55,6 +55,8 @@ inline int flux_tiles3(int nx, int ny, int nz) {
 void launch_cfl(const LaunchCtx& L);
 void launch_dt_finalize(const LaunchCtx& L, int use_tend);
 void launch_commit(const LaunchCtx& L, int use_tend);
+// copy a committed state from the second state buffer back into the first (1D / 2D problems)
+void launch_state_home(const LaunchCtx& L);
 // troubled-cell flags of the current (stage_state 0) or stage (1) state; count: tally the interior
 // troubled cells; clear: zero the tallies first (the step's dt finalisation already does)
 void launch_flags(const LaunchCtx& L, int stage_state, int count, int clear);

@@ -29,7 +29,9 @@ NUM_LAUNCH_CONFIGS = 12  # flux launch configurations: 6 tile shapes x (one bloc
 
 ENTRY_POINTS = ("hgks_create", "hgks_workspace_bytes", "hgks_bind_workspace", "hgks_set_ic", "hgks_step",
                 "hgks_run", "hgks_get_state", "hgks_get_state_lo", "hgks_debug_flags", "hgks_debug_stage_fluxes",
-                "hgks_debug_flags3", "hgks_debug_stage_fluxes3", "hgks_get_stats", "hgks_get_tile", "hgks_get_profile", "hgks_destroy", "hgks_status_str")
+                "hgks_debug_flags3", "hgks_debug_stage_fluxes3", "hgks_get_stats", "hgks_get_tile", "hgks_get_profile", "hgks_destroy", "hgks_status_str",
+                "hgks_step_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20  # HGKS_NOALLOC_SCRATCH_BYTES
 
 
 class HgksLibraryMissing(ImportError):
@@ -217,6 +219,7 @@ def lib():
             "hgks_get_profile": (i32, [vp, vp]),
             "hgks_destroy": (None, [vp]),
             "hgks_status_str": (C.c_char_p, [i32]),
+            "hgks_step_noalloc": (i32, [C.POINTER(hgks_problem), i32, vp, d, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -330,6 +333,21 @@ def hgks_get_stats(h, prob: int):
     out = np.zeros(STATS_ENTRIES)
     _check(lib().hgks_get_stats(h, int(prob), out.ctypes.data_as(C.c_void_p)), "hgks_get_stats")
     return out
+
+
+def hgks_step_noalloc(problem: Problem, precision, W, t: float, hip_stream=None) -> float:
+    """One step of a single problem without a handle or any allocation (hgks_step_noalloc): W is a device
+    tensor of the problem's cell averages, advanced in place; returns the step's dt."""
+    if not (hasattr(W, "is_cuda") and W.is_cuda):
+        raise ValueError("hgks_step_noalloc takes a device tensor")
+    ps = problem.c_struct()
+    dt = C.c_double()
+    sp = None
+    if hip_stream is not None:
+        sp = C.c_void_p(hip_stream.cuda_stream if hasattr(hip_stream, "cuda_stream") else int(hip_stream))
+    _check(lib().hgks_step_noalloc(C.byref(ps), int(precision), C.c_void_p(W.data_ptr()), float(t), C.byref(dt), sp),
+           "hgks_step_noalloc")
+    return dt.value
 
 
 def hgks_get_tile(h):
