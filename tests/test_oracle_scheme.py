@@ -76,26 +76,39 @@ def test_1d_accuracy_weno_ao_close_to_paper():
     assert np.all(orders > 4.8)
 
 
-def _run_2d_advection(m, recon):
+def _run_2d_advection(m, recon, fixed_dt=0.0):
     n = 2 * m
-    P = O.Problem(dim=2, nx=n, ny=n, x0=0, x1=2, y0=0, y1=2, bc=(0, 0, 0, 0), c1=0, c2=0, cfl=0.5, recon=recon)
+    P = O.Problem(dim=2, nx=n, ny=n, x0=0, x1=2, y0=0, y1=2, bc=(0, 0, 0, 0), c1=0, c2=0, cfl=0.5, recon=recon,
+                  fixed_dt=fixed_dt)
     W, t, _, _ = O.run(P, _advection_points_2d(n, 0.0), 2.0, nthreads=NT)
     e = np.abs(W[0] - _advection_points_2d(n, 2.0)[0])
     return np.array([e.mean(), np.sqrt((e ** 2).mean()), e.max()])
 
 
 def test_2d_accuracy_tables():
-    """Tables 2Daccuracy01/02: hybrid within a factor 1.5 of the printed hybrid errors, forced WENO-AO
-    within 8% of the printed WENO-AO errors, fifth order between dx = 1/5 and 1/10."""
+    """Tables 2Daccuracy01/02 (Sec. 3.3, CFL 0.5). Forced WENO-AO reproduces the printed WENO-AO table to
+    within 2-7% (L1, L2, Linf at dx = 1/5, 1/10). The hybrid scheme sits at a constant 0.730-0.740 of the
+    printed hybrid table, the same 2-7% from the printed WENO-AO one, at fifth order. The two printed
+    tables differ by 1.2-1.4x although the paper's 1D hybrid and WENO-AO tables agree to 8 digits; here the
+    two modes converge to each other (with no troubled cell, and there is none at dx <= 1/10, the hybrid
+    scheme is the linear one, which WENO-AO approaches on smooth data). The gap is not a reading of the
+    time step: the error of this smooth problem is a partial cancellation of spatial and temporal error
+    terms -- with dt -> 0 (dt = 0.075 dx) it rises to 0.905 of the printed hybrid table at both
+    resolutions -- and no fixed dt / dx reproduces the printed hybrid table at more than one resolution
+    (a scan of dt / dx from 0.12 to 0.42: the ratio crosses 1 at a different dt for each grid, with the
+    order of convergence lost)."""
     tab = _golden_table("accuracy_2d.txt")
     hy = [_run_2d_advection(m, O.RECON_HYBRID) for m in (5, 10)]
     for m, got in zip((5, 10), hy):
-        ref = np.array(tab[("hybrid", m)])
-        assert np.all(got < 1.5 * ref) and np.all(got > ref / 1.5)
-    assert math.log2(hy[0][0] / hy[1][0]) > 4.8
+        r = got / np.array(tab[("hybrid", m)])
+        assert np.all((r > 0.725) & (r < 0.745)), (m, r)
+    assert math.log2(hy[0][0] / hy[1][0]) > 4.9
     for m in (5, 10):
-        got = _run_2d_advection(m, O.RECON_WENOAO)
-        assert got[0] == pytest.approx(tab[("wenoao", m)][0], rel=0.08)
+        r = _run_2d_advection(m, O.RECON_WENOAO) / np.array(tab[("wenoao", m)])
+        assert np.all((r > 1.02) & (r < 1.075)), (m, r)
+    for m in (5, 10):  # the spatial error alone (dt -> 0)
+        r = _run_2d_advection(m, O.RECON_HYBRID, fixed_dt=0.075 / m) / np.array(tab[("hybrid", m)])
+        assert np.all((r > 0.895) & (r < 0.915)), (m, r)
 
 
 def test_hybrid_equals_linear_where_nothing_is_flagged():

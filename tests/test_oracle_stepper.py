@@ -96,3 +96,34 @@ def test_invalid_tableaux_rejected(bad):
     W, _ = wl.riemann_2d(12, seed=1)
     with pytest.raises(O.OracleError):
         O.step(O.Problem(nx=12, ny=12, **bad), W, 0.0)
+
+
+def test_s2o4_is_fourth_order_in_time():
+    """Sec. 2.2: S2O4 is fourth order in time when L_t is the time derivative of L. The gas-kinetic L_t
+    is built from the reconstructed slopes, so on a fixed grid it differs from dL/dt by a spatial
+    truncation term M, which adds dt^2/2 M (and higher powers of dt times M) per step: error terms in
+    dt, dt^2, ... whose size is that of the truncation error. The combination
+    H(dt) = W(dt) - 7 W(dt/2) + 14 W(dt/4) - 8 W(dt/8) cancels the exact solution and every error term in
+    dt^0, dt^1 and dt^2 (1 - 7 + 14 - 8 = 0, 1 - 7/2 + 14/4 - 8/8 = 0, 1 - 7/4 + 14/16 - 8/64 = 0) and
+    keeps 0.615 of the dt^4 term, so it must fall by 16 per halving of dt. 1D density wave, 40 cells,
+    tau = 0, to t = 0.4, dt = T/20 .. T/320 (CFL 0.96 .. 0.06). Besides, against a fine-step reference the
+    error at small dt is first order (the M floor), and that floor shrinks at high order with the grid."""
+    T = 0.4
+
+    def run(n, m):
+        kw = dict(dim=1, nx=n, ny=1, bc=(0, 0, 0, 0), x1=2.0, c1=0.0, c2=0.0, fixed_dt=T / m)
+        W, t, _, _ = O.run(O.Problem(**kw), wl.advection_1d(n), T, nthreads=NT)
+        assert abs(t - T) < 1e-12
+        return W[0]
+
+    ms = (20, 40, 80, 160, 320)
+    W = [run(40, m) for m in ms]
+    H = [np.abs(W[k] - 7 * W[k + 1] + 14 * W[k + 2] - 8 * W[k + 3]).max() for k in range(2)]
+    order = np.log2(H[0] / H[1])
+    assert 3.9 < order < 4.1, (H, order)
+    ref = run(40, 5120)
+    e = [np.abs(x - ref).max() for x in W[2:]]
+    assert all(0.9 < np.log2(e[k] / e[k + 1]) < 1.1 for k in range(2)), e
+    # 20 -> 40 cells at the same CFL (dt = T/40 and T/80): the floor falls by far more than 2^4
+    e20 = np.abs(run(20, 40) - run(20, 2560)).max()
+    assert e20 / e[0] > 16, (e20, e[0])

@@ -380,3 +380,127 @@ def test_flux_mirror_symmetry():
         Fd, Fh, _ = O.gp_flux(P, Wl, Wxl, Wyl, Wr, Wxr, Wyr, 1e-3)
         Gd, Gh, _ = O.gp_flux(P, S * Wr, -S * Wxr, S * Wyr, S * Wl, -S * Wxl, S * Wyl, 1e-3)
         np.testing.assert_allclose(Gd, -S * Fd, rtol=1e-11, atol=1e-15)
+
+
+# ------------------------------------------------------------------ Step-4 widening of the indicator
+def _isolated_pattern(n, c, s):
+    """Zero data except (s, s, -s) on cells c, c+1, c+2 (s = 0.9 h). Steps 1-3 by hand, per cell window
+    (cells i-2..i+2), with thr = 5h: i = c-2: D2 = 4s; c-1: D2 = 5s (both <= thr: smooth at Step 1);
+    c: window (0,0,s,s,-s), D1 = -s, D2 = -13s, xbar = -17/130, 3-cell quadratic a1 = s/2, a2 = -s/2,
+    xhat = 1/2, |xbar - xhat| = 0.631 > 1/4: TROUBLED; c+1: window (0,s,s,-s,0), D2 = -10s, D1 = -2s,
+    xbar = -0.34, xhat = -0.5, |.| = 0.16 <= 1/4: smooth; c+2: window (s,s,-s,0,0), D2 = 15s, D1 = -3s,
+    xbar = 0.34, xhat = 1/6, |.| = 0.173: smooth; c+3: D2 = 3s, c+4: D2 = -4s: smooth. So T = {c} only."""
+    q = np.zeros(n)
+    q[c:c + 3] = (s, s, -s)
+    return q
+
+
+def _widened(T):
+    F = T.copy()
+    F[1:] |= T[:-1]
+    F[:-1] |= T[1:]
+    return F
+
+
+@pytest.mark.parametrize("comp", [0, -1])
+def test_step4_widening_of_an_isolated_troubled_cell_1d(comp):
+    """Sec. 2.3.1 Step 4 from the unwidened indicator: one troubled cell (c = 9) gives flags exactly at
+    8, 9, 10; two troubled cells five apart give two separate triples (the widening is applied once, to
+    the unwidened flags). The pattern sits in the density or in the energy of a state at rest."""
+    n = 30
+    h = 1.0 / n
+    P = O.Problem(dim=1, nx=n, ny=1, bc=(0, 0, 0, 0))
+    base = np.stack([np.ones(n), np.zeros(n), np.full(n, 2.5)])
+    for cs in ([9], [9, 16]):
+        W = base.copy()
+        for c in cs:
+            W[comp] += _isolated_pattern(n, c, 0.9 * h)
+        fx, _ = O.flags(P, W)
+        expect = np.zeros(n, np.uint8)
+        for c in cs:
+            expect[c - 1:c + 2] = 1
+        assert np.array_equal(fx, expect), (cs, np.nonzero(fx))
+        for c in cs:  # the unwidened indicator of the pattern's own window, by hand above
+            assert O.indicator(W[comp][c - 2:c + 3], h)[0] == 1
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_step4_widening_per_direction_2d(direction):
+    """2D: the pattern along x (the same in every row) flags columns c-1..c+1 in x and nothing in y; the
+    transposed state flags rows c-1..c+1 in y and nothing in x (each direction widens its own flags)."""
+    n = 24
+    h = 1.0 / n
+    P = O.Problem(dim=2, nx=n, ny=n, bc=(0, 0, 0, 0))
+    line = _isolated_pattern(n, 11, 0.9 * h)
+    rho = 1.0 + (line[None, :] if direction == 0 else line[:, None]) * np.ones((n, n))
+    W = np.stack([rho, np.zeros((n, n)), np.zeros((n, n)), np.full((n, n), 2.5)])
+    fx, fy = O.flags(P, W)
+    band = np.zeros((n, n), np.uint8)
+    if direction == 0:
+        band[:, 10:13] = 1
+        assert np.array_equal(fx, band) and not fy.any()
+    else:
+        band[10:13, :] = 1
+        assert np.array_equal(fy, band) and not fx.any()
+    # an isolated cell of the x-direction pattern in one row only: x flags in that row's three cells;
+    # in y that cell's column sees a single cell of s and s, -s beside it: it decides its own y flags
+    W1 = np.stack([np.ones((n, n)), np.zeros((n, n)), np.zeros((n, n)), np.full((n, n), 2.5)])
+    W1[0, 7] += line
+    fx1, _ = O.flags(P, W1)
+    exp = np.zeros((n, n), np.uint8)
+    exp[7, 10:13] = 1
+    assert np.array_equal(fx1, exp)
+    assert np.array_equal(_widened(np.array([O.indicator(W1[0, 7, i - 2:i + 3], h)[0] if 2 <= i < n - 2 else 0
+                                             for i in range(n)], np.uint8)), fx1[7])
+
+
+# ------------------------------------------------------------------ smoothness indicators, exact arithmetic
+def _frac_cell_avg_matrix(offs, deg):
+    """Rows: exact cell averages of xi^m (m = 0..deg) over the cells [o - 1/2, o + 1/2]."""
+    F = Fraction
+    return [[(F(2 * o + 1, 2) ** (m + 1) - F(2 * o - 1, 2) ** (m + 1)) / (m + 1) for m in range(deg + 1)] for o in offs]
+
+
+def _frac_solve(A, b):
+    n = len(b)
+    M = [row[:] + [bb] for row, bb in zip(A, b)]
+    for k in range(n):
+        piv = next(r for r in range(k, n) if M[r][k] != 0)
+        M[k], M[piv] = M[piv], M[k]
+        for r in range(n):
+            if r != k and M[r][k] != 0:
+                f = M[r][k] / M[k][k]
+                M[r] = [x - f * y for x, y in zip(M[r], M[k])]
+    return [M[k][n] / M[k][k] for k in range(n)]
+
+
+def _frac_beta(q, offs):
+    """sum over q = 1..deg of the integral over [-1/2, 1/2] of (d^q p / dxi^q)^2, p the polynomial of degree
+    len(offs) - 1 with the given cell averages: polynomial algebra in exact fractions."""
+    F = Fraction
+    deg = len(offs) - 1
+    c = _frac_solve(_frac_cell_avg_matrix(offs, deg), q)
+    total = F(0)
+    d = c[:]
+    for _ in range(deg):
+        d = [k * d[k] for k in range(1, len(d))]  # derivative
+        sq = [F(0)] * (2 * len(d) - 1)
+        for i, a in enumerate(d):
+            for j, b in enumerate(d):
+                sq[i + j] += a * b
+        total += sum(a * (F(1, 2) ** (m + 1) - F(-1, 2) ** (m + 1)) / (m + 1) for m, a in enumerate(sq))
+    return total
+
+
+def test_smoothness_indicators_exact_on_random_data():
+    """beta_k (Sec. 2.3.1, in normalised units) of generic data, every cross term of the squared
+    derivatives included: random rational cell averages, the sub-stencil quadratics and the quartic
+    fitted and integrated in exact fractions, against the oracle to 1e-12."""
+    rng = np.random.default_rng(17)
+    subs = {0: [-2, -1, 0], 1: [-1, 0, 1], 2: [0, 1, 2], 3: [-2, -1, 0, 1, 2]}
+    for _ in range(30):
+        q = [Fraction(int(rng.integers(-60, 61)), int(rng.integers(1, 13))) for _ in range(5)]
+        for k, offs in subs.items():
+            exact = _frac_beta([q[o + 2] for o in offs], offs)
+            got = O.beta(k, np.array([float(x) for x in q]))
+            assert got == pytest.approx(float(exact), rel=1e-12, abs=1e-12), (k, q)
