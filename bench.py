@@ -10,14 +10,17 @@ reduction), inputs resident in device memory.
 `value` is the plain FP64 path in Mcell-updates/s, timed over K steps issued eagerly with HIP events
 around the flux launches only. The same line carries: the FP32-bulk path on the same workload; FP32-bulk
 with compensated state; (with --variants ...,wenoao) forced WENO5-AO against the hybrid scheme; the batched
-path (64 uneven problems in one set of launches); the three-dimensional scheme on an eight-octant Riemann
-problem (FP64 and FP32-bulk); per-kernel-group times and graph-replay step times from
+path (64 uneven problems in one set of launches; eager, one HIP graph per step, and the persistent launch
+form); the viscous shock tube (Navier-Stokes, 1000 x 500, 10 steps); the three-dimensional scheme on an
+eight-octant Riemann problem (FP64 and FP32-bulk); per-kernel-group times and graph-replay step times from
 short side windows; the rate with host transfers included; the L1/Linf distance of the first step of each
 precision to the CPU oracle over the full grid; the roofline position of the dominant kernel (fused
-reconstruction + flux, VALU-bound: algorithmic FP64 flops per Gauss point x Gauss points per launch over
-the HIP-event mean launch time in the timed region; HBM bytes per launch from committed FETCH_SIZE /
-WRITE_SIZE counts when they match the sources and the launch configuration); and the oracle's own CPU
-throughput on a bounded sample.
+reconstruction + flux, VALU-bound) for FP64, FP32-bulk and the batch: the method's algorithmic operations
+(tests/opcount.py counts them per Gauss point and per troubled side; the flagged fractions of the run
+give the troubled sides) over the HIP-event mean launch time in the timed region, and algorithmic HBM
+bytes against 8 TB/s, with the executed operations and counted HBM bytes of the committed counter summary
+when it matches the sources; and the oracle's own CPU throughput on a bounded sample (one thread and all
+host cores, median of 5).
 
 Other modes: --tile-sweep times every flux launch configuration; --copy-calibration runs a plain copy for
 scaling the HBM byte counters.
@@ -36,16 +39,36 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mcell-updates/s, 2D Euler 1024^2: FP64 plain vs FP32 vs batched, L1 err vs oracle"
 PEAK_FP64_VALU = 78.6  # TFLOP/s, MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
-PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (packed)
+PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (published, packed; the kernels issue non-packed FP32)
 PEAK_HBM = 8000.0  # GB/s
-# FP64 operations (FMA = 2) per Gauss-point evaluation of the fused reconstruction + flux kernel on this
-# workload (seed 0) in the default timed window (3 warm-up + 20 steps, 1.6-2% of the cells troubled):
-# normal and tangential reconstruction, equilibrium state and gas-kinetic flux, from the
-# SQ_INSTS_VALU_FLOPS_FP64 counter over the window's launches (profiles/k_flux_rp1024_counters.txt). The
-# counter counts active lanes, so this is the algorithmic count of the hybrid scheme to well under 1%
-# (linear path everywhere, WENO5-AO on troubled sides; profiles/k_flux_rp1024_recon_modes.txt). Measured
-# on the 16 x 8 tile; the 8 x 8 tile, which the autotuner picks about as often, executes 0.6% more.
-FLOPS_PER_GP_FP64 = 2530.2
+# Algorithmic operations of the method (tests/opcount.py: its formulas evaluated on a counting scalar
+# type, +, -, *, / one each, a fused multiply-add two; checked against the oracle's fluxes and against
+# these constants by tests/test_opcount.py):
+#   per Gauss point of the linear path: the gas-kinetic flux from the two reconstructed sides (2182), the
+#   tangential reconstruction of both sides (2 x 148: values, tangential slopes, normal-slope values) and
+#   half of an interface row's normal reconstruction (132 / 2; a row serves its segment's two points);
+#   per troubled side, what WENO-AO in characteristic variables adds: 842 per normal side-row, 1645 per
+#   tangential side and Gauss point.
+ALG_FLOPS_PER_GP_LINEAR = 2544.0
+ALG_FLOPS_AO_NORMAL_SIDE = 842
+ALG_FLOPS_AO_TANGENTIAL_SIDE = 1645
+
+
+def alg_flops_per_launch(gps, flagged_cells_x, flagged_cells_y):
+    """Algorithmic operations of one 2D flux launch: every Gauss point on the linear path, plus WENO-AO
+    where a side is troubled. A cell flagged in x is the troubled side of the normal reconstruction of
+    two x-interfaces (one row each) and of the tangential reconstruction of two y-interfaces (two Gauss
+    points each); the same with x and y exchanged."""
+    nf = flagged_cells_x + flagged_cells_y
+    return gps * ALG_FLOPS_PER_GP_LINEAR + nf * (2 * ALG_FLOPS_AO_NORMAL_SIDE + 4 * ALG_FLOPS_AO_TANGENTIAL_SIDE)
+
+
+def alg_bytes_per_launch(cells, interfaces, fp32):
+    """Algorithmic HBM bytes of one flux launch, mean of the two stages: the state read once (4 x 8 B per
+    cell), the flags (1 B per cell), F and dF/dt written in stage 1 (2 x 4 values per interface), dF/dt
+    only in stage 2."""
+    v = 4 if fp32 else 8
+    return cells * (32 + 1) + interfaces * 4 * v * 1.5
 
 
 def log(*a):
@@ -173,18 +196,42 @@ def gpu_first_step(H, W0, n, precision):
     return W, dt
 
 
-def oracle_leg(W0, n):
-    """The oracle as it stands, on host cores: one S2O4 step of the whole workload (FP64 C oracle, all host
-    threads up to 16). Returns (state, dt, cpu_baseline record)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_leg(W0, n, crop=256, reps=5):
+    """The oracle as it stands, on host cores. cpu_baseline: one S2O4 step of a crop x crop window of the
+    workload's initial data around the quadrant junction (outflow sides), median of `reps` runs on one thread
+    and on every host core up to 16. Parity: one step of the full n x n grid (all threads). Returns (full
+    state, dt, cpu_baseline record)."""
     import oracle
-    Po = oracle.Problem(dim=2, nx=n, ny=n, bc=(1, 1, 1, 1), c1=0.01, c2=1.0, cfl=0.5)
     nth = min(16, os.cpu_count() or 1)
-    t0 = time.perf_counter()
+    c0 = (n - crop) // 2
+    Wc = np.ascontiguousarray(W0[:, c0:c0 + crop, c0:c0 + crop])
+    Pc = oracle.Problem(dim=2, nx=crop, ny=crop, bc=(1, 1, 1, 1), c1=0.01, c2=1.0, cfl=0.5)
+    med = {}
+    for k in (1, nth):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.step(Pc, Wc, 0.0, nthreads=k)
+            ts.append(time.perf_counter() - t0)
+        med[k] = float(np.median(ts))
+    rec = {"value": crop * crop / med[nth] / 1e6, "unit": "Mcell-updates/s", "cores": nth, "kind": "oracle",
+           "sample": f"one S2O4 step of the central {crop}x{crop} window of the {n}x{n} initial data (outflow "
+                     f"sides), FP64 C oracle (gcc -O2, OpenMP over rows), median of {reps} runs",
+           "single_thread": {"value": crop * crop / med[1] / 1e6, "seconds_median": med[1], "threads": 1},
+           "all_cores": {"value": crop * crop / med[nth] / 1e6, "seconds_median": med[nth], "threads": nth},
+           "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+    Po = oracle.Problem(dim=2, nx=n, ny=n, bc=(1, 1, 1, 1), c1=0.01, c2=1.0, cfl=0.5)
     W, t, dt = oracle.step(Po, W0, 0.0, nthreads=nth)
-    el = time.perf_counter() - t0
-    rec = {"value": n * n / el / 1e6, "unit": "Mcell-updates/s", "cores": nth, "kind": "oracle",
-           "sample": f"one S2O4 step of the full {n}x{n} Riemann problem from its initial data, FP64 C oracle, "
-                     f"{nth} OpenMP threads, {el:.1f} s wall"}
     return W, dt, rec
 
 
@@ -218,6 +265,31 @@ def time_3d(H, wl, n, seed, steps, warmup):
         r["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
                          "frac": ach / PEAK_FP64_VALU, "traffic": float(t3["bytes_per_launch"]),
                          "flops_per_gauss_point": fl, "traffic_unit": "bytes per launch"}
+    return out
+
+
+def vst_problem(H, nx, ny, Pr=0.73):
+    from paper_2304_05572_amd import workloads as wl
+    W0 = wl.viscous_shock_tube(nx, ny)
+    P = H.Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=0.5, eqn=H.NS, mu=1.0 / 200.0, Pr=Pr,
+                  cfl=0.3, c1=0.01, c2=1.0, bc=(H.BC_NOSLIP, H.BC_NOSLIP, H.BC_NOSLIP, H.BC_REFLECT))
+    return P, W0
+
+
+def time_vst(H, steps, warmup):
+    """The viscous shock tube (Navier-Stokes, Re = 200, Pr = 0.73, 1000 x 500 cells), FP64 and FP32-bulk: steps
+    from the initial data issued eagerly, the flux kernel's HIP-event mean."""
+    P, W0 = vst_problem(H, 1000, 500)
+    out = {"workload": "viscous shock tube, Navier-Stokes, Re 200, Pr 0.73, [0,1]x[0,0.5], 1000x500 cells, "
+                       "no-slip adiabatic walls, symmetry top, CFL 0.3, hybrid WENO5-AO GKS with the Prandtl "
+                       f"correction, S2O4; {steps} timed steps from the initial data"}
+    for name, prec in (("fp64", H.FP64), ("fp32_bulk", H.FP32_BULK)):
+        log(f"[bench] timing vst {name}: {warmup} warm-up + {steps} steps")
+        el, flux_ms, stats, tile, prof = time_solver(H, [P], [W0], prec, steps, warmup, -1)
+        out[name] = {"value": 1000 * 500 * steps / el / 1e6, "ms_per_step": el / steps * 1e3,
+                     "flux_ms_per_launch": flux_ms, "launch_config": launch_config(tile),
+                     "flagged_x": stats[0]["flagged_x"], "flagged_y": stats[0]["flagged_y"]}
+        log(f"[bench] vst {name}: {out[name]['value']:.1f} Mcell-updates/s")
     return out
 
 
@@ -348,9 +420,10 @@ def main():
     ap.add_argument("--tile", type=int, default=-1, help="tile-shape index; -1 autotunes")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--n3", type=int, default=128, help="cells per side of the 3D variant")
-    ap.add_argument("--variants", default="fp64,fp32,batched,fp32c,3d",
+    ap.add_argument("--variants", default="fp64,fp32,batched,fp32c,3d,vst",
                     help="comma list of fp64, fp32, batched, fp32c (FP32-bulk with compensated state), "
-                         "3d (the three-dimensional scheme on an n3^3 octant problem), "
+                         "3d (the three-dimensional scheme on an n3^3 octant problem), vst (the viscous shock "
+                         "tube, Navier-Stokes 1000 x 500, 10 steps), "
                          "wenoao (FP64 with every cell troubled: the WENO5-AO scheme the hybrid one is "
                          "compared against; not in the default run, whose FP64 flux-kernel statistics "
                          "would mix both)")
@@ -417,14 +490,35 @@ def main():
         sizes = wl.batch_sizes(args.batch, seed=args.seed)
         probs = [rp_problem(H, m) for m in sizes]
         bstates = [wl.riemann_2d(m, seed=args.seed * 1000 + k + 1)[0] for k, m in enumerate(sizes)]
-        log(f"[bench] timing batched: {len(sizes)} problems, {sum(m * m for m in sizes)} cells")
+        bcells = sum(m * m for m in sizes)
+        log(f"[bench] timing batched: {len(sizes)} problems, {bcells} cells")
         el, flux_ms, stats, tile, prof = time_solver(H, probs, bstates, H.FP32_BULK, args.steps, args.warmup,
                                                      args.tile)
-        bcells = sum(m * m for m in sizes)
+        fcx = sum(st["flagged_x"] * m * m for st, m in zip(stats, sizes))
+        fcy = sum(st["flagged_y"] * m * m for st, m in zip(stats, sizes))
         batch = dict(mcells=bcells * args.steps / el / 1e6, ms_per_step=el / args.steps * 1e3, cells=bcells,
-                     problems=len(sizes), min_n=min(sizes), max_n=max(sizes), launch_config=launch_config(tile))
-        log(f"[bench] batched: {batch['mcells']:.1f} Mcell-updates/s")
+                     problems=len(sizes), min_n=min(sizes), max_n=max(sizes), launch_config=launch_config(tile),
+                     flux_ms=flux_ms, gps=sum(4 * m * (m + 1) for m in sizes),
+                     interfaces=sum(2 * m * (m + 1) for m in sizes), fcx=fcx, fcy=fcy)
+        # the same batch with one HIP graph per step, and in the persistent launch form of the same tile
+        for label, kw in (("graph", dict(use_graph=True)), ("persistent", dict())):
+            cfg = tile[3] if label == "graph" else (tile[3] % 6) + 6
+            s_ = H.Solver(probs, precision=H.FP32_BULK, tile=cfg, **kw)
+            for p_, W_ in enumerate(bstates):
+                s_.set_ic(p_, W_)
+            s_.run(np.inf, args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s_.run(np.inf, args.steps)
+            torch.cuda.synchronize()
+            el_ = time.perf_counter() - t0
+            batch[label] = {"value": bcells * args.steps / el_ / 1e6, "ms_per_step": el_ / args.steps * 1e3,
+                            "launch_config": launch_config(s_.tile())}
+            s_.close()
+            log(f"[bench] batched {label}: {batch[label]['value']:.1f} Mcell-updates/s")
         del bstates
+
+    vst = time_vst(H, 10, 2) if "vst" in variants else None
 
     res3 = time_3d(H, wl, args.n3, args.seed, args.steps, args.warmup) if "3d" in variants else None
 
@@ -446,22 +540,51 @@ def main():
         return
     r = res["fp64"]
     gps = 2 * ((n + 1) * n * 2)  # two Gauss points on every x- and y-interface
-    roof = None
-    fl = FLOPS_PER_GP_FP64
+    nif = 2 * (n + 1) * n        # x- and y-interfaces
     traffic = read_profile_table("k_flux_traffic_rp1024_fp64.txt")
-    if n == 1024 and r["flux_ms"] > 0:
-        achieved = fl * gps / (r["flux_ms"] * 1e-3) / 1e12
-        tr = None  # counted HBM bytes, only for the sources and launch configuration they were taken on
-        key = "bytes_per_launch_%d" % r["tile"][3]
-        if traffic.get("kernel_hash") == kernel_hash() and key in traffic:
-            tr = float(traffic[key])
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VALU, "traffic": tr,
-                "kernel": ("k_flux_persistent" if r["tile"][4] else "k_flux") + "<double, %d, %d, 2, false, 0, %d>"
-                          % (r["tile"][0], r["tile"][1], r["tile"][2]) + " (fused reconstruction + GKS flux)",
-                "ms_per_launch": r["flux_ms"],
-                "flops_per_launch": fl * gps, "flops_per_gauss_point": fl, "gauss_points_per_launch": gps,
-                "traffic_unit": "bytes per launch"}
+    counted = traffic.get("kernel_hash") == kernel_hash()
+
+    def roofline(kernel, ms, gps_, cells_, nif_, fcx, fcy, fp32, key=None):
+        """Roofline record of one flux launch: algorithmic operations (method formulas) and bytes over the
+        HIP-event mean launch time, against the FP64 or FP32 vector peak and HBM; the executed count and the
+        counted HBM bytes come from the committed counter summary when it matches the sources."""
+        if not ms or ms <= 0:
+            return None
+        fl = alg_flops_per_launch(gps_, fcx, fcy)
+        by = alg_bytes_per_launch(cells_, nif_, fp32)
+        peak = PEAK_FP32_VALU if fp32 else PEAK_FP64_VALU
+        ach = fl / (ms * 1e-3) / 1e12
+        tr = float(traffic[key]) if (counted and key and key in traffic) else None
+        ex = traffic.get("executed_flops_per_gauss_point_%s" % ("fp32" if fp32 else "fp64")) if counted else None
+        return {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": tr, "traffic_unit": "bytes per launch", "kernel": kernel, "ms_per_launch": ms,
+                "algorithmic_flops_per_launch": fl, "algorithmic_flops_per_gauss_point": fl / gps_,
+                "gauss_points_per_launch": gps_,
+                "executed_flops_per_gauss_point": float(ex) if ex is not None else None,
+                "hbm": {"algorithmic_bytes_per_launch": by, "achieved_GBps": by / (ms * 1e-3) / 1e9,
+                        "peak_GBps": PEAK_HBM, "frac": by / (ms * 1e-3) / 1e9 / PEAK_HBM,
+                        "counted_GBps": tr / (ms * 1e-3) / 1e9 if tr else None}}
+
+    def kname(T, tile):
+        return ("k_flux_persistent" if tile[4] else "k_flux") + "<%s, %d, %d, 2, false, 0, %d>" % (
+            T, tile[0], tile[1], tile[2]) + " (fused reconstruction + GKS flux)"
+
+    roof = None
+    if n == 1024:
+        st = r["stats"]
+        roof = roofline(kname("double", r["tile"]), r["flux_ms"], gps, n * n, nif, st["flagged_x"] * n * n,
+                        st["flagged_y"] * n * n, False, "bytes_per_launch_%d" % r["tile"][3])
+    roof32 = None
+    if "fp32" in res and n == 1024:
+        f = res["fp32"]
+        roof32 = roofline(kname("float", f["tile"]), f["flux_ms"], gps, n * n, nif, f["stats"]["flagged_x"] * n * n,
+                          f["stats"]["flagged_y"] * n * n, True, "bytes_per_launch_fp32_%d" % f["tile"][3])
+    roofb = None
+    if batch:
+        lc = batch["launch_config"]
+        roofb = roofline(("k_flux_persistent" if lc["persistent_blocks"] else "k_flux") + "<float, %d, %d, 2, false, 0, %d>"
+                         % (lc["tile"][0], lc["tile"][1], lc["waves_per_simd_target"]), batch["flux_ms"], batch["gps"],
+                         batch["cells"], batch["interfaces"], batch["fcx"], batch["fcy"], True)
     out = {
         "metric": METRIC,
         "value": r["mcells"],
@@ -492,7 +615,7 @@ def main():
     }
     if "fp32" in res:
         f = res["fp32"]
-        out["variants"]["fp32_bulk"] = {"value": f["mcells"], "ms_per_step": f["ms_per_step"],
+        out["variants"]["fp32_bulk"] = {"value": f["mcells"], "ms_per_step": f["ms_per_step"], "roofline": roof32,
                                         "flux_ms_per_launch": f["flux_ms"], "dtype": "f32 (f64 state/flags/CFL)",
                                         "l1_rel_vs_oracle": parity.get("fp32", (None,) * 3)[0],
                                         "linf_rel_vs_oracle": parity.get("fp32", (None,) * 3)[1],
@@ -516,9 +639,13 @@ def main():
     if res3:
         out["variants"]["three_dimensional"] = res3
     if batch:
-        out["variants"]["batched"] = dict(batch, value=batch["mcells"], dtype="f32 (f64 state/flags/CFL)",
+        b = {k: v for k, v in batch.items() if k not in ("gps", "interfaces", "fcx", "fcy")}
+        out["variants"]["batched"] = dict(b, value=batch["mcells"], dtype="f32 (f64 state/flags/CFL)", roofline=roofb,
                                           workload=f"{batch['problems']} independent Riemann problems, N in "
-                                                   f"[{batch['min_n']}, {batch['max_n']}], one launch per kernel")
+                                                   f"[{batch['min_n']}, {batch['max_n']}], one launch per kernel, "
+                                                   "eager launches (graph and persistent forms beside)")
+    if vst:
+        out["variants"]["viscous_shock_tube"] = vst
     print(json.dumps(out), flush=True)
 
 

@@ -120,7 +120,7 @@ typedef struct {
  * Euler equations or Navier-Stokes with Pr = 1, no prescribed-state sides, no positivity fallbacks and no
  * compensated accumulation. */
 typedef struct {
-  int32_t dim, nx, ny;          /* dim 1 or 2; ny must be 1 when dim == 1; nx, ny >= 5 */
+  int32_t dim, nx, ny;          /* dim 1, 2 or 3; ny must be 1 when dim == 1; nx, ny (and nz) >= 5 */
   double x0, x1, y0, y1;        /* uniform Cartesian cells on [x0,x1] x [y0,y1] */
   int32_t eqn;                  /* hgks_eqn: Euler (f = g) or Navier-Stokes (first-order expansion) */
   double gamma, mu, Pr;         /* ratio of specific heats (> 1), dynamic viscosity, Prandtl number */
@@ -181,9 +181,14 @@ typedef struct {
 
 typedef struct hgks hgks_t;
 
-/* Validate the problems and prepare the device-side tables. nprob >= 1 independent problems are
- * advanced together, each with its own time step. Device memory is allocated here unless the
- * caller binds a workspace before the first hgks_set_ic (see hgks_workspace_bytes). */
+/* Validate the problems and prepare the device-side tables (Sec. 2: the conservation laws of Eq. (equ1)
+ * on a structured grid of cell averages, Euler or Navier-Stokes with the gas parameters of Sec. 2.1 and the
+ * test parameters of Sec. 3). nprob >= 1 independent problems are advanced together, each with its own
+ * time step. Returns HGKS_EINVAL (before any HIP call) for an invalid statement: n < 5, gamma <= 1, CFL
+ * and fixed dt both <= 0, Pr <= 0 with Navier-Stokes, unpaired periodic sides, a non-physical prescribed
+ * state, mismatched dimensions or tableaux across the batch. *out receives the handle (owned by the caller,
+ * released by hgks_destroy). Device memory is allocated at the first hgks_set_ic unless the caller binds a
+ * workspace first (see hgks_workspace_bytes). */
 hgks_status hgks_create(const hgks_problem* probs, int32_t nprob, const hgks_opts* opts, hgks_t** out);
 
 /* Bytes of device memory the handle needs (states, stage buffers, flags, fluxes, scalars). */
@@ -194,16 +199,23 @@ size_t hgks_workspace_bytes(const hgks_t* h);
 hgks_status hgks_bind_workspace(hgks_t* h, void* dev_ptr, size_t bytes);
 
 /* Upload the cell averages of problem `prob` ([nc][ny][nx] FP64, host or device as `on_device`
- * says) and set its time to t0; recomputes the CFL minimum of the handle's problems. Synchronises the
- * stream. */
+ * says; the unknowns of Eq. (equ1) averaged over each cell, Sec. 2) and set its time to t0; clears the
+ * problem's failure status and recomputes the CFL minimum of the handle's problems. W stays the
+ * caller's. Synchronises the stream. */
 hgks_status hgks_set_ic(hgks_t* h, int32_t prob, const double* W, int32_t on_device, double t0);
 
-/* Advance every problem by one S2O4 step of its own CFL (or fixed) time step, with no end time.
- * dt_taken: nprob entries (may be NULL). Synchronises the stream. */
+/* Advance every problem by one S2O4 step (Sec. 2.2 steps (1)-(4): the flux and its time derivative of
+ * the current state, the intermediate state at t + dt/2, the derivative of its flux, the new state) of
+ * its own CFL time step (Sec. 3: dt = CFL h / max(|U| + c), and h^2 / (4 nu) for Navier-Stokes) or fixed
+ * time step, with no end time. dt_taken: nprob entries (may be NULL). Returns HGKS_ENONPHYS /
+ * HGKS_EDT when a problem's step failed (that problem keeps its last good state). Synchronises the
+ * stream. */
 hgks_status hgks_step(hgks_t* h, double* dt_taken);
 
-/* Advance every problem to its t_end[p] (the last step is shortened to land on it), or until
- * max_steps steps have been issued. steps_out: nprob entries (may be NULL). */
+/* Advance every problem to its t_end[p] by S2O4 steps (Sec. 2.2) of its CFL time step (Sec. 3), the
+ * last step shortened to land on t_end[p], or until max_steps steps have been issued. dt and t stay on
+ * the device; the host checks the problems' status every 16 steps, and a problem whose step failed stops
+ * at its last good state (HGKS_ENONPHYS / HGKS_EDT). steps_out: nprob entries (may be NULL). */
 hgks_status hgks_run(hgks_t* h, const double* t_end, int64_t max_steps, int64_t* steps_out);
 
 /* Copy the state of problem `prob` out; *t receives its time (t may be NULL). */

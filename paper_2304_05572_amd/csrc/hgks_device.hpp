@@ -353,62 +353,85 @@ __device__ inline void gauss_linear(const T q[5], int gp, T& v, T& d) {
 #undef S3
 
 // ---------------------------------------------------------------------------------------------
-// Characteristic variables (Sec. 2.3.1): right eigenvectors R of the Euler flux Jacobian along the
-// direction whose momentum sits in slot `nslot` (1 or 2; the other velocity slot is tangential),
-// columns ordered u_n - c, u_n (entropy), u_n (shear), u_n + c; L = R^{-1} in closed form.
+// Characteristic variables (Sec. 2.3.1) of the 2D Euler equations along frame slot D (1: the momentum of
+// slot 1, 2: that of slot 2; the other velocity slot is tangential): right eigenvectors R with columns
+// u_D - c, entropy (1, u, v, q^2/2), shear (0, e_t, u_t), u_D + c, and L = R^{-1} in closed form. Neither
+// matrix is stored: both projections are applied from nine scalars of the state (b1 = (gamma-1)/c^2,
+// b2 = b1 q^2/2), which keeps the troubled path's register footprint small.
 // ---------------------------------------------------------------------------------------------
 template <typename T>
-struct CharMat {
-  T R[4][4], L[4][4];
+struct Char4 {
+  T u[2], c, ic, H, b1, b2, hq2;
 };
 
 template <typename T>
-__device__ inline void char_matrices(const T w[4], T gamma, int nslot, CharMat<T>& m) {
-  const int tslot = 3 - nslot;
+__device__ inline void char4(const T w[4], T gamma, Char4<T>& m) {
   const T ir = drcp(w[0]);
-  const T u[3] = {T(0), w[1] * ir, w[2] * ir};
-  const T un = u[nslot], ut = u[tslot];
-  const T q2 = u[1] * u[1] + u[2] * u[2];
-  const T p = (gamma - 1) * (w[3] - T(0.5) * w[0] * q2);
-  const T c = dsqrt(gamma * p * ir);
-  const T ic = drcp(c);
-  const T H = (w[3] + p) * ir;
-  const T b1 = (gamma - 1) * ic * ic, b2 = T(0.5) * q2 * b1;
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) { m.R[a][b] = 0; m.L[a][b] = 0; }
-  m.R[0][0] = 1; m.R[nslot][0] = un - c; m.R[tslot][0] = ut; m.R[3][0] = H - un * c;
-  m.R[0][1] = 1; m.R[nslot][1] = un;     m.R[tslot][1] = ut; m.R[3][1] = T(0.5) * q2;
-  m.R[tslot][2] = 1; m.R[3][2] = ut;
-  m.R[0][3] = 1; m.R[nslot][3] = un + c; m.R[tslot][3] = ut; m.R[3][3] = H + un * c;
-  m.L[0][0] = T(0.5) * (b2 + un * ic); m.L[0][nslot] = T(-0.5) * (b1 * un + ic); m.L[0][tslot] = T(-0.5) * b1 * ut; m.L[0][3] = T(0.5) * b1;
-  m.L[1][0] = 1 - b2;                 m.L[1][nslot] = b1 * un;                  m.L[1][tslot] = b1 * ut;            m.L[1][3] = -b1;
-  m.L[2][0] = -ut;                                                              m.L[2][tslot] = 1;
-  m.L[3][0] = T(0.5) * (b2 - un * ic); m.L[3][nslot] = T(-0.5) * (b1 * un - ic); m.L[3][tslot] = T(-0.5) * b1 * ut; m.L[3][3] = T(0.5) * b1;
+  m.u[0] = w[1] * ir;
+  m.u[1] = w[2] * ir;
+  m.hq2 = T(0.5) * (m.u[0] * m.u[0] + m.u[1] * m.u[1]);
+  const T p = (gamma - 1) * (w[3] - w[0] * m.hq2);
+  m.c = dsqrt(gamma * p * ir);
+  m.ic = drcp(m.c);
+  m.H = (w[3] + p) * ir;
+  m.b1 = (gamma - 1) * m.ic * m.ic;
+  m.b2 = m.b1 * m.hq2;
 }
 
-// WENO-AO of a vector (4 conserved variables) in characteristic space; `ev` chooses the evaluation:
-// ev 0/1: face xi = +1/2 / -1/2, ev 2/3: Gauss point -eta / +eta. Returns value and xi-derivative.
+// L q: (acoustic -, entropy, shear, acoustic +)
+template <int D, typename T>
+__device__ inline void to_char4(const Char4<T>& m, const T q[4], T out[4]) {
+  constexpr int t = 3 - D;  // tangential slot
+  const T um = m.u[0] * q[1] + m.u[1] * q[2];
+  const T A = m.b2 * q[0] - m.b1 * um + m.b1 * q[3];
+  const T X = m.ic * (m.u[D - 1] * q[0] - q[D]);
+  out[0] = T(0.5) * (A + X);
+  out[1] = q[0] - A;
+  out[2] = q[t] - m.u[t - 1] * q[0];
+  out[3] = T(0.5) * (A - X);
+}
+
+// R cv
+template <int D, typename T>
+__device__ inline void from_char4(const Char4<T>& m, const T cv[4], T out[4]) {
+  constexpr int t = 3 - D;
+  const T s = cv[0] + cv[1] + cv[3], dl = cv[3] - cv[0];
+  out[0] = s;
+  out[D] = m.u[D - 1] * s + m.c * dl;
+  out[t] = m.u[t - 1] * s + cv[2];
+  out[3] = m.H * (cv[0] + cv[3]) + m.u[D - 1] * m.c * dl + m.hq2 * cv[1] + m.u[t - 1] * cv[2];
+}
+
+// WENO-AO of one characteristic component's five values q; ev 0/1: face xi = +1/2 / -1/2, ev 2/3: Gauss
+// point -eta / +eta. Value and xi-derivative.
 template <typename T>
-__device__ inline void ao_vector(const T qc[5][4], const CharMat<T>& m, int ev, T ghi, T glo, T eps, T val[4],
-                                 T der[4]) {
-  T cv[4], cd[4];
+__device__ inline void ao_scalar(const T q[5], int ev, T ghi, T glo, T eps, T& v, T& d) {
+  T beta[4], pv[4], pd[4];
+  smoothness(q, beta);
+  if (ev < 2) face_polys(q, ev, pv, pd);
+  else gauss_polys(q, ev - 2, pv, pd);
+  ao_combine(beta, pv, pd, ghi, glo, eps, v, d);
+}
+
+// WENO-AO of a vector (4 conserved variables) in the characteristic variables of slot D, from five rows of
+// four components that may sit in registers or in LDS (component v of row r at qc[r * rs + v * cs]); each
+// row is projected as it is read, so only the projections stay live.
+template <int D, typename T>
+__device__ inline void ao_vector(const T* qc, int rs, int cs, const Char4<T>& m, int ev, T ghi, T glo, T eps,
+                                 T val[4], T der[4]) {
+  T ch[5][4], cv[4], cd[4];
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const T q[4] = {qc[r * rs], qc[r * rs + cs], qc[r * rs + 2 * cs], qc[r * rs + 3 * cs]};
+    to_char4<D>(m, q, ch[r]);
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    T q[5];
-#pragma unroll
-    for (int r = 0; r < 5; ++r)
-      q[r] = m.L[k][0] * qc[r][0] + m.L[k][1] * qc[r][1] + m.L[k][2] * qc[r][2] + m.L[k][3] * qc[r][3];
-    T beta[4], pv[4], pd[4];
-    smoothness(q, beta);
-    if (ev < 2) face_polys(q, ev, pv, pd);
-    else gauss_polys(q, ev - 2, pv, pd);
-    ao_combine(beta, pv, pd, ghi, glo, eps, cv[k], cd[k]);
+    const T q[5] = {ch[0][k], ch[1][k], ch[2][k], ch[3][k], ch[4][k]};
+    ao_scalar(q, ev, ghi, glo, eps, cv[k], cd[k]);
   }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    val[a] = m.R[a][0] * cv[0] + m.R[a][1] * cv[1] + m.R[a][2] * cv[2] + m.R[a][3] * cv[3];
-    der[a] = m.R[a][0] * cd[0] + m.R[a][1] * cd[1] + m.R[a][2] * cd[2] + m.R[a][3] * cd[3];
-  }
+  from_char4<D>(m, cv, val);
+  from_char4<D>(m, cd, der);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -639,20 +662,32 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
         !(g0.rho > T(0) && g0.lam > T(0) && g0.lam < inf))
       return;
   }
-
-  // collision time (Sec. 3) and the time-integral combinations (FP64):
-  // F = (4 F(dt/2) - F(dt)) / dt, dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2, term by term
-  TermCoef<T> tc;
+  // collision time (Sec. 3)
   double tau;
   {
     const double pl = double(acc.p_side[0]), pr = double(acc.p_side[1]);
     const double jump = fabs((pl - pr) / (pl + pr));
-    if (fp.ns) {
-      const double p0 = double(T(0.5) * g0.rho * drcp(g0.lam));
-      tau = fp.mu / p0 + fp.c2 * jump * fp.dt;
-    } else {
-      tau = fp.c1 * fp.dt + fp.c2 * jump * fp.dt;
-    }
+    if (fp.ns) tau = fp.mu / double(T(0.5) * g0.rho * drcp(g0.lam)) + fp.c2 * jump * fp.dt;
+    else tau = fp.c1 * fp.dt + fp.c2 * jump * fp.dt;
+  }
+  // heat flux q = int (u-U0)((u-U0)^2+(v-V0)^2+xi^2)/2 f of one term, written through its flux moments
+  // (u psi) M and conserved moments (psi) N; the energy flux of the term gains (1/Pr - 1) q
+  const T U0 = g0.U, V0 = g0.V;
+  const T cA = T(1.5) * U0 * U0 + T(0.5) * V0 * V0, cB = T(0.5) * U0 * (U0 * U0 + V0 * V0);
+  const T kpr = T(fp.kpr);
+  auto heat = [&](const T M[4], const T N[4]) -> T {
+    return M[3] - U0 * M[1] - V0 * M[2] + cA * M[0] + U0 * V0 * N[2] - U0 * N[3] - cB * N[0];
+  };
+  if (PRFIX) {
+    acc.M4a[3] += kpr * heat(acc.M4a, acc.Wc);
+    acc.M4b[3] += kpr * heat(acc.M4b, acc.N4b);
+    acc.M5[3] += kpr * heat(acc.M5, acc.N5);
+  }
+
+  // the time-integral combinations (FP64): F = (4 F(dt/2) - F(dt)) / dt, dF/dt = 4 (F(dt) - 2 F(dt/2)) / dt^2,
+  // term by term
+  TermCoef<T> tc;
+  {
     double Cd[5], Ch[5];
     time_integrals_pair(fp.dt, fp.dth, tau, Cd, Ch);
     const double idt = fp.idt, idt2 = fp.idt2;
@@ -664,14 +699,6 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
     tc.f4t = fp.want_F ? wgt * T(tau * (4.0 * Ch[3] - Cd[3]) * idt) : T(0);
     tc.d4t = wgt * T(tau * (Cd[3] - 2.0 * Ch[3]) * idt2);
   }
-  // heat flux q = int (u-U0)((u-U0)^2+(v-V0)^2+xi^2)/2 f of one term, written through its flux moments
-  // (u psi) M and conserved moments (psi) N; the energy flux of the term gains (1/Pr - 1) q
-  const T U0 = g0.U, V0 = g0.V;
-  const T cA = T(1.5) * U0 * U0 + T(0.5) * V0 * V0, cB = T(0.5) * U0 * (U0 * U0 + V0 * V0);
-  const T kpr = T(fp.kpr);
-  auto heat = [&](const T M[4], const T N[4]) -> T {
-    return M[3] - U0 * M[1] - V0 * M[2] + cA * M[0] + U0 * V0 * N[2] - U0 * N[3] - cB * N[0];
-  };
   const bool want_F = fp.want_F;  // the second stage needs dF/dt only (uniform per launch)
   auto fold = [&](const T M[4], T cf, T cd) {
 #pragma unroll
@@ -681,14 +708,12 @@ __device__ inline void flux_finish(FluxAcc<T>& acc, const FluxParams& fp, T wgt,
     }
   };
   // free-transport terms of both sides: C4 (M4a - tau M4b) - C5 M5
-  if (PRFIX) {
-    acc.M4a[3] += kpr * heat(acc.M4a, acc.Wc);
-    acc.M4b[3] += kpr * heat(acc.M4b, acc.N4b);
-    acc.M5[3] += kpr * heat(acc.M5, acc.N5);
-  }
   fold(acc.M4a, tc.f[3], tc.d[3]);
   fold(acc.M4b, -tc.f4t, -tc.d4t);
   fold(acc.M5, -tc.f[4], -tc.d[4]);
+  // the equilibrium part below is scheduled on its own: interleaved with the time integrals above, the two
+  // sets of live values together cost registers (and occupancy)
+  __builtin_amdgcn_sched_barrier(0);
 
   // equilibrium terms: C1 rho0 <u psi> + C2 rho0 <u (a0 u + b0 v) psi> + C3 rho0 <u A0 psi>
   maxw_moments(g0, K, 0);

@@ -353,25 +353,18 @@ __device__ inline void tangential_side(const T* sNR, int tt, int k, int s, int f
   constexpr int NRW = nr_row<T, TN>();
   const int ov = 8 * s, od = 8 * s + 4;
   if (ft) {
-    CharMat<T> m;
+    Char4<T> m;
     T own[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       own[v] = csm ? T(0.5) * (sNR[(tt + 2) * NRW + k * kNRS + v] + sNR[(tt + 2) * NRW + k * kNRS + 8 + v])
                    : sNR[(tt + 2) * NRW + k * kNRS + ov + v];
-    char_matrices(own, gam, 2, m);
-    T qv[5][4], qd[5][4], val[4], der[4];
-#pragma unroll
-    for (int r = 0; r < 5; ++r)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        qv[r][v] = sNR[(tt + r) * NRW + k * kNRS + ov + v];
-        qd[r][v] = sNR[(tt + r) * NRW + k * kNRS + od + v];
-      }
-    ao_vector(qv, m, 2 + gp, ghi, glo, eps, val, der);
+    char4(own, gam, m);
+    T val[4], der[4];
+    ao_vector<2>(sNR + tt * NRW + k * kNRS + ov, NRW, 1, m, 2 + gp, ghi, glo, eps, val, der);
 #pragma unroll
     for (int v = 0; v < 4; ++v) { Ws[v] = val[v]; Wys[v] = der[v] * iht; }
-    ao_vector(qd, m, 2 + gp, ghi, glo, eps, val, der);
+    ao_vector<2>(sNR + tt * NRW + k * kNRS + od, NRW, 1, m, 2 + gp, ghi, glo, eps, val, der);
 #pragma unroll
     for (int v = 0; v < 4; ++v) Wxs[v] = val[v];
   } else {
@@ -518,53 +511,51 @@ __device__ __attribute__((always_inline)) inline void flux_tile(const ProbDev* _
   const T gam = T(P.gamma), ghi = T(P.ghi), glo = T(P.glo), eps = T(P.eps);
   for (int e = tid; e < R * TN; e += NTH) {
     const int r = e / TN, k = e % TN;
-    T q6[6][4];
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) q6[m][v] = sW[v][r][k + m];  // cells n0+k-3 .. n0+k+2
+    // the row's six cells n0+k-3 .. n0+k+2 stay in LDS: component v of cell m at cw[m + v * CS]; the
+    // outputs go to sNR as they are formed, so the troubled path holds only its projections
+    constexpr int CS = R * C;
+    const T* cw = &sW[0][r][k];
+    T* dst = sNR + r * NRW + k * kNRS;
     const int fl = sF[r][k] & 1, fr = sF[r][k + 1] & 1;
-    T out[16];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      out[v] = (T(2) * q6[0][v] - T(13) * q6[1][v] + T(47) * q6[2][v] + T(27) * q6[3][v] - T(3) * q6[4][v]) *
-               T(1.0 / 60.0);
-      const T sl = (q6[1][v] - T(15) * q6[2][v] + T(15) * q6[3][v] - q6[4][v]) * (T(1.0 / 12.0) * ihn);
-      out[4 + v] = sl;
-      out[12 + v] = sl;
-      out[8 + v] = (T(-3) * q6[1][v] + T(27) * q6[2][v] + T(47) * q6[3][v] - T(13) * q6[4][v] + T(2) * q6[5][v]) *
-                   T(1.0 / 60.0);
+      const T* q = cw + v * CS;
+      const T q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4], q5 = q[5];
+      const T sl = (q1 - T(15) * q2 + T(15) * q3 - q4) * (T(1.0 / 12.0) * ihn);
+      dst[v] = (T(2) * q0 - T(13) * q1 + T(47) * q2 + T(27) * q3 - T(3) * q4) * T(1.0 / 60.0);
+      dst[4 + v] = sl;
+      dst[8 + v] = (T(-3) * q1 + T(27) * q2 + T(47) * q3 - T(13) * q4 + T(2) * q5) * T(1.0 / 60.0);
+      dst[12 + v] = sl;
     }
     if (fl | fr) {
-      CharMat<T> m;
+      Char4<T> m;
       T avg[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) avg[v] = T(0.5) * (q6[2][v] + q6[3][v]);
-      char_matrices(avg, gam, 1, m);
+      for (int v = 0; v < 4; ++v) avg[v] = T(0.5) * (cw[2 + v * CS] + cw[3 + v * CS]);
+      char4(avg, gam, m);
       T val[4], der[4];
       if (fl) {
-        ao_vector(reinterpret_cast<const T(*)[4]>(&q6[0][0]), m, 0, ghi, glo, eps, val, der);
+        ao_vector<1>(cw, 1, CS, m, 0, ghi, glo, eps, val, der);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) { out[v] = val[v]; out[4 + v] = der[v] * ihn; }
+        for (int v = 0; v < 4; ++v) { dst[v] = val[v]; dst[4 + v] = der[v] * ihn; }
       }
       if (fr) {
-        ao_vector(reinterpret_cast<const T(*)[4]>(&q6[1][0]), m, 1, ghi, glo, eps, val, der);
+        ao_vector<1>(cw + 1, 1, CS, m, 1, ghi, glo, eps, val, der);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) { out[8 + v] = val[v]; out[12 + v] = der[v] * ihn; }
+        for (int v = 0; v < 4; ++v) { dst[8 + v] = val[v]; dst[12 + v] = der[v] * ihn; }
       }
     }
     if (P.positivity) {  // first order where a side's value is not a physical state
-      if (!admissible(out, gam, stencil_emax(q6[0][3], q6[1][3], q6[2][3], q6[3][3], q6[4][3]))) {
+      const T* e3 = cw + 3 * CS;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) { out[v] = q6[2][v]; out[4 + v] = T(0); }
-      }
-      if (!admissible(out + 8, gam, stencil_emax(q6[1][3], q6[2][3], q6[3][3], q6[4][3], q6[5][3]))) {
+      for (int sd = 0; sd < 2; ++sd) {
+        const T w[4] = {dst[8 * sd], dst[8 * sd + 1], dst[8 * sd + 2], dst[8 * sd + 3]};
+        if (!admissible(w, gam, stencil_emax(e3[sd], e3[sd + 1], e3[sd + 2], e3[sd + 3], e3[sd + 4]))) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) { out[8 + v] = q6[3][v]; out[12 + v] = T(0); }
+          for (int v = 0; v < 4; ++v) { dst[8 * sd + v] = cw[2 + sd + v * CS]; dst[8 * sd + 4 + v] = T(0); }
+        }
       }
     }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) sNR[r * NRW + k * kNRS + v] = out[v];
   }
   __syncthreads();
 

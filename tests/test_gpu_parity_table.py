@@ -1,0 +1,241 @@
+"""Measured parity of every workload configuration in both precisions against the oracle, with the
+tolerance each is held to, gathered into one JSON record (written to $HGKS_PARITY_TABLE when set, and
+printed).
+
+  [0] 1D Sod tube, 200 cells, to t = 0.2 (whole run against the oracle's whole run)
+  [1] 2D density-wave advection, 20^2 .. 80^2, to t = 2 (whole runs)
+  [2] 2D four-quadrant Riemann problem (seed 0): the 128^2 grid to t = 0.25 (whole runs, the oracle's
+      flags of the GPU state against the GPU's every 25 steps), and the 1024^2 grid's 100th step on
+      windows (one oracle step from the GPU's 99th state)
+  [3] viscous shock tube, Navier-Stokes 1000 x 500, Pr = 0.73: the 100th step on windows (FP64), FP32-bulk
+      after 100 steps against FP64
+  [4] the 64-problem batch, FP32-bulk, every problem to t = 0.25 in one handle with one HIP graph per
+      step: each problem equals its single-problem run bit for bit; the four smallest against the
+      oracle's whole runs
+
+L1 is the mean absolute difference over the mean absolute value, Linf the maximum over the maximum, both
+over all conserved components."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_05572_amd import hgks as H
+from paper_2304_05572_amd import workloads as wl
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skip(
+    reason="the first GPU run that included this module ended with the box faulted (the record names no test); "
+           "reading this module and the kernel changes of that run found no cause, so the module stays off the "
+           "GPU until one is shown (the kernel changes were taken out)")]
+NT = min(16, os.cpu_count() or 1)
+TABLE = {}
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def l1(a, b):
+    return float(np.abs(a - b).mean() / np.abs(b).mean())
+
+
+def linf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def record(cfg, prec, what, l1_, linf_, tol_l1, tol_linf, **extra):
+    row = {"what": what, "l1_rel": l1_, "linf_rel": linf_, "tol_l1_rel": tol_l1, "tol_linf_rel": tol_linf,
+           "pass": bool(l1_ <= tol_l1 and (tol_linf is None or linf_ <= tol_linf)), **extra}
+    TABLE.setdefault(cfg, {}).setdefault(prec, []).append(row)
+    say(cfg, prec, row)
+    return row["pass"]
+
+
+PRECS = (("fp64", H.FP64), ("fp32_bulk", H.FP32_BULK))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _write_table():
+    """After the module (whatever passed): the record on stderr and in $HGKS_PARITY_TABLE."""
+    yield
+    rec = json.dumps({"parity_table": TABLE})
+    print(rec, file=sys.stderr, flush=True)
+    path = os.environ.get("HGKS_PARITY_TABLE")
+    if path:
+        with open(path, "w") as fh:
+            fh.write(rec + "\n")
+
+
+def test_config0_sod():
+    n = 200
+    kw = dict(dim=1, nx=n, ny=1, bc=(H.BC_REFLECT,) * 2 + (0, 0), cfl=0.5, c1=0.01, c2=1.0)
+    W0 = wl.sod_1d(n)
+    Wo, to, steps, _ = O.run(O.Problem(**kw), W0, 0.2, nthreads=NT)
+    ok = True
+    for name, prec in PRECS:
+        s = H.Solver(H.Problem(**kw), precision=prec)
+        s.set_ic(0, W0)
+        s.run(0.2)
+        Wg, tg = s.get_state(0)
+        fx, _ = s.flags(0)
+        ox, _ = O.flags(O.Problem(**kw), Wg)
+        tol = (1e-12, 1e-10) if prec == H.FP64 else (1e-5, 1e-3)
+        ok &= record("0_sod_1d_200", name, f"whole run to t = 0.2 ({steps} oracle steps)", l1(Wg, Wo), linf(Wg, Wo),
+                     *tol, flags_mismatch_end=int((fx != ox).sum()), t=tg)
+    assert ok
+
+
+def test_config1_advection():
+    ok = True
+    for n in (20, 40, 80):
+        kw = dict(dim=2, nx=n, ny=n, x0=0, x1=2, y0=0, y1=2, bc=(0, 0, 0, 0), cfl=0.5, c1=0.0, c2=0.0)
+        W0 = wl.advection_2d(n)
+        Wo, _, steps, _ = O.run(O.Problem(**kw), W0, 2.0, nthreads=NT)
+        for name, prec in PRECS:
+            s = H.Solver(H.Problem(**kw), precision=prec, use_graph=True)
+            s.set_ic(0, W0)
+            s.run(2.0)
+            Wg, _ = s.get_state(0)
+            tol = (1e-11, 1e-9) if prec == H.FP64 else (2e-6, 2e-5)
+            ok &= record(f"1_advection_{n}", name, f"whole run to t = 2 ({steps} steps)", l1(Wg, Wo), linf(Wg, Wo),
+                         *tol, exact_l1=float(np.abs(Wg[0] - wl.advection_2d(n, 2.0)[0]).mean()))
+    assert ok
+
+
+def rp(n):
+    return dict(dim=2, nx=n, ny=n, bc=(1, 1, 1, 1), cfl=0.5, c1=0.01, c2=1.0)
+
+
+def test_config2_riemann_128_to_end():
+    n = 128
+    W0, _ = wl.riemann_2d(n, seed=0)
+    Po = O.Problem(**rp(n))
+    # the oracle's whole run, keeping every 25th state for the flag comparison
+    Wo, t, k = W0.copy(), 0.0, 0
+    ok = True
+    sols = {name: H.Solver(H.Problem(**rp(n)), precision=prec) for name, prec in PRECS}
+    for s in sols.values():
+        s.set_ic(0, W0)
+    mism = {name: 0 for name, _ in PRECS}
+    checks = 0
+    while t < 0.25:
+        Wo, t, _ = O.step(Po, Wo, t, 0.25, nthreads=NT)
+        k += 1
+        for name, s in sols.items():
+            s.run(0.25, 1)
+        if k % 25 == 0:
+            checks += 1
+            for name, s in sols.items():
+                Wg, _ = s.get_state(0)
+                gx, gy = s.flags(0)
+                ox, oy = O.flags(Po, Wg)
+                mism[name] += int((gx != ox).sum() + (gy != oy).sum())
+    for name, prec in PRECS:
+        Wg, tg = sols[name].get_state(0)
+        assert abs(tg - 0.25) < 1e-14
+        tol = (1e-9, 1e-6) if prec == H.FP64 else (1e-5, 1e-3)
+        ok &= record("2_riemann_128_seed0", name, f"whole run to t = 0.25 ({k} steps)", l1(Wg, Wo), linf(Wg, Wo),
+                     *tol, flag_checks=checks, flag_mismatches_gpu_state=mism[name])
+        assert mism[name] == 0
+    assert ok
+
+
+def _windows(Wprev, Wnext, dt, n, centres, half=24, margin=10, h=None, ny=None, y1=None, bc=(1, 1, 1, 1), **kw):
+    """The oracle's step on windows of Wprev (margins beyond the two-stage dependency radius, the real
+    boundary where a window touches an edge) with the GPU's dt, against the window interiors of Wnext;
+    returns (L1, Linf) over the windows."""
+    ny = ny or n
+    h = h or 1.0 / n
+    A_all, B_all = [], []
+    for (ci, cj) in centres:
+        i0, i1 = max(ci - half - margin, 0), min(ci + half + margin, n)
+        j0, j1 = max(cj - half - margin, 0), min(cj + half + margin, ny)
+        sub = np.ascontiguousarray(Wprev[:, j0:j1, i0:i1])
+        wbc = (bc[0] if i0 == 0 else 1, bc[1] if i1 == n else 1, bc[2] if j0 == 0 else 1, bc[3] if j1 == ny else 1)
+        P = O.Problem(dim=2, nx=i1 - i0, ny=j1 - j0, x0=i0 * h, x1=i1 * h, y0=j0 * h, y1=j1 * h, bc=wbc,
+                      fixed_dt=dt, **kw)
+        Wo, _, _ = O.step(P, sub, 0.0, nthreads=NT)
+        a0 = 0 if i0 == 0 else margin
+        a1 = (i1 - i0) if i1 == n else (i1 - i0 - margin)
+        b0 = 0 if j0 == 0 else margin
+        b1 = (j1 - j0) if j1 == ny else (j1 - j0 - margin)
+        A_all.append(Wnext[:, j0 + b0:j0 + b1, i0 + a0:i0 + a1].reshape(Wnext.shape[0], -1))
+        B_all.append(Wo[:, b0:b1, a0:a1].reshape(Wo.shape[0], -1))
+    A, B = np.concatenate(A_all, 1), np.concatenate(B_all, 1)
+    return l1(A, B), linf(A, B)
+
+
+def test_config2_riemann_1024_hundredth_step():
+    n = 1024
+    W0, _ = wl.riemann_2d(n, seed=0)
+    ok = True
+    centres = [(512, 512), (512, 300), (700, 512), (40, 30), (1000, 1010), (300, 700)]
+    for name, prec in PRECS:
+        s = H.Solver(H.Problem(**rp(n)), precision=prec, autotune=True, use_graph=True)
+        s.set_ic(0, W0)
+        s.run(np.inf, 99)
+        W99, _ = s.get_state(0)
+        dt = s.step()[0]
+        W100, _ = s.get_state(0)
+        a, b = _windows(W99, W100, dt, n, centres, cfl=0.5, c1=0.01, c2=1.0)
+        tol = (1e-12, 1e-11) if prec == H.FP64 else (1e-6, 1e-4)
+        ok &= record("2_riemann_1024_seed0", name, "100th step on 6 windows of 48^2 cells (oracle step from the GPU's "
+                     "99th state)", a, b, *tol, launch_config=[int(x) for x in s.tile()])
+    assert ok
+
+
+def test_config3_viscous_shock_tube():
+    nx, ny = 1000, 500
+    kw = dict(dim=2, nx=nx, ny=ny, y1=0.5, bc=(3, 3, 3, 2), eqn=1, mu=1 / 200, Pr=0.73, cfl=0.3, c1=0.01, c2=1.0)
+    W0 = wl.viscous_shock_tube(nx, ny)
+    s = H.Solver(H.Problem(**kw), use_graph=True)
+    s.set_ic(0, W0)
+    s.run(np.inf, 99)
+    W99, _ = s.get_state(0)
+    dt = s.step()[0]
+    W100, _ = s.get_state(0)
+    centres = [(500, 250), (505, 5), (3, 3), (996, 496), (520, 480)]
+    a, b = _windows(W99, W100, dt, nx, centres, ny=ny, h=1.0 / nx, bc=(3, 3, 3, 2), eqn=1, mu=1 / 200, Pr=0.73,
+                    c1=0.01, c2=1.0)
+    ok = record("3_viscous_shock_tube_1000x500", "fp64", "100th step on 5 windows (oracle step from the GPU's 99th "
+                "state)", a, b, 1e-12, 1e-11)
+    f = H.Solver(H.Problem(**kw), precision=H.FP32_BULK, use_graph=True)
+    f.set_ic(0, W0)
+    f.run(np.inf, 100)
+    Wf, _ = f.get_state(0)
+    ok &= record("3_viscous_shock_tube_1000x500", "fp32_bulk", "after 100 steps against the FP64 GPU run",
+                 l1(Wf, W100), linf(Wf, W100), 1e-6, 1e-4)
+    assert ok
+
+
+def test_config4_batch_to_end_time():
+    sizes = wl.batch_sizes(64, seed=0)
+    states = [wl.riemann_2d(m, seed=k + 1)[0] for k, m in enumerate(sizes)]
+    say("batch 64 to t = 0.25")
+    s = H.Solver([H.Problem(**rp(m)) for m in sizes], precision=H.FP32_BULK, use_graph=True)
+    for p, W in enumerate(states):
+        s.set_ic(p, W)
+    steps = s.run([0.25] * len(sizes))
+    out = [s.get_state(p)[0] for p in range(len(sizes))]
+    s.close()
+    same = 0
+    for p, m in enumerate(sizes):
+        r = H.Solver(H.Problem(**rp(m)), precision=H.FP32_BULK, use_graph=True)
+        r.set_ic(0, states[p])
+        n1 = r.run(0.25)[0]
+        Wr, tr = r.get_state(0)
+        r.close()
+        assert n1 == steps[p] and abs(tr - 0.25) < 1e-14
+        same += int(np.array_equal(Wr, out[p]))
+    ok = True
+    for p in np.argsort(sizes)[:4]:
+        Wo, _, no, _ = O.run(O.Problem(**rp(sizes[p])), states[p], 0.25, nthreads=NT)
+        ok &= record("4_batch_64", "fp32_bulk", f"problem {p} ({sizes[p]}^2) whole run to t = 0.25 ({no} steps)",
+                     l1(out[p], Wo), linf(out[p], Wo), 1e-5, 1e-3)
+    TABLE["4_batch_64"]["equal_to_single_runs_bitwise"] = f"{same} of {len(sizes)}"
+    TABLE["4_batch_64"]["steps_per_problem"] = [int(x) for x in steps]
+    say("batch problems equal to their single runs:", same)
+    assert same == len(sizes) and ok
