@@ -541,7 +541,7 @@ def main():
     r = res["fp64"]
     gps = 2 * ((n + 1) * n * 2)  # two Gauss points on every x- and y-interface
     nif = 2 * (n + 1) * n        # x- and y-interfaces
-    traffic = read_profile_table("k_flux_traffic_rp1024_fp64.txt")
+    traffic = read_profile_table("k_flux_traffic_rp1024.txt")
     counted = traffic.get("kernel_hash") == kernel_hash()
 
     def roofline(kernel, ms, gps_, cells_, nif_, fcx, fcy, fp32, key=None):
