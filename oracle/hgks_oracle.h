@@ -108,7 +108,9 @@ double oracle_beta(int k, const double* q);
 void oracle_ao_eval(const double* q, double xi, double gamma_hi, double gamma_lo, double eps,
                     double* val, double* der);
 int oracle_indicator(const double* q, double h, int zeta1_mode, double* xbar, double* xhat, int* step);
+/* dim 1 or 2, dir 1 (x) or 2 (y); R (right eigenvectors as columns) and L = R^-1: (dim+2)^2, row-major */
 void oracle_char_matrices(int dim, int dir, const double* W, double gamma, double* R, double* L);
+/* <u^n> (half: -1 / 1 the left / right half line, 0 the full line), <v^n> for n = 0..8, <xi^2n> n = 0..3 */
 void oracle_maxwell_moments(double rho, double U, double V, double lam, double K, int half,
                             double* Mu, double* Mv, double* Mxi);
 void oracle_slope_solve(int dim, const double* W, double gamma, const double* b, double* a);
