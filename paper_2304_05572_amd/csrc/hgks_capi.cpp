@@ -211,8 +211,8 @@ static void plan(hgks* h) {
     const long cells = (long)cells_of(q);
     const long ext = (long)(q.nx + 4) * (q.dim >= 2 ? q.ny + 4 : 1) * (q.dim == 3 ? q.nz + 4 : 1);
     h->tab_cell[p + 1] = h->tab_cell[p] + (int)((cells + 255) / 256);
-    // flag blocks: 32 x 16 tiles of the extended range in 2D, runs of 256 cells in 1D
-    const long fblocks = (q.dim == 2) ? (long)((q.nx + 4 + 31) / 32) * ((q.ny + 4 + 15) / 16) : (ext + 255) / 256;
+    // flag blocks: kFX x kFY tiles of the extended range in 2D, runs of 256 cells in 1D
+    const long fblocks = (q.dim == 2) ? flag_tiles2(q.nx, q.ny) : (ext + 255) / 256;
     h->tab_ext[p + 1] = h->tab_ext[p] + (int)fblocks;
     for (int t = 0; t < kNumTiles; ++t)
       h->tab_flux[t][p + 1] =
@@ -632,7 +632,7 @@ static NoallocPlan plan_noalloc(const hgks_problem& q, int fp32) {
   const size_t nc = q.dim + 2, nx = q.nx, ny = q.ny, cells = nx * ny;
   const size_t state = nc * cells * sizeof(double);
   n.cell_blocks = (int)((cells + 255) / 256);
-  n.ext_blocks = q.dim == 2 ? (int)(((nx + 4 + 31) / 32) * ((ny + 4 + 15) / 16)) : (int)((nx + 4 + 255) / 256);
+  n.ext_blocks = q.dim == 2 ? (int)flag_tiles2(nx, ny) : (int)((nx + 4 + 255) / 256);
   n.flux_blocks = flux_tiles(q.dim, q.nx, q.ny, 0);
   size_t o = 0;
   n.probs = o; o = align256(o + sizeof(ProbDev));

@@ -207,19 +207,22 @@ __global__ void __launch_bounds__(256) k_flags(const ProbDev* __restrict__ probs
   }
 }
 
-// 2D form: a block owns a kFX x kFY tile of the extended range and stages the cells it needs in LDS
-// (3 beyond the tile on each side, ghosts synthesised), evaluates the indicator T once per cell and
-// direction for the tile plus one cell on each side, then widens it and writes the flags (two rows per
-// thread).
-constexpr int kFX = 32, kFY = 16, kFThreads = 256;
-
+// 2D form: a block owns a kFX x kFY tile of the extended range (the tile shape is in hgks_launch.h).
+// Every thread first issues the loads of its share of the tile's cells and their 3-cell halo (ghosts
+// synthesised); the four conserved components then pass one at a time through a single LDS plane, and
+// the indicator T of each is evaluated for the tile plus one cell on each side, along x and along y, and
+// OR-ed into registers. One plane instead of four keeps the block's LDS small, so that enough blocks
+// share a CU for their load latencies to overlap. Finally T is widened (Step 4) and the flags written.
 __global__ void __launch_bounds__(kFThreads) k_flags2d(const ProbDev* __restrict__ probs,
                                                       const TimeDev* __restrict__ ts,
                                                       const int* __restrict__ off, int nprob,
                                                       int use_stage_state, int count) {
   constexpr int LX = kFX + 6, LY = kFY + 6;
   constexpr int RPT = kFX * kFY / kFThreads;  // output rows per thread
-  __shared__ double sW[4][LY][LX];          // cell (i0 - 3 + s, j0 - 3 + r) at [c][r][s]
+  constexpr int NTX = kFY * (kFX + 2), NTY = (kFY + 2) * kFX;  // T_x and T_y evaluations per component
+  constexpr int EX = (NTX + kFThreads - 1) / kFThreads, EY = (NTY + kFThreads - 1) / kFThreads;
+  static_assert(kFX * kFY % kFThreads == 0 && kFThreads % kFX == 0, "whole rows per thread");
+  __shared__ double sQ[LY][LX];             // one component of cell (i0 - 3 + s, j0 - 3 + r) at [r][s]
   __shared__ uint8_t sTx[kFY][kFX + 2];     // T_x of cell (i0 - 1 + a, j0 + b) at [b][a]
   __shared__ uint8_t sTy[kFY + 2][kFX];     // T_y of cell (i0 + a, j0 - 1 + b) at [b][a]
   // neighbouring tiles share their halos: keep them on one XCD (and its L2)
@@ -250,34 +253,51 @@ __global__ void __launch_bounds__(kFThreads) k_flags2d(const ProbDev* __restrict
       const int e = tid + u * kFThreads;
       if (e < LX * LY) load_cell(P, W, i0 - 3 + e % LX, j0 - 3 + e / LX, tb, q4[u]);
     }
-#pragma unroll
-    for (int u = 0; u < NL; ++u) {
-      const int e = tid + u * kFThreads;
-      if (e < LX * LY) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) sW[k][e / LX][e % LX] = q4[u][k];
-      }
-    }
-    __syncthreads();
     const double tx = (P.zeta1_mode == 0) ? 5.0 * P.dx : 5.0 * P.dx * P.dx * P.dx;
     const double ty = (P.zeta1_mode == 0) ? 5.0 * P.dy : 5.0 * P.dy * P.dy * P.dy;
-    for (int e = tid; e < kFY * (kFX + 2); e += kFThreads) {  // T_x: row bb, cells aa .. aa+4
-      const int bb = e / (kFX + 2), aa = e % (kFX + 2);
-      int t = 0;
+    int Tx[EX], Ty[EY];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        t |= troubled5(sW[k][bb + 3][aa], sW[k][bb + 3][aa + 1], sW[k][bb + 3][aa + 2], sW[k][bb + 3][aa + 3],
-                       sW[k][bb + 3][aa + 4], tx);
-      sTx[bb][aa] = (uint8_t)t;
+    for (int u = 0; u < EX; ++u) Tx[u] = 0;
+#pragma unroll
+    for (int u = 0; u < EY; ++u) Ty[u] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k) __syncthreads();  // the previous component's reads are done
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int e = tid + u * kFThreads;
+        if (e < LX * LY) sQ[e / LX][e % LX] = q4[u][k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < EX; ++u) {  // T_x: row bb, cells aa .. aa+4
+        const int e = tid + u * kFThreads;
+        if (e < NTX) {
+          const int bb = e / (kFX + 2), aa = e % (kFX + 2);
+          const double* r = &sQ[bb + 3][aa];
+          if (!Tx[u]) Tx[u] = troubled5(r[0], r[1], r[2], r[3], r[4], tx);  // T is the OR over components
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < EY; ++u) {  // T_y: column ay, rows by .. by+4
+        const int e = tid + u * kFThreads;
+        if (e < NTY) {
+          const int ay = e % kFX, by = e / kFX;
+          if (!Ty[u])
+            Ty[u] = troubled5(sQ[by][ay + 3], sQ[by + 1][ay + 3], sQ[by + 2][ay + 3], sQ[by + 3][ay + 3],
+                              sQ[by + 4][ay + 3], ty);
+        }
+      }
     }
-    for (int e = tid; e < (kFY + 2) * kFX; e += kFThreads) {  // T_y: column ay, rows by .. by+4
-      const int ay = e % kFX, by = e / kFX;
-      int t = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        t |= troubled5(sW[k][by][ay + 3], sW[k][by + 1][ay + 3], sW[k][by + 2][ay + 3], sW[k][by + 3][ay + 3],
-                       sW[k][by + 4][ay + 3], ty);
-      sTy[by][ay] = (uint8_t)t;
+    for (int u = 0; u < EX; ++u) {
+      const int e = tid + u * kFThreads;
+      if (e < NTX) sTx[e / (kFX + 2)][e % (kFX + 2)] = (uint8_t)Tx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < EY; ++u) {
+      const int e = tid + u * kFThreads;
+      if (e < NTY) sTy[e / kFX][e % kFX] = (uint8_t)Ty[u];
     }
     __syncthreads();
 #pragma unroll

@@ -22,7 +22,7 @@ struct LaunchCtx {
   TimeDev* ts;           // device array [nprob]
   const int* off_cell;   // prefix sums of 256-cell blocks per problem
   double* qpart;         // CFL minimum of every 256-cell block (cell_blocks entries)
-  const int* off_ext;    // prefix sums of flag blocks over the extended range: 32 x 16 tiles (2D) or
+  const int* off_ext;    // prefix sums of flag blocks over the extended range: kFX x kFY tiles (2D) or
                          // 256-cell runs (1D)
   const int* off_flux;   // prefix sums of flux tiles (x then y) for the current tile shape
   int nprob, dim, fp32, tile;
@@ -33,6 +33,10 @@ struct LaunchCtx {
   int tfm;               // tangential flag: 0 the side cell's flag, 1 the indicator on the line values (2D)
   int cell_blocks, ext_blocks, flux_blocks;  // flux_blocks: tiles of all problems
 };
+
+// 2D flag tiles: kFX x kFY cells of the extended range [-2, n+1]^2 per block of kFThreads threads
+constexpr int kFX = 32, kFY = 32, kFThreads = 256;
+inline long flag_tiles2(int nx, int ny) { return (long)((nx + 4 + kFX - 1) / kFX) * ((ny + 4 + kFY - 1) / kFY); }
 
 // number of flux tiles of one problem for tile shape `tile`
 inline int flux_tiles(int dim, int nx, int ny, int tile) {
