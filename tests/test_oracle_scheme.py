@@ -517,6 +517,19 @@ def test_interface_vacuum_carries_no_flux(dim):
         assert not Fd.any() and not Fh.any()
 
 
+def test_interface_vacuum_rule_gated_on_physical_sides_and_density():
+    """The no-flux rule applies only to two physical sides whose interface equilibrium density falls below
+    the unit roundoff of the smaller side density: a side with negative pressure gives NaN (which the
+    step reports), and a side of density 1e-300 next to a normal state still gives a finite, non-zero flux
+    (the interface equilibrium holds half the normal side's density)."""
+    P = O.Problem(dim=1, nx=8, ny=1, c1=0.0, c2=1.0)
+    z = np.zeros(3)
+    Fd, Fh, _ = O.gp_flux(P, np.array([1.0, 0.1, -0.1]), z, z, np.array([1.0, 0.2, 2.5]), z, z, 1e-3)
+    assert np.isnan(Fd).all() and np.isnan(Fh).all()
+    Fd, Fh, _ = O.gp_flux(P, np.array([1e-300, 0.0, 2.5e-300]), z, z, np.array([1.0, 0.0, 2.5]), z, z, 1e-3)
+    assert np.isfinite(Fd).all() and np.isfinite(Fh).all() and Fd[0] < 0 and abs(Fd[0]) > 1e-4
+
+
 def test_interface_vacuum_step_stays_physical():
     """A 1D state of two cold halves separating at Mach ~60 (the centre face has no equilibrium): the
     step keeps every cell physical, conserves mass and leaves the centre face without flux (the two
