@@ -497,9 +497,10 @@ static void tune_cache_store(const std::string& key, int tile) {
 }
 
 // Time the first-stage flux kernel of every launch configuration on the current state (dt already set
-// by the step's finalize launch) and keep the fastest: two interleaved rounds of three timed launches per
-// configuration after one untimed launch, the better round counting, so that clock ramps and noise
-// affect all candidates alike.
+// by the step's finalize launch) and keep the fastest: after a burst of untimed launches that brings the
+// clocks up (the autotuner usually runs first thing in a process), three interleaved rounds of three
+// timed launches per configuration after one untimed launch, the best round counting, so that clock
+// ramps and noise affect all candidates alike.
 static hgks_status autotune(hgks* h) {
   h->tuned = 1;
   const std::string key = tune_key(h);
@@ -515,8 +516,9 @@ static hgks_status autotune(hgks* h) {
   {
     LaunchCtx L = ctx(h);
     launch_flags(L, 0, 0, 0);
+    for (int r = 0; r < 16; ++r) launch_flux(L, 1);
   }
-  for (int round = 0; round < 2; ++round) {
+  for (int round = 0; round < 3; ++round) {
     for (int t = 0; t < kNumConfigs; ++t) {
       h->tile = t;
       LaunchCtx L = ctx(h);
