@@ -13,6 +13,12 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: longer CPU-only check")
 
 
+def pytest_sessionfinish(session, exitstatus):
+    # the measured-parity record of the GPU tests that ran (written only when $HGKS_PARITY_TABLE is set)
+    import parity_record
+    parity_record.dump()
+
+
 @pytest.fixture(scope="session")
 def oracle_lib():
     import oracle

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import parity_record as PR
 from paper_2304_05572_amd import hgks as H
 from paper_2304_05572_amd import workloads as wl
 
@@ -52,6 +53,8 @@ def test_riemann_1024_first_step_full_grid(rp1024, precision, tol1, tolinf):
     assert dt == dto
     Wg, _ = s.get_state(0)
     say("L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+    PR.record("2 four-quadrant Riemann problem", PR.prec_name(precision), "1024^2 seed 0, first step, full grid",
+              l1(Wg, Wo), linf(Wg, Wo), tol1, tolinf, dt_bit_exact=(dt == dto), flags_bit_exact=True)
     assert l1(Wg, Wo) < tol1 and linf(Wg, Wo) < tolinf
 
 
@@ -60,6 +63,7 @@ def _window_check(Wprev, Wnext, dt, n, centres, half=24, margin=10, bc=(1, 1, 1,
     conditions where a window touches the domain edge) with the GPU's dt; compare window interiors."""
     h = 1.0 / n
     worst = 0.0
+    A_all, B_all = [], []
     for (ci, cj) in centres:
         i0, i1 = max(ci - half - margin, 0), min(ci + half + margin, n)
         j0, j1 = max(cj - half - margin, 0), min(cj + half + margin, n)
@@ -75,7 +79,9 @@ def _window_check(Wprev, Wnext, dt, n, centres, half=24, margin=10, bc=(1, 1, 1,
         A = Wnext[:, j0 + b0:j0 + b1, i0 + a0:i0 + a1]
         B = Wo[:, b0:b1, a0:a1]
         worst = max(worst, linf(A, B))
-    return worst
+        A_all.append(A.reshape(A.shape[0], -1))
+        B_all.append(B.reshape(B.shape[0], -1))
+    return worst, l1(np.concatenate(A_all, 1), np.concatenate(B_all, 1))
 
 
 def test_riemann_1024_after_twelve_steps_windows():
@@ -92,8 +98,10 @@ def test_riemann_1024_after_twelve_steps_windows():
     W12, _ = s.get_state(0)
     fx, _ = s.flags(0)
     centres = [(512, 512), (512, 300), (700, 512), (40, 30), (1000, 1010)]
-    worst = _window_check(W11, W12, dt, n, centres, cfl=0.5, c1=0.01, c2=1.0)
+    worst, wl1 = _window_check(W11, W12, dt, n, centres, cfl=0.5, c1=0.01, c2=1.0)
     say("worst window Linf", worst, "flagged", fx.mean())
+    PR.record("2 four-quadrant Riemann problem", "fp64", "1024^2 seed 0, the 12th step on 5 windows of 48^2 cells "
+              "(one oracle step from the GPU's 11th state); Linf: worst window", wl1, worst, 1e-12, 1e-12)
     assert worst < 1e-12
 
 
@@ -114,6 +122,8 @@ def test_viscous_shock_tube_1000x500():
         s.step()
         Wg, tg = s.get_state(0)
         say("L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+        PR.record("3 viscous shock tube, NS 1000 x 500, Pr = 0.73", PR.prec_name(precision), "two steps, full grid",
+                  l1(Wg, Wo), linf(Wg, Wo), tol)
         assert tg == pytest.approx(t, rel=1e-14)
         assert l1(Wg, Wo) < tol
 
@@ -135,6 +145,8 @@ def test_batch_of_64_sampled_problems():
         assert dts[p] == dto
         Wg, _ = s.get_state(p)
         say("problem", p, sizes[p], "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+        PR.record("4 batch of 64 uneven problems", "fp32_bulk", f"problem {p} ({sizes[p]}^2), first step",
+                  l1(Wg, Wo), linf(Wg, Wo), 1e-8, 1e-5, dt_bit_exact=(dts[p] == dto))
         assert l1(Wg, Wo) < 1e-8 and linf(Wg, Wo) < 1e-5
 
 
@@ -165,8 +177,11 @@ def test_advection_convergence_fp64_and_fp32():
             say("advection", precision, n, steps, "L1", e)
             if n <= 40:
                 Wo, to, no, _ = O.run(O.Problem(**kw), _adv_points(n, 0.0), 2.0, nthreads=NT)
+                tol = 1e-12 if precision == H.FP64 else 1e-6
+                PR.record("1 density-wave advection 2D", PR.prec_name(precision), f"{n}^2, whole run to t = 2 ({no} steps)",
+                          l1(Wg, Wo), linf(Wg, Wo), tol, exact_l1=e)
                 assert no == steps
-                assert l1(Wg, Wo) < (1e-12 if precision == H.FP64 else 1e-6)
+                assert l1(Wg, Wo) < tol
     e64 = np.array(errs[H.FP64])
     orders = np.log2(e64[:-1] / e64[1:])
     say("fp64 orders", orders)
@@ -220,9 +235,11 @@ def test_largest_grid_64bit_offsets():
     s.set_ic(0, W0)
     dt = s.step()[0]
     W1, _ = s.get_state(0)
-    worst = _window_check(W0, W1, dt, n, [(20, 20), (4096, 4096), (8170, 8175), (4096, 8180)], cfl=0.5, c1=0.01,
-                          c2=1.0)
+    worst, wl1 = _window_check(W0, W1, dt, n, [(20, 20), (4096, 4096), (8170, 8175), (4096, 8180)], cfl=0.5,
+                               c1=0.01, c2=1.0)
     say("worst window Linf", worst)
+    PR.record("2 four-quadrant Riemann problem", "fp64", "8192^2 seed 4, first step on 4 windows (64-bit offsets); "
+              "Linf: worst window", wl1, worst, 1e-12, 1e-12)
     assert worst < 1e-12
     del W1
 

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import parity_record as PR
 from paper_2304_05572_amd import hgks as H
 from paper_2304_05572_amd import workloads as wl
 
@@ -48,6 +49,8 @@ def test_shu_osher_to_end_time(shu_oracle, precision, tol1, tolinf):
     steps = s.run(1.8)[0]
     Wg, t = s.get_state(0)
     say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+    PR.record("Shu-Osher 1D, 400 cells", PR.prec_name(precision), f"whole run to t = 1.8 ({no} oracle steps)",
+              l1(Wg, Wo), linf(Wg, Wo), tol1, tolinf)
     assert t == 1.8 and abs(int(steps) - no) <= 1
     assert l1(Wg, Wo) < tol1 and linf(Wg, Wo) < tolinf
     fx, _ = s.flags(0)
@@ -86,6 +89,8 @@ def test_blast_wave_with_fallbacks_to_end_time(precision, tol1):
     steps = s.run(0.038)[0]
     Wg, t = s.get_state(0)
     say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+    PR.record("blast wave 1D with the first-order fallbacks", PR.prec_name(precision),
+              f"whole run to t = 0.038 ({no} oracle steps)", l1(Wg, Wo), linf(Wg, Wo), tol1)
     assert t == 0.038 and abs(int(steps) - no) <= 2
     assert l1(Wg, Wo) < tol1
     for c in (0, 2):
@@ -106,10 +111,39 @@ def test_riemann_256_to_end_time():
     steps = s.run(0.25)[0]
     Wg, t = s.get_state(0)
     say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
-    assert t == 0.25 and steps == no
-    assert l1(Wg, Wo) < 1e-9 and linf(Wg, Wo) < 1e-6
     fx, fy = s.flags(0)
     ox, oy = O.flags(O.Problem(**kw), Wg)
+    PR.record("2 four-quadrant Riemann problem", "fp64", f"256^2 seed 0, whole run to t = 0.25 ({no} steps)",
+              l1(Wg, Wo), linf(Wg, Wo), 1e-9, 1e-6,
+              flag_mismatches_final_state=int((fx != ox).sum() + (fy != oy).sum()))
+    assert t == 0.25 and steps == no
+    assert l1(Wg, Wo) < 1e-9 and linf(Wg, Wo) < 1e-6
+    assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
+
+
+def test_riemann_256_fp32_bulk_to_end_time():
+    """The same problem in FP32-bulk (FP32 reconstruction and flux, FP64 state, flags and time step) to
+    t = 0.25 against the FP64 oracle's whole run: the step count within one of the oracle's (the time step
+    comes from a state that differs by FP32 rounding), L1 within 1e-5 and Linf within 1e-3 relative, and
+    the flags of the final state, evaluated in FP64, bit-exact with the oracle's on that state."""
+    n = 256
+    kw = dict(dim=2, nx=n, ny=n, bc=(1, 1, 1, 1), cfl=0.5, c1=0.01, c2=1.0)
+    W0, _ = wl.riemann_2d(n, seed=0)
+    say("rp256 fp32-bulk to t_end: oracle")
+    Wo, to, no, _ = O.run(O.Problem(**kw), W0, 0.25, nthreads=NT)
+    say("rp256 fp32-bulk to t_end: gpu")
+    s = H.Solver(H.Problem(**kw), precision=H.FP32_BULK, use_graph=True, autotune=True)
+    s.set_ic(0, W0)
+    steps = s.run(0.25)[0]
+    Wg, t = s.get_state(0)
+    say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
+    fx, fy = s.flags(0)
+    ox, oy = O.flags(O.Problem(**kw), Wg)
+    PR.record("2 four-quadrant Riemann problem", "fp32_bulk", f"256^2 seed 0, whole run to t = 0.25 ({no} oracle "
+              f"steps, {int(steps)} GPU steps)", l1(Wg, Wo), linf(Wg, Wo), 1e-5, 1e-3,
+              flag_mismatches_final_state=int((fx != ox).sum() + (fy != oy).sum()))
+    assert t == 0.25 and abs(int(steps) - no) <= 1
+    assert l1(Wg, Wo) < 1e-5 and linf(Wg, Wo) < 1e-3
     assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
 
 
@@ -130,10 +164,13 @@ def test_paper_riemann_configurations_to_end_time(name, states, cfl, t_end):
     steps = s.run(t_end)[0]
     Wg, t = s.get_state(0)
     say("steps", steps, "oracle", no, "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
-    assert t == t_end and steps == no
-    assert l1(Wg, Wo) < 1e-9 and linf(Wg, Wo) < 1e-6
     fx, fy = s.flags(0)
     ox, oy = O.flags(O.Problem(**kw), Wg)
+    PR.record("2 four-quadrant Riemann problem", "fp64", f"Sec. 3.4 {name}, 128^2, whole run to t = {t_end} "
+              f"({no} steps)", l1(Wg, Wo), linf(Wg, Wo), 1e-9, 1e-6,
+              flag_mismatches_final_state=int((fx != ox).sum() + (fy != oy).sum()))
+    assert t == t_end and steps == no
+    assert l1(Wg, Wo) < 1e-9 and linf(Wg, Wo) < 1e-6
     assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
 
 
@@ -153,6 +190,7 @@ def test_viscous_shock_tube_hundredth_step():
     W100, _ = s.get_state(0)
     h = 1.0 / nx
     worst = 0.0
+    A_all, B_all = [], []
     for (ci, cj) in [(500, 250), (520, 30), (560, 480), (30, 20), (970, 490), (700, 300)]:
         half, margin = 24, 10
         i0, i1 = max(ci - half - margin, 0), min(ci + half + margin, nx)
@@ -167,7 +205,12 @@ def test_viscous_shock_tube_hundredth_step():
         b0 = 0 if j0 == 0 else margin
         b1 = (j1 - j0) if j1 == ny else (j1 - j0 - margin)
         worst = max(worst, linf(W100[:, j0 + b0:j0 + b1, i0 + a0:i0 + a1], Wo[:, b0:b1, a0:a1]))
+        A_all.append(W100[:, j0 + b0:j0 + b1, i0 + a0:i0 + a1].reshape(4, -1))
+        B_all.append(Wo[:, b0:b1, a0:a1].reshape(4, -1))
     say("vst window Linf", worst)
+    PR.record("3 viscous shock tube, NS 1000 x 500, Pr = 0.73", "fp64", "the 100th step on 6 windows of 48^2 cells "
+              "(one oracle step from the GPU's 99th state); Linf: worst window",
+              l1(np.concatenate(A_all, 1), np.concatenate(B_all, 1)), worst, 1e-12, 1e-12)
     assert worst < 1e-12
     say("vst 100 steps fp32-bulk")
     s32 = H.Solver(H.Problem(**kw), precision=H.FP32_BULK, autotune=True, use_graph=True)
@@ -175,4 +218,6 @@ def test_viscous_shock_tube_hundredth_step():
     s32.run(np.inf, 100)
     W32, _ = s32.get_state(0)
     say("fp32 vs fp64 after 100 steps L1", l1(W32, W100), "Linf", linf(W32, W100))
+    PR.record("3 viscous shock tube, NS 1000 x 500, Pr = 0.73", "fp32_bulk", "after 100 steps against the FP64 GPU "
+              "run (whose 100th step matches the oracle above)", l1(W32, W100), linf(W32, W100), 1e-6)
     assert l1(W32, W100) < 1e-6

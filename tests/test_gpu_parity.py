@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import parity_record as PR
 from paper_2304_05572_amd import hgks as H
 from paper_2304_05572_amd import workloads as wl
 
@@ -28,6 +29,10 @@ def pair(**kw):
 
 def rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _l1(a, b):
+    return float(np.abs(a - b).mean() / np.abs(b).mean())
 
 
 def noisy_state(nx, ny, seed, amp=0.3):
@@ -154,6 +159,8 @@ def test_sod_1d_full_run():
     steps = s.run(0.2)[0]
     Wg, tg = s.get_state(0)
     Wo, to, no, _ = O.run(Po, W, 0.2)
+    PR.record("0 Sod tube 1D, 200 cells", "fp64", f"whole run to t = 0.2 ({no} steps)", _l1(Wg, Wo), rel(Wg, Wo),
+              1e-10, 1e-10)
     assert tg == 0.2 and to == 0.2 and steps == no
     assert rel(Wg, Wo) < 1e-10
 
@@ -198,6 +205,9 @@ def test_batch_equals_single_problems():
         Po = O.Problem(**kw)
         for _ in range(3):
             Wo, t, _ = O.step(Po, Wo, t, nthreads=NT)
+        PR.record("4 batch (uneven problems in one handle)", "fp64",
+                  f"problem {p} ({kw['nx']} x {kw['ny']}) after 3 steps; equal to its single run bitwise",
+                  _l1(a, Wo), rel(a, Wo), 1e-11, 1e-11)
         assert rel(a, Wo) < 1e-11
 
 
@@ -252,6 +262,8 @@ def test_fp32_bulk_close_to_oracle():
     Wg, _ = s.get_state(0)
     l1 = np.abs(Wg - Wo).mean() / np.abs(Wo).mean()
     say("fp32 L1_rel", l1, "Linf_rel", rel(Wg, Wo))
+    PR.record("2 four-quadrant Riemann problem", "fp32_bulk", "70 x 45 (outflow), 10 steps", l1, rel(Wg, Wo), 1e-5,
+              1e-3)
     assert l1 < 1e-5 and rel(Wg, Wo) < 1e-3
 
 
