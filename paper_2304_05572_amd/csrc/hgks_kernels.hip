@@ -731,12 +731,15 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ probs, TimeDev* __restrict__ ts,
                                                 const int* __restrict__ off, int nprob, int stage,
                                                 double* __restrict__ qpart) {
-  const int p = find_prob(off, nprob, blockIdx.x);
+  // each XCD takes a contiguous range of blocks: a row's y-faces are read by the blocks of the rows on
+  // either side, which then share one L2
+  const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int p = find_prob(off, nprob, b);
   const ProbDev& P = probs[p];
   TimeDev& tsp = ts[p];
   if (!tsp.active) return;
   const size_t ncell = (size_t)P.nx * P.ny;
-  const size_t cell = (size_t)(blockIdx.x - off[p]) * blockDim.x + threadIdx.x;
+  const size_t cell = (size_t)(b - off[p]) * blockDim.x + threadIdx.x;
   double q = __builtin_inf();
   if (cell < ncell) {
     const int i = (int)(cell % P.nx), j = (int)(cell / P.nx);
@@ -796,7 +799,7 @@ __global__ void __launch_bounds__(256) k_update(const ProbDev* __restrict__ prob
   }
   if (stage == 2) {
     q = block_min(q);
-    if (threadIdx.x == 0) qpart[blockIdx.x] = q;
+    if (threadIdx.x == 0) qpart[b] = q;
   }
 }
 
