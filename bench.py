@@ -439,8 +439,8 @@ def main():
                          "to their end times, hybrid against forced WENO5-AO")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (each box has one GPU); "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (the sharding is a design "
+              "only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     variants = set(x for x in args.variants.split(",") if x)
     if args.copy_calibration:
