@@ -1051,7 +1051,7 @@ static void flux_variant(const LaunchCtx& L, int stage, int* grid) {
 
 // launch configurations: tile shape and the waves-per-SIMD target the register allocator works to
 // (1: no target; 2 or 3: spill what does not fit rather than lose occupancy)
-const TileShape kTiles[kNumTiles] = {{8, 8, 1}, {8, 8, 2}, {16, 8, 1}, {16, 8, 2}, {16, 16, 2}, {8, 8, 3}};
+const TileShape kTiles[kNumTiles] = {{8, 8, 1}, {8, 8, 2}, {16, 8, 1}, {16, 8, 2}, {16, 8, 3}, {8, 8, 3}};
 
 template <typename T>
 static void launch_flux_t(const LaunchCtx& L, int stage, int* grid) {
@@ -1060,7 +1060,7 @@ static void launch_flux_t(const LaunchCtx& L, int stage, int* grid) {
     case 1: flux_variant<T, 8, 8, 2>(L, stage, grid); break;
     case 2: flux_variant<T, 16, 8, 1>(L, stage, grid); break;
     case 3: flux_variant<T, 16, 8, 2>(L, stage, grid); break;
-    case 4: flux_variant<T, 16, 16, 2>(L, stage, grid); break;
+    case 4: flux_variant<T, 16, 8, 3>(L, stage, grid); break;
     default: flux_variant<T, 8, 8, 3>(L, stage, grid); break;
   }
 }
