@@ -176,3 +176,44 @@ def test_compensation_conserves_the_carried_state():
     say("largest absolute drift of a conserved total: plain", drift[False], "compensated", drift[True])
     assert drift[False] < 1e-11  # both conserve to rounding
     assert drift[True] < drift[False] / 4
+
+
+# Every launch configuration in the kernel's other instances: the Prandtl correction (Navier-Stokes, Pr =
+# 0.73), the line-value tangential flag, forced WENO5-AO (every side through the characteristic path) and
+# FP32-bulk. Stage fluxes of a 37 x 29 state (ragged against every tile shape) against the oracle's.
+MODES = {
+    "ns_prandtl": dict(eqn=O.NS, mu=2e-3, Pr=0.73, bc=(3, 2, 3, 2)),
+    "line_value_flag": dict(tangential_flag_mode=1, bc=(1, 1, 1, 1)),
+    "forced_wenoao": dict(recon=1, bc=(1, 1, 1, 1)),
+    "fp32_bulk": dict(bc=(1, 1, 1, 1)),
+}
+_MODE_ORACLE = {}
+
+
+def _mode_case(mode):
+    if mode not in _MODE_ORACLE:
+        W = wl.quadrants(37, 29, wl.RP_CONFIG6)
+        kw = dict(nx=37, ny=29, **MODES[mode])
+        Po = O.Problem(**kw)
+        dt = 0.4 * O.cfl_dt(Po, W) / Po.cfl
+        _MODE_ORACLE[mode] = (kw, W, dt, O.stage_fluxes(Po, W, dt, nthreads=NT))
+    return _MODE_ORACLE[mode]
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("config", range(NCONF))
+def test_every_launch_config_in_every_kernel_instance(config, mode):
+    """FP64 instances: every interface's F and dF/dt within 1e-12 of the largest magnitude of its array.
+    FP32-bulk: within 1e-4 of it (the reconstruction and the moments carry a few hundred units of the FP32
+    roundoff, 6e-8, into F and dF/dt; the time coefficients stay FP64)."""
+    kw, W, dt, o = _mode_case(mode)
+    prec = H.FP32_BULK if mode == "fp32_bulk" else H.FP64
+    s = H.Solver(H.Problem(**kw), precision=prec, tile=config)
+    s.set_ic(0, W)
+    g = s.stage_fluxes(0, dt)
+    assert s.tile()[3] == config
+    s.close()
+    tol = 1e-4 if prec == H.FP32_BULK else 1e-12
+    worst = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(g, o))
+    say("config", config, mode, "worst", worst)
+    assert worst <= tol
