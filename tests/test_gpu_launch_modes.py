@@ -217,3 +217,28 @@ def test_every_launch_config_in_every_kernel_instance(config, mode):
     worst = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(g, o))
     say("config", config, mode, "worst", worst)
     assert worst <= tol
+
+
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32_BULK])
+@pytest.mark.parametrize("config", range(NCONF))
+def test_minimum_grid_every_launch_config(config, precision):
+    """The smallest grid the library takes (5 x 5, a fraction of one tile, ghosts reaching across the
+    whole grid: periodic sides on x, reflecting and no-slip walls on y), two steps against the oracle:
+    the first time step bit-exact (identical input state); the states within 1e-12 (FP64) or 1e-5
+    (FP32-bulk) of the largest magnitude, and the second time step, which follows from the state after the
+    first step, relatively within the same bound."""
+    kw = dict(nx=5, ny=5, bc=(0, 0, 2, 3))
+    W = noisy_state(5, 5, 11)
+    Wo, t, dts = W.copy(), 0.0, []
+    for _ in range(2):
+        Wo, t, dt = O.step(O.Problem(**kw), Wo, t, nthreads=1)
+        dts.append(dt)
+    s = H.Solver(H.Problem(**kw), precision=precision, tile=config)
+    s.set_ic(0, W)
+    got = [s.step()[0] for _ in range(2)]
+    Wg, _ = s.get_state(0)
+    s.close()
+    say("5x5 config", config, precision, rel(Wg, Wo), got[1] / dts[1] - 1)
+    tol = 1e-12 if precision == H.FP64 else 1e-5
+    assert got[0] == dts[0] and abs(got[1] / dts[1] - 1) < tol
+    assert rel(Wg, Wo) < tol
