@@ -242,3 +242,26 @@ def test_minimum_grid_every_launch_config(config, precision):
     tol = 1e-12 if precision == H.FP64 else 1e-5
     assert got[0] == dts[0] and abs(got[1] / dts[1] - 1) < tol
     assert rel(Wg, Wo) < tol
+
+
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32_BULK])
+@pytest.mark.parametrize("nx,ny", [(2000, 5), (5, 2000)])
+def test_strip_grids(nx, ny, precision):
+    """Strips one way thin (five cells: every tile ragged across them, ghosts on both sides of every row)
+    and long the other, outflow on the long sides, reflecting walls on the short: flags bit-exact, the first
+    time step bit-exact, one step within 1e-12 (FP64) or 1e-5 (FP32-bulk) of the largest magnitude."""
+    kw = dict(nx=nx, ny=ny, bc=(2, 1, 1, 2) if nx > ny else (1, 2, 2, 1))
+    W = noisy_state(nx, ny, 12)
+    Po = O.Problem(**kw)
+    Wo, _, dto = O.step(Po, W, 0.0, nthreads=NT)
+    s = H.Solver(H.Problem(**kw), precision=precision)
+    s.set_ic(0, W)
+    fx, fy = s.flags(0)
+    ox, oy = O.flags(Po, W)
+    dt = s.step()[0]
+    Wg, _ = s.get_state(0)
+    s.close()
+    say("strip", nx, ny, precision, rel(Wg, Wo))
+    assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
+    assert dt == dto
+    assert rel(Wg, Wo) < (1e-12 if precision == H.FP64 else 1e-5)
