@@ -27,7 +27,7 @@ from paper_2304_05572_amd import hgks as H
 from paper_2304_05572_amd import workloads as wl
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="the first GPU run that included this module ended with the box faulted (the record names no test); "
+    reason="the first GPU run that included this module ended in a GPU fault that named no test; "
            "reading this module and the kernel changes of that run found no cause, so the module stays off the "
            "GPU until one is shown (the kernel changes were taken out)")]
 NT = min(16, os.cpu_count() or 1)
