@@ -114,7 +114,11 @@ def launch_config(tile):
             "persistent_blocks": tile[4] if tile[4] else None}
 
 
-def time_solver(H, problems, states, precision, steps, warmup, tile, compensated=False):
+def time_solver(H, problems, states, precision, steps, warmup, tile, compensated=False, repeats=0, out=None):
+    """Seconds of exactly `steps` steps after `warmup` untimed ones, the flux kernel's mean launch time and
+    the handle's stats; with `repeats`, the same window (initial data, `warmup` untimed steps, `steps` timed
+    ones) is run that many more times on the same handle and launch configuration, its seconds going to
+    out["repeat_seconds"] (the reported window is the first)."""
     import torch
     s = H.Solver(problems, precision=precision, tile=tile, profile=1, autotune=(tile < 0), compensated=compensated)
     for p, W in enumerate(states):
@@ -133,6 +137,18 @@ def time_solver(H, problems, states, precision, steps, warmup, tile, compensated
     stats = [s.stats(p) for p in range(len(problems))]
     tile_used = s.tile()
     prof = {k: (prof1[k][0] - prof0[k][0], prof1[k][1] - prof0[k][1]) for k in prof1}
+    if repeats and out is not None:
+        secs = []
+        for _ in range(repeats):
+            for p, W in enumerate(states):
+                s.set_ic(p, W)
+            s.run(np.inf, warmup)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            s.run(np.inf, steps)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - a)
+        out["repeat_seconds"] = secs
     s.close()
     return t1 - t0, flux_ms / max(flux_n, 1), stats, tile_used, prof
 
@@ -471,10 +487,16 @@ def main():
         if name not in variants:
             continue
         log(f"[bench] timing {name}: {args.warmup} warm-up + {args.steps} steps")
+        rep = {}
         el, flux_ms, stats, tile, prof = time_solver(H, [rp_problem(H, n, recon)], [W0], prec, args.steps,
-                                                     args.warmup, args.tile, comp)
+                                                     args.warmup, args.tile, comp, repeats=4 if name == "fp64" else 0,
+                                                     out=rep)
         res[name] = dict(seconds=el, flux_ms=flux_ms, stats=stats[0], tile=tile, prof=prof,
                          mcells=cells * args.steps / el / 1e6, ms_per_step=el / args.steps * 1e3)
+        if rep:
+            wins = [el] + rep["repeat_seconds"]
+            res[name]["windows"] = {"steps_each": args.steps, "mcells": [cells * args.steps / w / 1e6 for w in wins],
+                                    "median_mcells": float(np.median([cells * args.steps / w / 1e6 for w in wins]))}
         if name in ("fp64", "fp32", "fp32c"):
             res[name].update(side_windows(H, [rp_problem(H, n, recon)], [W0], prec, tile[3], comp))
         if name == "fp64":
@@ -608,6 +630,7 @@ def main():
             "fp64": {"value": r["mcells"], "ms_per_step": r["ms_per_step"], "flux_ms_per_launch": r["flux_ms"],
                      "kernel_ms_per_step": r["kernel_ms_per_step"], "graph_ms_per_step": r["graph_ms_per_step"],
                      "host_io": r["host_io"],
+                     "five_windows": r.get("windows"),
                      "l1_rel_vs_oracle": parity.get("fp64", (None,) * 3)[0],
                      "linf_rel_vs_oracle": parity.get("fp64", (None,) * 3)[1],
                      "dt_bit_exact_vs_oracle": parity.get("fp64", (None,) * 3)[2]},
