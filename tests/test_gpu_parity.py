@@ -149,20 +149,29 @@ def test_steps_fp64(name):
     assert np.array_equal(fx, ox) and np.array_equal(fy, oy)
 
 
-def test_sod_1d_full_run():
-    """Shock tube, 200 cells, reflective ends, CFL 0.5, t_end 0.2."""
+@pytest.mark.parametrize("precision", [H.FP64, H.FP32_BULK])
+def test_sod_1d_full_run(precision):
+    """Shock tube, 200 cells, reflective ends, CFL 0.5, t_end 0.2: FP64 within 1e-10 of the oracle's whole
+    run (Linf relative); FP32-bulk within 1e-5 (L1) and 1e-3 (Linf), its step count within one of the
+    oracle's (its time steps come from a state that differs by FP32 rounding)."""
     Po, Ph = pair(dim=1, nx=200, ny=1, bc=(2, 2, 0, 0), cfl=0.5)
     W = wl.sod_1d(200)
-    say("sod 1d full run")
-    s = H.Solver(Ph)
+    say("sod 1d full run", precision)
+    s = H.Solver(Ph, precision=precision)
     s.set_ic(0, W)
     steps = s.run(0.2)[0]
     Wg, tg = s.get_state(0)
     Wo, to, no, _ = O.run(Po, W, 0.2)
-    PR.record("0 Sod tube 1D, 200 cells", "fp64", f"whole run to t = 0.2 ({no} steps)", _l1(Wg, Wo), rel(Wg, Wo),
-              1e-10, 1e-10)
-    assert tg == 0.2 and to == 0.2 and steps == no
-    assert rel(Wg, Wo) < 1e-10
+    if precision == H.FP64:
+        PR.record("0 Sod tube 1D, 200 cells", "fp64", f"whole run to t = 0.2 ({no} steps)", _l1(Wg, Wo),
+                  rel(Wg, Wo), 1e-10, 1e-10)
+        assert tg == 0.2 and to == 0.2 and steps == no
+        assert rel(Wg, Wo) < 1e-10
+    else:
+        PR.record("0 Sod tube 1D, 200 cells", "fp32_bulk", f"whole run to t = 0.2 ({no} oracle steps, {int(steps)} "
+                  "GPU steps)", _l1(Wg, Wo), rel(Wg, Wo), 1e-5, 1e-3)
+        assert tg == 0.2 and abs(int(steps) - no) <= 1
+        assert _l1(Wg, Wo) < 1e-5 and rel(Wg, Wo) < 1e-3
 
 
 def test_navier_stokes_steps():
