@@ -128,13 +128,14 @@ def test_viscous_shock_tube_1000x500():
         assert l1(Wg, Wo) < tol
 
 
-def test_batch_of_64_sampled_problems():
-    """64 uneven Riemann problems in one handle, FP32-bulk, one step; the smallest, the largest and two
-    others are checked against the oracle (each has its own dt)."""
+@pytest.mark.parametrize("precision,tol1,tolinf", [(H.FP32_BULK, 1e-8, 1e-5), (H.FP64, 1e-14, 1e-12)])
+def test_batch_of_64_sampled_problems(precision, tol1, tolinf):
+    """64 uneven Riemann problems in one handle, one step; the smallest, the largest and two others are
+    checked against the oracle (each has its own dt, bit-exact)."""
     sizes = wl.batch_sizes(64, seed=0)
     states = [wl.riemann_2d(m, seed=k + 1)[0] for k, m in enumerate(sizes)]
-    say("batch 64", sum(m * m for m in sizes), "cells")
-    s = H.Solver([H.Problem(**rp(m)) for m in sizes], precision=H.FP32_BULK, autotune=True)
+    say("batch 64", sum(m * m for m in sizes), "cells", precision)
+    s = H.Solver([H.Problem(**rp(m)) for m in sizes], precision=precision, autotune=True)
     for p, W in enumerate(states):
         s.set_ic(p, W)
     dts = s.step()
@@ -145,9 +146,9 @@ def test_batch_of_64_sampled_problems():
         assert dts[p] == dto
         Wg, _ = s.get_state(p)
         say("problem", p, sizes[p], "L1", l1(Wg, Wo), "Linf", linf(Wg, Wo))
-        PR.record("4 batch of 64 uneven problems", "fp32_bulk", f"problem {p} ({sizes[p]}^2), first step",
-                  l1(Wg, Wo), linf(Wg, Wo), 1e-8, 1e-5, dt_bit_exact=(dts[p] == dto))
-        assert l1(Wg, Wo) < 1e-8 and linf(Wg, Wo) < 1e-5
+        PR.record("4 batch of 64 uneven problems", PR.prec_name(precision), f"problem {p} ({sizes[p]}^2), first step",
+                  l1(Wg, Wo), linf(Wg, Wo), tol1, tolinf, dt_bit_exact=(dts[p] == dto))
+        assert l1(Wg, Wo) < tol1 and linf(Wg, Wo) < tolinf
 
 
 def _adv_points(n, t):
