@@ -105,6 +105,27 @@ def test_riemann_1024_after_twelve_steps_windows():
     assert worst < 1e-12
 
 
+def test_riemann_1024_hundredth_step_windows():
+    """The 100th step of the 1024^2 problem (seed 0) in the benchmark's launch configuration (autotuned), on
+    windows over the developed shocks and contacts, the centre, the corners (one oracle step from the
+    GPU's 99th state with its dt)."""
+    n = 1024
+    W0, _ = wl.riemann_2d(n, seed=0)
+    say("rp1024 windows of the 100th step")
+    s = H.Solver(H.Problem(**rp(n)), precision=H.FP64, autotune=True)
+    s.set_ic(0, W0)
+    s.run(np.inf, 99)
+    W99, _ = s.get_state(0)
+    dt = s.step()[0]
+    W100, _ = s.get_state(0)
+    centres = [(512, 512), (512, 300), (700, 512), (300, 700), (40, 30), (1000, 1010), (30, 1000)]
+    worst, wl1 = _window_check(W99, W100, dt, n, centres, cfl=0.5, c1=0.01, c2=1.0)
+    say("worst window Linf", worst)
+    PR.record("2 four-quadrant Riemann problem", "fp64", "1024^2 seed 0, the 100th step on 7 windows of 48^2 cells "
+              "(one oracle step from the GPU's 99th state); Linf: worst window", wl1, worst, 1e-12, 1e-12)
+    assert worst < 1e-12
+
+
 def test_viscous_shock_tube_1000x500():
     """Navier-Stokes, Re = 200, Pr = 0.73, no-slip walls, symmetry top: two steps of the full grid in FP64
     and in FP32-bulk against the oracle."""
